@@ -1,0 +1,49 @@
+"""Seeded query batches: (halfedge h, barycentric (u, v), footprint f).
+
+h is uniform over [0, H); (u, v) is uniform over the triangle u, v >= 0,
+u + v <= 1 (two uniforms, folded when their sum exceeds 1), rounded to
+float32.  The footprint f is the isotropic screen-space filter width in quad
+parameter units, log-uniform: log2 f ~ U[lo, hi].  `sort=True` orders the batch
+by h (stable), as a rasteriser walking triangles would deliver it.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Queries:
+    h: np.ndarray   # int32 [Q]
+    u: np.ndarray   # float32 [Q]
+    v: np.ndarray   # float32 [Q]
+    f: np.ndarray | None  # float32 [Q] or None
+
+    @property
+    def Q(self):
+        return len(self.h)
+
+    def take(self, idx):
+        return Queries(self.h[idx], self.u[idx], self.v[idx],
+                       None if self.f is None else self.f[idx])
+
+
+def uniform_queries(H: int, Q: int, seed: int, log2f=None, sort: bool = False,
+                    shuffle_seed: int | None = None) -> Queries:
+    rng = np.random.default_rng(seed)
+    h = rng.integers(0, H, size=Q, dtype=np.int64)
+    r = rng.random((2, Q))
+    fold = r[0] + r[1] > 1.0
+    u = np.where(fold, 1.0 - r[0], r[0])
+    v = np.where(fold, 1.0 - r[1], r[1])
+    f = None
+    if log2f is not None:
+        lo, hi = log2f
+        f = np.exp2(rng.uniform(lo, hi, size=Q)).astype(np.float32)
+    q = Queries(h.astype(np.int32), u.astype(np.float32), v.astype(np.float32), f)
+    if sort:
+        q = q.take(np.argsort(q.h, kind="stable"))
+    elif shuffle_seed is not None:
+        q = q.take(np.random.default_rng(shuffle_seed).permutation(Q))
+    return q

@@ -1,0 +1,564 @@
+/*
+ * htex_oracle.c -- plain FP64 CPU oracle for batched Htex sampling.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the package smoke check and
+ * the benchmark's CPU-baseline leg may load this library.  The product path
+ * (the HIP library) never calls it, links it or shares code with it.
+ *
+ * What it computes, from the paper (Barbier & Dupuy, "Htex: Per-Halfedge
+ * Texturing for Arbitrary Mesh Topologies", 2022):
+ *   - halfedge operators Twin/Next/Prev/Edge (Section 2, Fig. 2);
+ *   - the quad parameterization of a halfedge's intrinsic triangle
+ *     (Section 4.2, Alg. 2 TriangleToQuadUV);
+ *   - Htexture (Section 4.4, Alg. 3): three texture fetches -- the halfedge's
+ *     own edge quad at its (u, v), the Next halfedge's quad at (v, -u) and the
+ *     Prev halfedge's quad at (-v, u) -- each filtered with CLAMP_TO_BORDER and
+ *     a zero border, summed with a border-normalization channel of ones, and
+ *     divided by that channel (Section 4.4, "Texture and Sampler
+ *     Initialization" and "Rendering");
+ *   - the texture fetch itself is the OpenGL filter the paper relies on
+ *     (Section 4.3 "Filtering"): texel centres at (i + 1/2) / n, bilinear
+ *     weights, and for trilinear filtering the LINEAR_MIPMAP_LINEAR level pair
+ *     chosen from the footprint.  The normalization channel is all ones, so
+ *     its filtered value is the sum of the in-bounds tap weights; it is
+ *     computed, not stored.
+ *
+ * Everything is FP64 on FP32 inputs promoted exactly; the pool is passed in
+ * as doubles (the caller widens the stored FP32 / BF16 / FP8 values exactly).
+ * Readings of points the paper leaves open are listed in the design notes of
+ * the repository; the ones that shape this code are repeated where used.
+ *
+ * Parity of every function here is pinned by CPU tests (closed forms,
+ * invariants, the Fig. 2 table, brute force, library routines); see tests/.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#include "htex_oracle.h"
+
+/* ------------------------------------------------------------------ layout */
+
+/* Offset, in texels, of mip level l inside an edge whose level 0 is 2^k wide:
+ * levels follow each other from the finest to the coarsest, so level l starts
+ * after sum_{m<l} 4^(k-m) texels. */
+static int64_t level_offset(int k, int l)
+{
+    int64_t off = 0;
+    for (int m = 0; m < l; ++m)
+        off += (int64_t)1 << (2 * (k - m));
+    return off;
+}
+
+/* ------------------------------------------------------ Alg. 2 (Sec. 4.2) */
+
+/* TriangleToQuadUV: the halfedge with the larger id keeps (u, v) (lower-left
+ * half of the quad); the other one is reflected to (1-u, 1-v).  A boundary
+ * halfedge has Twin = -1 and therefore always keeps (u, v). */
+static int triangle_to_quad_uv(int32_t g, const int32_t *twin, double a, double b,
+                               double *x, double *y)
+{
+    if (g > twin[g]) {
+        *x = a;
+        *y = b;
+        return 0;
+    }
+    *x = 1.0 - a;
+    *y = 1.0 - b;
+    return 1;
+}
+
+/* -------------------------------------------- level selection (Sec. 4.3) */
+
+/* OpenGL LINEAR_MIPMAP_LINEAR on a texture of 2^k texels per side, for an
+ * isotropic footprint f in quad units: lambda = log2(f * 2^k).  lambda <= 0
+ * magnifies (level 0 only); lambda >= k clamps to the coarsest level; in
+ * between the two levels floor(lambda), floor(lambda)+1 are blended with the
+ * fraction of lambda.  The integer part comes from the exponent of f, so
+ * f = m * 2^E with m in [1, 2), floor(lambda) = E + k, frac = log2(m). */
+static int lod_levels(int filter, double f, int k, int lv[2], double om[2], double *phi)
+{
+    *phi = 0.0;
+    lv[1] = -1;
+    om[1] = 0.0;
+    if (filter == ORA_BILINEAR || !(f > 0.0)) {
+        lv[0] = 0;
+        om[0] = 1.0;
+        return 1;
+    }
+    if (isinf(f)) {
+        lv[0] = k;
+        om[0] = 1.0;
+        return 1;
+    }
+    int E;
+    double m = frexp(f, &E);   /* f = m * 2^E with m in [0.5, 1) */
+    m *= 2.0;
+    E -= 1;                     /* now m in [1, 2) */
+    int li = E + k;
+    if (li < 0) {
+        lv[0] = 0;
+        om[0] = 1.0;
+        return 1;
+    }
+    if (li >= k) {
+        lv[0] = k;
+        om[0] = 1.0;
+        return 1;
+    }
+    double p = log2(m);
+    *phi = p;
+    lv[0] = li;
+    om[0] = 1.0 - p;
+    lv[1] = li + 1;
+    om[1] = p;
+    return 2;
+}
+
+/* ------------------------------------------ texture fetch (Sec. 4.3-4.4) */
+
+/* One filtered fetch: what Alg. 3's Texture(e, <x, y>) returns for the colour
+ * channels and for the border-normalization channel. */
+typedef struct {
+    int32_t g;        /* halfedge whose quad is read                    */
+    int32_t e;        /* Edge(g): the texture                           */
+    int k;            /* log2 of the level-0 resolution of e            */
+    int flip;         /* 1 if Alg. 2 reflected the coordinates          */
+    int nlev;         /* 1 or 2 mip levels                              */
+    int lv[2];        /* levels (lv[1] = -1 if unused)                  */
+    double om[2];     /* level weights                                  */
+    double x, y;      /* quad coordinates                               */
+    int32_t i0[2], j0[2], inb[2];  /* integer tap bases, in-bounds mask */
+    double C[4];      /* filtered colour (weights not normalized)        */
+    double W;         /* filtered normalization channel                  */
+} fetch_rec;
+
+/* Bilinear taps of one level: texel centres at (i + 1/2)/n, so the sample
+ * point in texel units is s = x n - 1/2, t = y n - 1/2; taps (i0 + di, j0 + dj)
+ * with i0 = floor(s), j0 = floor(t) carry weights (1-a or a)(1-b or b),
+ * a = s - i0, b = t - j0.  Taps outside [0, n)^2 read the zero border. */
+typedef struct {
+    int64_t i0, j0;
+    double a, b;
+} taps;
+
+static taps level_taps(double x, double y, int64_t n)
+{
+    taps T;
+    double s = x * (double)n - 0.5, t = y * (double)n - 0.5;
+    double fi = floor(s), fj = floor(t);
+    T.a = s - fi;
+    T.b = t - fj;
+    /* points far outside the quad only produce out-of-bounds taps; keep the
+     * integer conversion defined (exact for |coordinate| <= 4) */
+    double lim = 8.0 * (double)n;
+    if (fi < -lim) fi = -lim;
+    if (fi > lim) fi = lim;
+    if (fj < -lim) fj = -lim;
+    if (fj > lim) fj = lim;
+    T.i0 = (int64_t)fi;
+    T.j0 = (int64_t)fj;
+    return T;
+}
+
+static double tap_weight(const taps *T, int di, int dj)
+{
+    return (di ? T->a : 1.0 - T->a) * (dj ? T->b : 1.0 - T->b);
+}
+
+static void texture_fetch(const ora_pool *P, fetch_rec *F)
+{
+    memset(F->C, 0, sizeof F->C);
+    F->W = 0.0;
+    for (int s = 0; s < 2; ++s) {
+        F->i0[s] = F->j0[s] = F->inb[s] = 0;
+    }
+    for (int s = 0; s < F->nlev; ++s) {
+        int l = F->lv[s];
+        int64_t n = (int64_t)1 << (F->k - l);
+        const double *T = P->texels + 4 * (P->base[F->e] + level_offset(F->k, l));
+        taps tp = level_taps(F->x, F->y, n);
+        int mask = 0;
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di) {
+                int64_t i = tp.i0 + di, j = tp.j0 + dj;
+                if (i < 0 || i >= n || j < 0 || j >= n)
+                    continue;
+                double ow = F->om[s] * tap_weight(&tp, di, dj);
+                const double *t = T + 4 * (j * n + i);
+                for (int c = 0; c < 4; ++c)
+                    F->C[c] += ow * t[c];
+                F->W += ow;
+                mask |= 1 << (dj * 2 + di);
+            }
+        F->i0[s] = (int32_t)tp.i0;
+        F->j0[s] = (int32_t)tp.j0;
+        F->inb[s] = mask;
+    }
+}
+
+/* Alg. 3 for one query, in the algorithm's order: the own quad at (u, v),
+ * the Next halfedge's quad at (v, -u), the Prev halfedge's quad at (-v, u),
+ * each mapped by Alg. 2; each fetch is formed on its own and added to the
+ * running sum (c <- c + Texture(...)); the result is c_i / c_n. */
+static void htexture(const ora_mesh *M, const ora_pool *P, int filter, int32_t h,
+                     double u, double v, double f, fetch_rec F[3], double out[4],
+                     double *phi, double *Wtot)
+{
+    const int32_t g[3] = {h, M->next[h], M->prev[h]};
+    const double a[3] = {u, v, -v};
+    const double b[3] = {v, -u, u};
+    double C[4] = {0, 0, 0, 0}, W = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        fetch_rec *R = &F[q];
+        R->g = g[q];
+        R->flip = triangle_to_quad_uv(g[q], M->twin, a[q], b[q], &R->x, &R->y);
+        R->e = M->edge[g[q]];
+        R->k = P->log2res[R->e];
+        R->nlev = lod_levels(filter, f, R->k, R->lv, R->om, phi);
+        texture_fetch(P, R);
+        for (int c = 0; c < 4; ++c)
+            C[c] += R->C[c];
+        W += R->W;
+    }
+    for (int c = 0; c < 4; ++c)
+        out[c] = C[c] / W;
+    *Wtot = W;
+}
+
+static int query_valid(const ora_mesh *M, int32_t h, float u, float v)
+{
+    return h >= 0 && h < M->H && isfinite(u) && isfinite(v);
+}
+
+int64_t ora_sample(const ora_mesh *M, const ora_pool *P, int64_t Q, const int32_t *h,
+                   const float *u, const float *v, const float *fp, int filter,
+                   double *out, ora_debug *dbg, int nthreads)
+{
+    if (filter == ORA_TRILINEAR && !P->has_mips)
+        return -1;
+    int64_t errs = 0;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static) reduction(+ : errs)
+#endif
+    for (int64_t q = 0; q < Q; ++q) {
+        ora_debug *d = dbg ? dbg + q : NULL;
+        if (!query_valid(M, h[q], u[q], v[q])) {
+            for (int c = 0; c < 4; ++c)
+                out[4 * q + c] = NAN;
+            if (d) {
+                memset(d, 0, sizeof(*d));
+                d->next = d->prev = -1;
+                for (int s = 0; s < 3; ++s) {
+                    d->edge[s] = -1;
+                    d->level[s][0] = d->level[s][1] = -1;
+                }
+            }
+            errs += 1;
+            continue;
+        }
+        double f = fp ? (double)fp[q] : 0.0;
+        fetch_rec F[3];
+        double phi = 0.0, W = 0.0;
+        htexture(M, P, filter, h[q], (double)u[q], (double)v[q], f, F, out + 4 * q, &phi, &W);
+        if (d) {
+            d->next = F[1].g;
+            d->prev = F[2].g;
+            for (int s = 0; s < 3; ++s) {
+                d->edge[s] = F[s].e;
+                d->flip[s] = F[s].flip;
+                for (int l = 0; l < 2; ++l) {
+                    d->level[s][l] = F[s].lv[l];
+                    d->i0[s][l] = F[s].i0[l];
+                    d->j0[s][l] = F[s].j0[l];
+                    d->inb[s][l] = F[s].inb[l];
+                }
+                d->wf[s] = F[s].W;
+            }
+            d->phi = phi;
+            d->W = W;
+        }
+    }
+    return errs;
+}
+
+/* ----------------------------------------------------------- backward */
+
+/* The output of Alg. 3 is linear in the texels: out_c = sum over taps of
+ * (om w / W) T_c.  The gradient of L with respect to a texel channel is the
+ * sum, over every query and every in-bounds tap that reads it, of
+ * (om w / W) dL/dout_c.  `dtex` (pool-shaped, 4 doubles per texel) is added
+ * to; `dabs`, if given, receives the sum of the absolute values of the same
+ * contributions (a scale for tolerances). */
+int64_t ora_backward(const ora_mesh *M, const ora_pool *P, int64_t Q, const int32_t *h,
+                     const float *u, const float *v, const float *fp, int filter,
+                     const double *dout, double *dtex, double *dabs)
+{
+    if (filter == ORA_TRILINEAR && !P->has_mips)
+        return -1;
+    int64_t errs = 0;
+    for (int64_t q = 0; q < Q; ++q) {
+        if (!query_valid(M, h[q], u[q], v[q])) {
+            errs += 1;
+            continue;
+        }
+        double f = fp ? (double)fp[q] : 0.0;
+        fetch_rec F[3];
+        double out[4], phi, W;
+        htexture(M, P, filter, h[q], (double)u[q], (double)v[q], f, F, out, &phi, &W);
+        for (int s3 = 0; s3 < 3; ++s3) {
+            const fetch_rec *R = &F[s3];
+            for (int s = 0; s < R->nlev; ++s) {
+                int64_t n = (int64_t)1 << (R->k - R->lv[s]);
+                int64_t off = P->base[R->e] + level_offset(R->k, R->lv[s]);
+                taps tp = level_taps(R->x, R->y, n);
+                for (int dj = 0; dj < 2; ++dj)
+                    for (int di = 0; di < 2; ++di) {
+                        int64_t i = tp.i0 + di, j = tp.j0 + dj;
+                        if (i < 0 || i >= n || j < 0 || j >= n)
+                            continue;
+                        double w = R->om[s] * tap_weight(&tp, di, dj) / W;
+                        int64_t t = off + j * n + i;
+                        for (int c = 0; c < 4; ++c) {
+                            double gr = w * dout[4 * q + c];
+                            dtex[4 * t + c] += gr;
+                            if (dabs)
+                                dabs[4 * t + c] += fabs(gr);
+                        }
+                    }
+            }
+        }
+    }
+    return errs;
+}
+
+/* ----------------------------------------------------------------- mips */
+
+/* Box-filtered mip chain: each texel of level l+1 is the mean of the 2x2
+ * block of level l it covers (the paper relies on hardware mip-mapping and
+ * does not say how levels are made; a 2x2 box is the standard
+ * construction).  Works in place on a pool whose level 0 is filled. */
+void ora_build_mips(const ora_pool *P, double *texels)
+{
+    for (int32_t e = 0; e < P->E; ++e) {
+        int k = P->log2res[e];
+        for (int l = 1; l <= k; ++l) {
+            int64_t n = (int64_t)1 << (k - l);
+            double *src = texels + 4 * (P->base[e] + level_offset(k, l - 1));
+            double *dst = texels + 4 * (P->base[e] + level_offset(k, l));
+            for (int64_t j = 0; j < n; ++j)
+                for (int64_t i = 0; i < n; ++i)
+                    for (int c = 0; c < 4; ++c) {
+                        double s = src[4 * ((2 * j) * (2 * n) + 2 * i) + c] +
+                                   src[4 * ((2 * j) * (2 * n) + 2 * i + 1) + c] +
+                                   src[4 * ((2 * j + 1) * (2 * n) + 2 * i) + c] +
+                                   src[4 * ((2 * j + 1) * (2 * n) + 2 * i + 1) + c];
+                        dst[4 * (j * n + i) + c] = 0.25 * s;
+                    }
+        }
+    }
+}
+
+/* -------------------------------------------------------- quantization */
+
+/* bfloat16: the upper 16 bits of a binary32 after rounding its significand
+ * to 8 bits, to nearest with ties to even.  NaN stays NaN (quiet). */
+uint16_t ora_f32_to_bf16(float x)
+{
+    uint32_t b;
+    memcpy(&b, &x, 4);
+    if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu))
+        return (uint16_t)((b >> 16) | 0x0040u);
+    uint32_t low = b & 0xffffu, hi = b >> 16;
+    if (low > 0x8000u || (low == 0x8000u && (hi & 1u)))
+        hi += 1;   /* carries into the exponent correctly, up to infinity */
+    return (uint16_t)hi;
+}
+
+double ora_bf16_to_f64(uint16_t c)
+{
+    uint32_t b = (uint32_t)c << 16;
+    float x;
+    memcpy(&x, &b, 4);
+    return (double)x;
+}
+
+/* OCP 8-bit E4M3 ("E4M3FN"): 1 sign, 4 exponent (bias 7), 3 mantissa bits;
+ * no infinities; S.1111.111 is NaN; largest finite magnitude 448; exponent
+ * field 0 encodes subnormals m * 2^-9. */
+double ora_e4m3_to_f64(uint8_t c)
+{
+    int s = c >> 7, e = (c >> 3) & 15, m = c & 7;
+    double v;
+    if (e == 15 && m == 7)
+        return NAN;
+    if (e == 0)
+        v = ldexp((double)m, -9);
+    else
+        v = ldexp(1.0 + m / 8.0, e - 7);
+    return s ? -v : v;
+}
+
+/* Round to the nearest finite E4M3 value, ties to the even code, magnitudes
+ * beyond 448 saturating to 448.  Written as a search over the 127 finite
+ * non-negative codes, which is the definition itself. */
+uint8_t ora_f64_to_e4m3_sat(double x)
+{
+    if (isnan(x))
+        return 0x7f;
+    int neg = signbit(x) ? 1 : 0;
+    double a = fabs(x);
+    if (a > 448.0)
+        a = 448.0;   /* saturation: the nearest finite value */
+    int best = 0;
+    double bd = INFINITY;
+    for (int c = 0; c <= 0x7e; ++c) {
+        double d = fabs(ora_e4m3_to_f64((uint8_t)c) - a);
+        if (d < bd || (d == bd && (c & 1) == 0 && (best & 1) == 1)) {
+            bd = d;
+            best = c;
+        }
+    }
+    return (uint8_t)(best | (neg << 7));
+}
+
+/* Per-edge FP8 quantization: scale s_e = max |T| over every level and
+ * channel of edge e divided by 448, both in float32 (the precision the
+ * device quantizer decides in); codes = E4M3(T / s_e) with the quotient
+ * rounded to float32 first.  An all-zero edge gets s_e = 0 and zero codes.
+ * `src` is the float32 pool, `codes` receives one byte per texel channel. */
+void ora_quantize_e4m3(const ora_pool *P, const float *src, int64_t total_texels,
+                       uint8_t *codes, float *scale)
+{
+    (void)total_texels;
+    for (int32_t e = 0; e < P->E; ++e) {
+        int k = P->log2res[e];
+        int64_t cnt = 0;
+        for (int l = 0; l <= (P->has_mips ? k : 0); ++l)
+            cnt += (int64_t)1 << (2 * (k - l));
+        const float *t = src + 4 * P->base[e];
+        float mx = 0.0f;
+        for (int64_t i = 0; i < 4 * cnt; ++i) {
+            float a = fabsf(t[i]);
+            if (a > mx)
+                mx = a;
+        }
+        float s = mx / 448.0f;
+        scale[e] = s;
+        uint8_t *o = codes + 4 * P->base[e];
+        for (int64_t i = 0; i < 4 * cnt; ++i) {
+            if (s == 0.0f) {
+                o[i] = 0;
+                continue;
+            }
+            volatile float qv = t[i] / s;
+            o[i] = ora_f64_to_e4m3_sat((double)qv);
+        }
+    }
+}
+
+void ora_quantize_bf16(const float *src, int64_t count, uint16_t *dst)
+{
+    for (int64_t i = 0; i < count; ++i)
+        dst[i] = ora_f32_to_bf16(src[i]);
+}
+
+/* -------------------------------------------------------- mesh checks */
+
+/* Halfedge invariants (Section 2 and Fig. 2): Twin is an involution where
+ * defined and links opposite directions (Vert(Twin h) = Vert(Next h));
+ * Next/Prev are inverse permutations; twins share their edge; every edge id
+ * is used by exactly one twin pair or one lone boundary halfedge; faces have
+ * at least three sides.  Returns 0 or a negative code, with the first bad
+ * halfedge in *first_bad. */
+int ora_validate(const ora_mesh *M, const int32_t *vert, int32_t *first_bad)
+{
+    int32_t H = M->H, E = M->E;
+    *first_bad = -1;
+    int32_t *use = (int32_t *)calloc((size_t)(E > 0 ? E : 1), sizeof(int32_t));
+    int rc = 0;
+    for (int32_t h = 0; h < H && rc == 0; ++h) {
+        int32_t t = M->twin[h], n = M->next[h], p = M->prev[h], e = M->edge[h];
+        if (t < -1 || t >= H || n < 0 || n >= H || p < 0 || p >= H || e < 0 || e >= E ||
+            t == h) {
+            rc = -1;
+        } else if (M->prev[n] != h || M->next[p] != h) {
+            rc = -2;
+        } else if (t >= 0 && (M->twin[t] != h || M->edge[t] != e ||
+                              (vert && vert[t] != vert[n]))) {
+            rc = -3;
+        } else if (n == h || M->next[n] == h) {
+            rc = -4; /* face with fewer than 3 sides */
+        }
+        if (rc) {
+            *first_bad = h;
+            break;
+        }
+        use[e] += 1;
+    }
+    if (rc == 0) {
+        for (int32_t h = 0; h < H; ++h) {
+            int32_t e = M->edge[h];
+            int want = M->twin[h] >= 0 ? 2 : 1;
+            if (use[e] != want) {
+                rc = -5;
+                *first_bad = h;
+                break;
+            }
+        }
+        for (int32_t e = 0; e < E && rc == 0; ++e)
+            if (use[e] == 0) {
+                rc = -6;
+                *first_bad = -1;
+            }
+    }
+    free(use);
+    return rc;
+}
+
+/* Exact widening of stored codes to FP64 (the values the sampler reads). */
+void ora_dequantize_bf16(const uint16_t *codes, int64_t count, double *out)
+{
+    for (int64_t i = 0; i < count; ++i)
+        out[i] = ora_bf16_to_f64(codes[i]);
+}
+
+/* FP8 texel value = decoded code times the edge's scale (exact in FP64). */
+void ora_dequantize_e4m3(const ora_pool *P, const uint8_t *codes, const float *scale,
+                         double *out)
+{
+    for (int32_t e = 0; e < P->E; ++e) {
+        int k = P->log2res[e];
+        int64_t cnt = 0;
+        for (int l = 0; l <= (P->has_mips ? k : 0); ++l)
+            cnt += (int64_t)1 << (2 * (k - l));
+        for (int64_t i = 4 * P->base[e]; i < 4 * (P->base[e] + cnt); ++i)
+            out[i] = ora_e4m3_to_f64(codes[i]) * (double)scale[e];
+    }
+}
+
+/* Alg. 3's Texture(e, <x, y>) on its own: one filtered fetch of edge e at quad
+ * coordinates (x, y) with footprint f, returning the colour C[0..3] and the
+ * border-normalization channel *W. */
+void ora_texture_fetch(const ora_pool *P, int32_t e, int filter, double f, double x,
+                       double y, double C[4], double *W)
+{
+    fetch_rec R;
+    double phi;
+    memset(&R, 0, sizeof R);
+    R.e = e;
+    R.k = P->log2res[e];
+    R.x = x;
+    R.y = y;
+    R.nlev = lod_levels(filter, f, R.k, R.lv, R.om, &phi);
+    texture_fetch(P, &R);
+    for (int c = 0; c < 4; ++c)
+        C[c] = R.C[c];
+    *W = R.W;
+}
