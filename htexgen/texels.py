@@ -83,16 +83,26 @@ def texel_values(kind: int, seed: int, e, n, boundary, i, j, c) -> np.ndarray:
         raise ValueError("unknown texel fill")
     a, fa = si >> 3, si & 7
     b, fb = sj >> 3, sj & 7
-
-    def lat(aa, bb):
-        return (hash5(seed, e, c, aa, bb) % np.uint64(63)).astype(np.int64) + 1
-
     rx1 = RAMP[fa]
     rx0 = 64 - rx1
     ry1 = RAMP[fb]
     ry0 = 64 - ry1
-    num = (rx0 * ry0 * lat(a, b) + rx1 * ry0 * lat(a + 1, b)
-           + rx0 * ry1 * lat(a, b + 1) + rx1 * ry1 * lat(a + 1, b + 1))
+    # hash each lattice point once per (edge, channel), then gather
+    shape = np.broadcast(e, c, a, b).shape
+    eb, cb, ab, bb = (np.broadcast_to(x, shape) for x in (e, c, a, b))
+    ue, einv = np.unique(eb.reshape(-1), return_inverse=True)
+    nl = int(ab.max()) + 2 if ab.size else 2
+    ci = np.arange(4)[None, :, None, None]
+    la = np.arange(nl)[None, None, :, None]
+    lb = np.arange(nl)[None, None, None, :]
+    table = (hash5(seed, ue[:, None, None, None], ci, la, lb) % np.uint64(63)).astype(np.int64) + 1
+    ei = einv.reshape(shape)
+
+    def lat(aa, bb_):
+        return table[ei, cb, aa, bb_]
+
+    num = (rx0 * ry0 * lat(ab, bb) + rx1 * ry0 * lat(ab + 1, bb)
+           + rx0 * ry1 * lat(ab, bb + 1) + rx1 * ry1 * lat(ab + 1, bb + 1))
     return num.astype(np.float32) * np.float32(2.0 ** -18)
 
 

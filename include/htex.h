@@ -1,0 +1,198 @@
+/*
+ * htex.h -- C ABI of the MI355X Htex sampling library (libhtex.so).
+ *
+ * Htex (Barbier & Dupuy 2022) textures a polygon mesh with one square texture
+ * per edge: the edge's halfedge/twin pair forms an intrinsic quad (Section
+ * 3.2; a boundary halfedge pairs with itself).  A query names a halfedge h and
+ * a barycentric point (u, v) of h's intrinsic triangle (Section 4.2); its
+ * value is Alg. 3 (Section 4.4): three filtered fetches -- the quad of
+ * Edge(h) at TriangleToQuadUV(h, (u, v)), the quad of Edge(Next h) at
+ * TriangleToQuadUV(Next h, (v, -u)) and the quad of Edge(Prev h) at
+ * TriangleToQuadUV(Prev h, (-v, u)) -- each read with a CLAMP_TO_BORDER
+ * sampler of border 0 together with a border-normalization channel of ones,
+ * summed, and divided by the summed normalization channel.  TriangleToQuadUV
+ * (Alg. 2) keeps (u, v) when h > Twin(h) and returns (1-u, 1-v) otherwise.
+ *
+ * Conventions used throughout (the paper leaves them to the GPU's texture
+ * unit; these are the OpenGL ones):
+ *   - texture of edge e: n = 2^k texels per side, k = log2res[e] in [0, 15];
+ *     the quad coordinate x in [0, 1] indexes columns i, y indexes rows j;
+ *     texel (i, j) is centred at ((i + 1/2)/n, (j + 1/2)/n);
+ *   - bilinear filtering of a point (x, y): taps (i0 + di, j0 + dj),
+ *     i0 = floor(x n - 1/2), j0 = floor(y n - 1/2), weights (1-a or a)(1-b or b)
+ *     with a = x n - 1/2 - i0, b = y n - 1/2 - j0; taps outside [0, n)^2 read
+ *     the zero border and add nothing to the normalization channel either;
+ *   - trilinear filtering (LINEAR_MIPMAP_LINEAR) with an isotropic footprint
+ *     f (quad units, one per query): lambda = log2(f n); lambda <= 0 reads
+ *     level 0, lambda >= k reads level k, otherwise levels floor(lambda) and
+ *     floor(lambda) + 1 blended by lambda - floor(lambda).  f <= 0, NaN or
+ *     subnormal reads level 0; f = +inf reads level k;
+ *   - the normalization channel is computed (sum of in-bounds tap weights),
+ *     never stored.
+ *
+ * Memory: every pointer inside htex_mesh / htex_pool / htex_queries and every
+ * output pointer is DEVICE memory owned by the caller; the structs themselves
+ * and pointers documented as "host" are host memory, read during the call
+ * only.  The sampling entry points allocate nothing.  All launches are
+ * asynchronous on `stream` (a hipStream_t; NULL = the null stream).
+ *
+ * Errors: arguments are checked on the host before anything is launched; a
+ * failed check returns a negative status, launches nothing and records a
+ * message readable with htex_last_error() (thread-local).  Per-query problems
+ * (h outside [0, H), non-finite u or v) do not abort the call: that query's
+ * output row is NaN and *err_count (if given) is incremented on the device.
+ * A launch failure returns HTEX_E_DEVICE.
+ */
+#ifndef HTEX_H
+#define HTEX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t htex_status;
+
+#define HTEX_OK 0
+#define HTEX_E_ARG (-1)          /* bad argument: NULL, size, enum, alignment */
+#define HTEX_E_TOPOLOGY (-2)     /* halfedge arrays violate an invariant      */
+#define HTEX_E_RANGE (-3)        /* a size exceeds what the library supports  */
+#define HTEX_E_DEVICE (-4)       /* a HIP call or kernel launch failed        */
+#define HTEX_E_UNSUPPORTED (-5)  /* valid request this build does not do      */
+#define HTEX_E_BUSY (-6)         /* resource in use (serving)                 */
+#define HTEX_E_NOMEM (-7)        /* memory budget exhausted (serving)         */
+
+/* texel storage */
+#define HTEX_F32 0        /* float32 RGBA, 16 bytes per texel                  */
+#define HTEX_BF16 1       /* bfloat16 RGBA, 8 bytes per texel                  */
+#define HTEX_FP8_E4M3 2   /* OCP E4M3 (no infinities, max 448) RGBA, 4 bytes  */
+                          /* per texel, times a float32 scale per edge         */
+/* filters */
+#define HTEX_BILINEAR 0
+#define HTEX_TRILINEAR 1
+/* flags */
+#define HTEX_QUERIES_SORTED (1u << 0) /* hint: queries arrive ordered by h    */
+
+/* Halfedge arrays (Section 2, Fig. 2), device, int32 [H] each.  Twin(h) = -1
+ * marks a boundary halfedge; Edge(h) in [0, E) names h's quad and texture.
+ * The sampler trusts these arrays; check them once with htex_mesh_validate. */
+typedef struct htex_mesh {
+    int32_t H, E;
+    const int32_t *twin, *next, *prev, *edge;
+} htex_mesh;
+
+/* Per-edge texel pool.  Edge e's texels start at texel index base[e] (a
+ * multiple of 16); its levels follow each other from level 0 (n x n) down to
+ * level k (1 x 1) when has_mips, level 0 only otherwise; each level is
+ * row-major (texel (i, j) at j * n + i), 4 channels per texel.  Level l of an
+ * edge of log2 resolution k starts (4^(k+1) - 4^(k+1-l)) / 3 texels after
+ * base[e].  htex_pool_layout computes a valid base[] (host).
+ * texels: 16-byte aligned for HTEX_F32, 8 for HTEX_BF16, 4 for HTEX_FP8_E4M3.
+ * scale: FP8 only, float32 [E], texel value = decoded code * scale[e]. */
+typedef struct htex_pool {
+    int32_t E;
+    int32_t dtype;         /* HTEX_F32 / HTEX_BF16 / HTEX_FP8_E4M3 */
+    int32_t has_mips;      /* 0 or 1 */
+    int32_t max_log2res;   /* max over log2res[] (host-known bound, <= 15) */
+    int64_t total_texels;  /* size of the pool in texels */
+    const uint8_t *log2res;   /* [E] */
+    const int64_t *base;      /* [E] */
+    const void *texels;
+    const float *scale;       /* [E] or NULL */
+} htex_pool;
+
+/* A batch of queries, device, SoA.  footprint may be NULL (bilinear only). */
+typedef struct htex_queries {
+    int64_t Q;
+    const int32_t *h;
+    const float *u, *v;
+    const float *footprint;
+} htex_queries;
+
+/* Optional per-query trace of the three fetches (s = 0 own quad, 1 Next,
+ * 2 Prev; slot l = first / second mip level).  Integer fields are exact:
+ * level = -1 and i0 = j0 = inb = 0 for an unused slot; inb bit (2 dj + di) is
+ * set for every in-bounds tap (whatever its weight); i0/j0 are exact while
+ * |u|, |v| <= 4 (beyond, the coordinate is clamped to +-4 first, which only
+ * moves taps that are out of bounds anyway).  An invalid query has next =
+ * prev = edge = level = -1 and zeros elsewhere.  phi is the trilinear
+ * fraction, W the summed normalization channel, wf the per-fetch channel. */
+typedef struct htex_debug_rec {
+    int32_t next, prev;
+    int32_t edge[3];
+    int32_t flip[3];
+    int32_t level[3][2];
+    int32_t i0[3][2];
+    int32_t j0[3][2];
+    int32_t inb[3][2];
+    float phi;
+    float W;
+    float wf[3];
+    int32_t pad[3];
+} htex_debug_rec; /* 160 bytes */
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *htex_last_error(void);
+const char *htex_status_string(htex_status s);
+
+/* Host only.  Fills base_host_out[E] with texel offsets for the pool format
+ * above (each edge padded to a multiple of 16 texels) and *total_texels_out
+ * with the pool size.  log2res_host[E] must hold values in [0, 15]. */
+htex_status htex_pool_layout(int32_t E, const uint8_t *log2res_host, int32_t has_mips,
+                             int64_t *base_host_out, int64_t *total_texels_out);
+
+/* Checks the halfedge invariants of Section 2 on the device and waits for the
+ * result: Twin is an involution without fixed points where it is >= 0; Next
+ * and Prev are inverse permutations; twins share their edge; every edge id in
+ * [0, E) is used by exactly one twin pair or one lone boundary halfedge; every
+ * face has at least 3 sides.  Returns HTEX_OK, or HTEX_E_TOPOLOGY with the
+ * smallest offending halfedge in *first_bad_host (-1 for an unused edge id).
+ * Allocates a small temporary device buffer (not for use under graph
+ * capture). */
+htex_status htex_mesh_validate(const htex_mesh *mesh, int32_t *first_bad_host,
+                               void *stream);
+
+/* Box-filtered mip chain, in place: for every edge and l = 1..k, texel (i, j)
+ * of level l becomes the mean of texels (2i..2i+1, 2j..2j+1) of level l-1,
+ * in float32.  The pool must be HTEX_F32 with has_mips = 1; `texels_rw` is
+ * the same memory as pool->texels, writable. */
+htex_status htex_build_mips(const htex_pool *pool, void *texels_rw, void *stream);
+
+/* Converts a float32 pool to `dtype` into `dst` (same layout, same base[],
+ * total_texels texels).  HTEX_BF16: round to nearest even.  HTEX_FP8_E4M3:
+ * per-edge scale s = (max |T| over every level and channel of the edge) / 448
+ * computed in float32 and written to scale_out[e]; code = E4M3 of the
+ * float32 quotient T / s, rounded to nearest even and saturated to +-448; an
+ * all-zero edge gets s = 0 and zero codes.  Padding texels are written as 0.
+ * scale_out is required for FP8 and ignored otherwise. */
+htex_status htex_quantize(const htex_pool *src_f32, int32_t dtype, void *dst,
+                          float *scale_out, void *stream);
+
+/* Alg. 3 for every query (Section 4.4) -> out[q][0..3] (float32, 16-byte
+ * aligned, Q x 4).  filter: HTEX_BILINEAR (level 0, footprint ignored) or
+ * HTEX_TRILINEAR (needs has_mips and a footprint array).  Colour is blended
+ * and normalized in float32 whatever the storage type.  debug (nullable):
+ * Q records.  err_count (nullable, device int32): incremented once per
+ * invalid query.  Results do not depend on the batch they are computed in. */
+htex_status htex_sample(const htex_mesh *mesh, const htex_pool *pool,
+                        const htex_queries *queries, int32_t filter, uint32_t flags,
+                        float *out, htex_debug_rec *debug, int32_t *err_count,
+                        void *stream);
+
+/* Transpose of htex_sample with respect to the texels: for every valid query
+ * and every in-bounds tap it reads, dtexels[tap][c] += (om w / W) * dout[q][c]
+ * (om: level weight, w: bilinear weight, W: the query's normalization).
+ * dtexels is float32 with the pool's layout (16-byte aligned) and is added
+ * to, with float32 atomics (summation order unspecified); the pool must be
+ * HTEX_F32.  dout is float32 Q x 4 (16-byte aligned). */
+htex_status htex_sample_backward(const htex_mesh *mesh, const htex_pool *pool,
+                                 const htex_queries *queries, int32_t filter,
+                                 uint32_t flags, const float *dout, float *dtexels,
+                                 void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HTEX_H */

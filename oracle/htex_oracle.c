@@ -80,9 +80,8 @@ static int triangle_to_quad_uv(int32_t g, const int32_t *twin, double a, double 
  * between the two levels floor(lambda), floor(lambda)+1 are blended with the
  * fraction of lambda.  The integer part comes from the exponent of f, so
  * f = m * 2^E with m in [1, 2), floor(lambda) = E + k, frac = log2(m). */
-static int lod_levels(int filter, double f, int k, int lv[2], double om[2], double *phi)
+static int lod_levels(int filter, double f, int k, int lv[2], double om[2])
 {
-    *phi = 0.0;
     lv[1] = -1;
     om[1] = 0.0;
     if (filter == ORA_BILINEAR || !(f > 0.0)) {
@@ -111,12 +110,23 @@ static int lod_levels(int filter, double f, int k, int lv[2], double om[2], doub
         return 1;
     }
     double p = log2(m);
-    *phi = p;
     lv[0] = li;
     om[0] = 1.0 - p;
     lv[1] = li + 1;
     om[1] = p;
     return 2;
+}
+
+/* Debug trace of the level blend: the fraction log2(m) of lambda for any
+ * positive, finite footprint that is a normal float32 number (whether or not
+ * a texture's level pair is clamped); 0 otherwise or for bilinear. */
+static double trilinear_fraction(int filter, double f)
+{
+    if (filter != ORA_TRILINEAR || !(f >= 0x1p-126) || isinf(f))
+        return 0.0;
+    int E;
+    double m = 2.0 * frexp(f, &E);
+    return log2(m);
 }
 
 /* ------------------------------------------ texture fetch (Sec. 4.3-4.4) */
@@ -207,7 +217,7 @@ static void texture_fetch(const ora_pool *P, fetch_rec *F)
  * running sum (c <- c + Texture(...)); the result is c_i / c_n. */
 static void htexture(const ora_mesh *M, const ora_pool *P, int filter, int32_t h,
                      double u, double v, double f, fetch_rec F[3], double out[4],
-                     double *phi, double *Wtot)
+                     double *Wtot)
 {
     const int32_t g[3] = {h, M->next[h], M->prev[h]};
     const double a[3] = {u, v, -v};
@@ -219,7 +229,7 @@ static void htexture(const ora_mesh *M, const ora_pool *P, int filter, int32_t h
         R->flip = triangle_to_quad_uv(g[q], M->twin, a[q], b[q], &R->x, &R->y);
         R->e = M->edge[g[q]];
         R->k = P->log2res[R->e];
-        R->nlev = lod_levels(filter, f, R->k, R->lv, R->om, phi);
+        R->nlev = lod_levels(filter, f, R->k, R->lv, R->om);
         texture_fetch(P, R);
         for (int c = 0; c < 4; ++c)
             C[c] += R->C[c];
@@ -265,8 +275,8 @@ int64_t ora_sample(const ora_mesh *M, const ora_pool *P, int64_t Q, const int32_
         }
         double f = fp ? (double)fp[q] : 0.0;
         fetch_rec F[3];
-        double phi = 0.0, W = 0.0;
-        htexture(M, P, filter, h[q], (double)u[q], (double)v[q], f, F, out + 4 * q, &phi, &W);
+        double W = 0.0;
+        htexture(M, P, filter, h[q], (double)u[q], (double)v[q], f, F, out + 4 * q, &W);
         if (d) {
             d->next = F[1].g;
             d->prev = F[2].g;
@@ -281,7 +291,7 @@ int64_t ora_sample(const ora_mesh *M, const ora_pool *P, int64_t Q, const int32_
                 }
                 d->wf[s] = F[s].W;
             }
-            d->phi = phi;
+            d->phi = trilinear_fraction(filter, f);
             d->W = W;
         }
     }
@@ -310,8 +320,8 @@ int64_t ora_backward(const ora_mesh *M, const ora_pool *P, int64_t Q, const int3
         }
         double f = fp ? (double)fp[q] : 0.0;
         fetch_rec F[3];
-        double out[4], phi, W;
-        htexture(M, P, filter, h[q], (double)u[q], (double)v[q], f, F, out, &phi, &W);
+        double out[4], W;
+        htexture(M, P, filter, h[q], (double)u[q], (double)v[q], f, F, out, &W);
         for (int s3 = 0; s3 < 3; ++s3) {
             const fetch_rec *R = &F[s3];
             for (int s = 0; s < R->nlev; ++s) {
@@ -550,13 +560,12 @@ void ora_texture_fetch(const ora_pool *P, int32_t e, int filter, double f, doubl
                        double y, double C[4], double *W)
 {
     fetch_rec R;
-    double phi;
     memset(&R, 0, sizeof R);
     R.e = e;
     R.k = P->log2res[e];
     R.x = x;
     R.y = y;
-    R.nlev = lod_levels(filter, f, R.k, R.lv, R.om, &phi);
+    R.nlev = lod_levels(filter, f, R.k, R.lv, R.om);
     texture_fetch(P, &R);
     for (int c = 0; c < 4; ++c)
         C[c] = R.C[c];

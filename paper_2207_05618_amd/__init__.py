@@ -1,0 +1,207 @@
+"""MI355X-native batched Htex sampling (per-halfedge texturing, Barbier &
+Dupuy 2022): a thin Python binding over libhtex's C ABI (include/htex.h).
+
+Names follow the C entry points.  This layer only marshals arguments: torch
+supplies device memory and the current stream; every step of the sampling
+path runs in the HIP kernels of libhtex.  Tensors must live on the GPU; there
+is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (DEBUG_FIELDS, HTEX_BF16, HTEX_BILINEAR, HTEX_F32, HTEX_FP8_E4M3,  # noqa: F401
+                   HTEX_QUERIES_SORTED, HTEX_TRILINEAR, HtexError, check, load)
+
+__all__ = ["Mesh", "Pool", "htex_pool_layout", "htex_mesh_validate", "htex_build_mips",
+           "htex_quantize", "htex_sample", "htex_sample_backward", "HtexSample",
+           "debug_records", "HtexError"]
+
+DEBUG_DTYPE = np.dtype(DEBUG_FIELDS)
+_TEXEL_TORCH = {HTEX_F32: torch.float32, HTEX_BF16: torch.int16, HTEX_FP8_E4M3: torch.uint8}
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Mesh:
+    """Halfedge operators Twin/Next/Prev/Edge (Section 2) as device int32 arrays."""
+
+    def __init__(self, twin, next, prev, edge, E: int, device="cuda"):
+        as_t = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.int32)).to(device)
+        self.twin, self.next, self.prev, self.edge = (as_t(twin), as_t(next), as_t(prev),
+                                                      as_t(edge))
+        self.H = int(self.twin.numel())
+        self.E = int(E)
+        self.c = _lib.htex_mesh(self.H, self.E, self.twin.data_ptr(), self.next.data_ptr(),
+                                self.prev.data_ptr(), self.edge.data_ptr())
+
+    @classmethod
+    def of(cls, m, device="cuda"):
+        return cls(m.twin, m.next, m.prev, m.edge, m.E, device)
+
+
+def htex_pool_layout(log2res, has_mips: bool):
+    """(base int64[E], total_texels) for the pool format of htex.h (host)."""
+    lr = np.ascontiguousarray(log2res, dtype=np.uint8)
+    E = len(lr)
+    base = np.zeros(max(E, 1), dtype=np.int64)
+    total = np.zeros(1, dtype=np.int64)
+    check(load().htex_pool_layout(E, lr.ctypes.data, int(bool(has_mips)), base.ctypes.data,
+                                  total.ctypes.data))
+    return base[:E], int(total[0])
+
+
+class Pool:
+    """Per-edge texel pool on the device (layout of htex.h).
+
+    texels: float32 [total, 4] (HTEX_F32), int16 [total, 4] holding bfloat16
+    bits (HTEX_BF16) or uint8 [total, 4] holding E4M3 codes (HTEX_FP8_E4M3,
+    with float32 scale [E])."""
+
+    def __init__(self, log2res, has_mips: bool, dtype: int = HTEX_F32, texels=None,
+                 scale=None, device="cuda"):
+        lr = np.ascontiguousarray(log2res, dtype=np.uint8)
+        self.E = len(lr)
+        self.has_mips = bool(has_mips)
+        self.dtype = int(dtype)
+        self.max_log2res = int(lr.max()) if self.E else 0
+        base, total = htex_pool_layout(lr, has_mips)
+        self.base_host = base
+        self.log2res_host = lr
+        self.total = total
+        self.log2res = torch.as_tensor(lr).to(device)
+        self.base = torch.as_tensor(base).to(device)
+        if texels is None:
+            texels = torch.zeros((total, 4), dtype=_TEXEL_TORCH[self.dtype], device=device)
+        self.texels = _dev(texels, _TEXEL_TORCH[self.dtype], "texels")
+        if self.texels.shape != (total, 4):
+            raise ValueError(f"texels must have shape ({total}, 4)")
+        self.scale = scale
+        if self.dtype == HTEX_FP8_E4M3:
+            self.scale = _dev(scale, torch.float32, "scale") if scale is not None else \
+                torch.zeros(self.E, dtype=torch.float32, device=device)
+        self._sync_c()
+
+    def _sync_c(self):
+        self.c = _lib.htex_pool(self.E, self.dtype, int(self.has_mips), self.max_log2res,
+                                self.total, self.log2res.data_ptr(), self.base.data_ptr(),
+                                self.texels.data_ptr(),
+                                self.scale.data_ptr() if self.scale is not None else None)
+
+    def nbytes(self) -> int:
+        return self.texels.numel() * self.texels.element_size()
+
+
+def htex_mesh_validate(mesh: Mesh, stream=None):
+    """(ok, first_bad_halfedge): checks the halfedge invariants on the device."""
+    bad = C.c_int32(-1)
+    st = load().htex_mesh_validate(C.byref(mesh.c), C.byref(bad), _stream(stream))
+    if st == -2:
+        return False, int(bad.value)
+    check(st)
+    return True, -1
+
+
+def htex_build_mips(pool: Pool, stream=None):
+    check(load().htex_build_mips(C.byref(pool.c), pool.texels.data_ptr(), _stream(stream)))
+
+
+def htex_quantize(pool: Pool, dtype: int, stream=None) -> Pool:
+    """New pool holding `pool` (float32) converted to HTEX_BF16 or HTEX_FP8_E4M3."""
+    q = Pool(pool.log2res_host, pool.has_mips, dtype, device=pool.texels.device)
+    scale_ptr = q.scale.data_ptr() if q.scale is not None else None
+    check(load().htex_quantize(C.byref(pool.c), int(dtype), q.texels.data_ptr(), scale_ptr,
+                               _stream(stream)))
+    return q
+
+
+def _queries(h, u, v, footprint):
+    h = _dev(h, torch.int32, "h")
+    u = _dev(u, torch.float32, "u")
+    v = _dev(v, torch.float32, "v")
+    if footprint is not None:
+        footprint = _dev(footprint, torch.float32, "footprint")
+    Q = h.numel()
+    if u.numel() != Q or v.numel() != Q or (footprint is not None and footprint.numel() != Q):
+        raise ValueError("query arrays differ in length")
+    q = _lib.htex_queries(Q, h.data_ptr(), u.data_ptr(), v.data_ptr(),
+                          footprint.data_ptr() if footprint is not None else None)
+    return q, Q
+
+
+def htex_sample(mesh: Mesh, pool: Pool, h, u, v, footprint=None, filter=HTEX_BILINEAR,
+                flags=0, out=None, debug=False, err_count=None, stream=None):
+    """Alg. 3 for every query -> (out float32 [Q, 4], debug int32 [Q, 40] or None)."""
+    q, Q = _queries(h, u, v, footprint)
+    if out is None:
+        out = torch.empty((Q, 4), dtype=torch.float32, device=h.device)
+    _dev(out, torch.float32, "out")
+    dbg = torch.zeros((Q, 40), dtype=torch.int32, device=h.device) if debug else None
+    if err_count is not None:
+        _dev(err_count, torch.int32, "err_count")
+    check(load().htex_sample(C.byref(mesh.c), C.byref(pool.c), C.byref(q), int(filter),
+                             int(flags), out.data_ptr(),
+                             dbg.data_ptr() if dbg is not None else None,
+                             err_count.data_ptr() if err_count is not None else None,
+                             _stream(stream)))
+    return out, dbg
+
+
+def debug_records(dbg: torch.Tensor) -> np.ndarray:
+    """Device debug output -> numpy structured array (fields of htex_debug_rec)."""
+    a = dbg.cpu().numpy()
+    return a.view(DEBUG_DTYPE).reshape(-1)
+
+
+def htex_sample_backward(mesh: Mesh, pool: Pool, h, u, v, dout, footprint=None,
+                         filter=HTEX_BILINEAR, flags=0, dtexels=None, stream=None):
+    """dtexels (float32, pool-shaped) += transpose of htex_sample applied to dout."""
+    q, Q = _queries(h, u, v, footprint)
+    _dev(dout, torch.float32, "dout")
+    if dtexels is None:
+        dtexels = torch.zeros_like(pool.texels, dtype=torch.float32)
+    _dev(dtexels, torch.float32, "dtexels")
+    check(load().htex_sample_backward(C.byref(mesh.c), C.byref(pool.c), C.byref(q),
+                                      int(filter), int(flags), dout.data_ptr(),
+                                      dtexels.data_ptr(), _stream(stream)))
+    return dtexels
+
+
+class HtexSample(torch.autograd.Function):
+    """Differentiable sampling with respect to a float32 pool's texels.
+
+    forward(texels, mesh, pool, h, u, v, footprint, filter) -> [Q, 4]; the
+    gradient flows to `texels` (which must be pool.texels)."""
+
+    @staticmethod
+    def forward(ctx, texels, mesh, pool, h, u, v, footprint=None, filter=HTEX_BILINEAR):
+        if texels.data_ptr() != pool.texels.data_ptr():
+            raise ValueError("texels must be pool.texels")
+        out, _ = htex_sample(mesh, pool, h, u, v, footprint, filter)
+        ctx.save_for_backward(h, u, v, footprint)
+        ctx.mesh, ctx.pool, ctx.filter = mesh, pool, filter
+        return out
+
+    @staticmethod
+    def backward(ctx, gout):
+        h, u, v, footprint = ctx.saved_tensors
+        d = htex_sample_backward(ctx.mesh, ctx.pool, h, u, v, gout.contiguous(), footprint,
+                                 ctx.filter)
+        return d, None, None, None, None, None, None, None

@@ -1,0 +1,273 @@
+// htex_api.cpp -- the C ABI of libhtex: synchronous argument checks, pool
+// layout, dispatch of the HIP kernels, status codes and messages.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "htex.h"
+#include "htex_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+htex_status fail(htex_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+htex_status ok()
+{
+    g_last_error.clear();
+    return HTEX_OK;
+}
+
+htex_status from_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return ok();
+    return fail(HTEX_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+size_t texel_bytes(int32_t dtype)
+{
+    switch (dtype) {
+    case HTEX_F32: return 16;
+    case HTEX_BF16: return 8;
+    case HTEX_FP8_E4M3: return 4;
+    default: return 0;
+    }
+}
+
+htex_status check_mesh(const htex_mesh *m)
+{
+    if (!m) return fail(HTEX_E_ARG, "mesh is NULL");
+    if (m->H < 0 || m->E < 0) return fail(HTEX_E_ARG, "negative H or E");
+    if (m->H > 0 && (!m->twin || !m->next || !m->prev || !m->edge))
+        return fail(HTEX_E_ARG, "a halfedge array is NULL");
+    if (m->E > m->H) return fail(HTEX_E_ARG, "E (%d) exceeds H (%d)", m->E, m->H);
+    return HTEX_OK;
+}
+
+htex_status check_pool(const htex_pool *p, const htex_mesh *m)
+{
+    if (!p) return fail(HTEX_E_ARG, "pool is NULL");
+    if (m && p->E != m->E) return fail(HTEX_E_ARG, "pool has %d edges, mesh has %d", p->E, m->E);
+    if (p->E < 0 || p->total_texels < 0) return fail(HTEX_E_ARG, "negative pool size");
+    const size_t tb = texel_bytes(p->dtype);
+    if (!tb) return fail(HTEX_E_ARG, "unknown texel dtype %d", p->dtype);
+    if (p->has_mips != 0 && p->has_mips != 1) return fail(HTEX_E_ARG, "has_mips must be 0 or 1");
+    if (p->max_log2res < 0 || p->max_log2res > 15)
+        return fail(HTEX_E_RANGE, "max_log2res %d outside [0, 15]", p->max_log2res);
+    if (p->E > 0 && (!p->log2res || !p->base || !p->texels))
+        return fail(HTEX_E_ARG, "a pool array is NULL");
+    if (p->texels && !aligned(p->texels, tb))
+        return fail(HTEX_E_ARG, "texels must be %zu-byte aligned", tb);
+    if (p->dtype == HTEX_FP8_E4M3 && p->E > 0 && !p->scale)
+        return fail(HTEX_E_ARG, "FP8 pool needs per-edge scales");
+    return HTEX_OK;
+}
+
+htex_status check_queries(const htex_queries *q, int32_t filter)
+{
+    if (!q) return fail(HTEX_E_ARG, "queries is NULL");
+    if (q->Q < 0) return fail(HTEX_E_ARG, "negative query count");
+    if (q->Q > (int64_t)INT32_MAX * 128) return fail(HTEX_E_RANGE, "too many queries in one call");
+    if (q->Q > 0 && (!q->h || !q->u || !q->v)) return fail(HTEX_E_ARG, "a query array is NULL");
+    if (filter != HTEX_BILINEAR && filter != HTEX_TRILINEAR)
+        return fail(HTEX_E_ARG, "unknown filter %d", filter);
+    if (filter == HTEX_TRILINEAR && q->Q > 0 && !q->footprint)
+        return fail(HTEX_E_ARG, "trilinear filtering needs footprints");
+    return HTEX_OK;
+}
+
+htex::SampleArgs make_args(const htex_mesh *m, const htex_pool *p, const htex_queries *q)
+{
+    htex::SampleArgs a{};
+    a.H = m->H;
+    a.twin = m->twin;
+    a.next = m->next;
+    a.prev = m->prev;
+    a.edge = m->edge;
+    a.log2res = p->log2res;
+    a.base = p->base;
+    a.texels = p->texels;
+    a.scale = p->scale;
+    a.Q = q->Q;
+    a.qh = q->h;
+    a.qu = q->u;
+    a.qv = q->v;
+    a.qf = q->footprint;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *htex_last_error(void) { return g_last_error.c_str(); }
+
+const char *htex_status_string(htex_status s)
+{
+    switch (s) {
+    case HTEX_OK: return "ok";
+    case HTEX_E_ARG: return "invalid argument";
+    case HTEX_E_TOPOLOGY: return "invalid halfedge topology";
+    case HTEX_E_RANGE: return "size out of supported range";
+    case HTEX_E_DEVICE: return "device error";
+    case HTEX_E_UNSUPPORTED: return "unsupported";
+    case HTEX_E_BUSY: return "busy";
+    case HTEX_E_NOMEM: return "out of memory budget";
+    default: return "unknown status";
+    }
+}
+
+htex_status htex_pool_layout(int32_t E, const uint8_t *log2res_host, int32_t has_mips,
+                             int64_t *base_host_out, int64_t *total_texels_out)
+{
+    if (E < 0) return fail(HTEX_E_ARG, "negative E");
+    if ((E > 0 && (!log2res_host || !base_host_out)) || !total_texels_out)
+        return fail(HTEX_E_ARG, "NULL argument");
+    if (has_mips != 0 && has_mips != 1) return fail(HTEX_E_ARG, "has_mips must be 0 or 1");
+    int64_t off = 0;
+    for (int32_t e = 0; e < E; ++e) {
+        const int k = log2res_host[e];
+        if (k > 15) return fail(HTEX_E_RANGE, "log2res[%d] = %d exceeds 15", e, k);
+        int64_t cnt = has_mips ? ((int64_t(4) << (2 * k)) - 1) / 3 : (int64_t(1) << (2 * k));
+        cnt = (cnt + 15) / 16 * 16;
+        base_host_out[e] = off;
+        off += cnt;
+    }
+    *total_texels_out = off;
+    return ok();
+}
+
+htex_status htex_mesh_validate(const htex_mesh *mesh, int32_t *first_bad_host, void *stream)
+{
+    htex_status st = check_mesh(mesh);
+    if (st) return st;
+    if (!first_bad_host) return fail(HTEX_E_ARG, "first_bad_host is NULL");
+    *first_bad_host = -1;
+    if (mesh->H == 0) return ok();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t *ws = nullptr;
+    const size_t words = (size_t)mesh->E + 2;
+    hipError_t e = hipMalloc(&ws, words * sizeof(int32_t));
+    if (e != hipSuccess) return from_hip(e, "hipMalloc");
+    int32_t init[2] = {INT32_MAX, 0};
+    e = hipMemsetAsync(ws, 0, (size_t)mesh->E * sizeof(int32_t), s);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + mesh->E, init, sizeof init, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = htex::launch_validate(*mesh, ws, ws + mesh->E, s);
+    int32_t res[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(res, ws + mesh->E, sizeof res, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(ws);
+    if (e != hipSuccess) return from_hip(e, "mesh validation");
+    if (res[0] != INT32_MAX) {
+        *first_bad_host = res[0];
+        return fail(HTEX_E_TOPOLOGY, "halfedge %d violates an invariant", res[0]);
+    }
+    if (res[1] != 0) return fail(HTEX_E_TOPOLOGY, "%d edge ids are unused", res[1]);
+    return ok();
+}
+
+htex_status htex_build_mips(const htex_pool *pool, void *texels_rw, void *stream)
+{
+    htex_status st = check_pool(pool, nullptr);
+    if (st) return st;
+    if (pool->dtype != HTEX_F32) return fail(HTEX_E_UNSUPPORTED, "mips are built on float32 pools");
+    if (!pool->has_mips) return fail(HTEX_E_ARG, "pool has no mip levels");
+    if (texels_rw != pool->texels) return fail(HTEX_E_ARG, "texels_rw must be pool->texels");
+    return from_hip(htex::launch_build_mips(static_cast<float *>(texels_rw), pool->log2res,
+                                            pool->base, pool->E, pool->max_log2res,
+                                            static_cast<hipStream_t>(stream)),
+                    "mip build");
+}
+
+htex_status htex_quantize(const htex_pool *src, int32_t dtype, void *dst, float *scale_out,
+                          void *stream)
+{
+    htex_status st = check_pool(src, nullptr);
+    if (st) return st;
+    if (src->dtype != HTEX_F32) return fail(HTEX_E_ARG, "quantize reads a float32 pool");
+    if (!dst && src->total_texels > 0) return fail(HTEX_E_ARG, "dst is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == HTEX_BF16) {
+        if (!aligned(dst, 8)) return fail(HTEX_E_ARG, "dst must be 8-byte aligned");
+        return from_hip(htex::launch_quantize_bf16(static_cast<const float *>(src->texels),
+                                                   static_cast<uint16_t *>(dst),
+                                                   src->total_texels * 4, s),
+                        "bf16 quantize");
+    }
+    if (dtype == HTEX_FP8_E4M3) {
+        if (!aligned(dst, 4)) return fail(HTEX_E_ARG, "dst must be 4-byte aligned");
+        if (!scale_out && src->E > 0) return fail(HTEX_E_ARG, "scale_out is NULL");
+        return from_hip(htex::launch_quantize_fp8(static_cast<const float *>(src->texels),
+                                                  static_cast<uint8_t *>(dst), scale_out,
+                                                  src->log2res, src->base, src->E,
+                                                  src->has_mips, src->total_texels, s),
+                        "fp8 quantize");
+    }
+    return fail(HTEX_E_ARG, "quantize target must be HTEX_BF16 or HTEX_FP8_E4M3");
+}
+
+htex_status htex_sample(const htex_mesh *mesh, const htex_pool *pool, const htex_queries *queries,
+                        int32_t filter, uint32_t flags, float *out, htex_debug_rec *debug,
+                        int32_t *err_count, void *stream)
+{
+    htex_status st = check_mesh(mesh);
+    if (!st) st = check_pool(pool, mesh);
+    if (!st) st = check_queries(queries, filter);
+    if (st) return st;
+    if (flags & ~HTEX_QUERIES_SORTED) return fail(HTEX_E_ARG, "unknown flags 0x%x", flags);
+    if (filter == HTEX_TRILINEAR && !pool->has_mips)
+        return fail(HTEX_E_ARG, "trilinear filtering needs a pool with mips");
+    if (queries->Q > 0 && (!out || !aligned(out, 16)))
+        return fail(HTEX_E_ARG, "out must be non-NULL and 16-byte aligned");
+    if (debug && !aligned(debug, 4)) return fail(HTEX_E_ARG, "debug must be 4-byte aligned");
+    if (queries->Q > 0 && mesh->H == 0) return fail(HTEX_E_ARG, "queries on an empty mesh");
+    htex::SampleArgs a = make_args(mesh, pool, queries);
+    a.out = out;
+    a.dbg = debug;
+    a.err = err_count;
+    return from_hip(htex::launch_sample(a, pool->dtype, filter, static_cast<hipStream_t>(stream)),
+                    "sample launch");
+}
+
+htex_status htex_sample_backward(const htex_mesh *mesh, const htex_pool *pool,
+                                 const htex_queries *queries, int32_t filter, uint32_t flags,
+                                 const float *dout, float *dtexels, void *stream)
+{
+    htex_status st = check_mesh(mesh);
+    if (!st) st = check_pool(pool, mesh);
+    if (!st) st = check_queries(queries, filter);
+    if (st) return st;
+    if (flags & ~HTEX_QUERIES_SORTED) return fail(HTEX_E_ARG, "unknown flags 0x%x", flags);
+    if (pool->dtype != HTEX_F32) return fail(HTEX_E_UNSUPPORTED, "gradients need a float32 pool");
+    if (filter == HTEX_TRILINEAR && !pool->has_mips)
+        return fail(HTEX_E_ARG, "trilinear filtering needs a pool with mips");
+    if (queries->Q > 0) {
+        if (!dout || !aligned(dout, 16)) return fail(HTEX_E_ARG, "dout must be 16-byte aligned");
+        if (!dtexels || !aligned(dtexels, 16))
+            return fail(HTEX_E_ARG, "dtexels must be 16-byte aligned");
+        if (mesh->H == 0) return fail(HTEX_E_ARG, "queries on an empty mesh");
+    }
+    htex::SampleArgs a = make_args(mesh, pool, queries);
+    a.dout = dout;
+    a.dtex = dtexels;
+    return from_hip(htex::launch_backward(a, filter, static_cast<hipStream_t>(stream)),
+                    "backward launch");
+}
+
+}  // extern "C"

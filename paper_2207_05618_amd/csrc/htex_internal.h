@@ -1,0 +1,50 @@
+// htex_internal.h -- declarations shared by the HIP kernel sources and the
+// C-ABI host layer of libhtex.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "htex.h"
+
+namespace htex {
+
+// Everything one sampling or backward launch needs, by value.
+struct SampleArgs {
+    int32_t H;
+    const int32_t *twin, *next, *prev, *edge;
+    const uint8_t *log2res;
+    const int64_t *base;
+    const void *texels;
+    const float *scale;
+    int64_t Q;
+    const int32_t *qh;
+    const float *qu, *qv, *qf;
+    float *out;                 // forward: [Q][4]
+    htex_debug_rec *dbg;        // forward, nullable
+    int32_t *err;               // forward, nullable
+    const float *dout;          // backward: [Q][4]
+    float *dtex;                // backward: pool-shaped float32
+};
+
+// Offset of mip level l inside an edge of log2 resolution k, in texels:
+// levels are stored from the finest to the coarsest, so level l follows
+// sum_{m<l} 4^(k-m) = (4^(k+1) - 4^(k+1-l)) / 3 texels.
+__host__ __device__ inline int64_t level_offset(int k, int l)
+{
+    return ((int64_t(1) << (2 * k + 2)) - (int64_t(1) << (2 * (k - l) + 2))) / 3;
+}
+
+hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t s);
+hipError_t launch_backward(const SampleArgs &a, int filter, hipStream_t s);
+hipError_t launch_build_mips(float *texels, const uint8_t *log2res, const int64_t *base,
+                             int32_t E, int max_k, hipStream_t s);
+hipError_t launch_quantize_bf16(const float *src, uint16_t *dst, int64_t count,
+                                hipStream_t s);
+hipError_t launch_quantize_fp8(const float *src, uint8_t *dst, float *scale,
+                               const uint8_t *log2res, const int64_t *base, int32_t E,
+                               int has_mips, int64_t total_texels, hipStream_t s);
+hipError_t launch_validate(const htex_mesh &m, int32_t *ws_use, int32_t *ws_bad,
+                           hipStream_t s);
+
+}  // namespace htex

@@ -1,0 +1,383 @@
+// htex_sample.hip -- batched Htex sampling (forward) and its transpose
+// (backward scatter) for gfx950.
+//
+// One lane per query.  Per query: the halfedge operators Next/Prev/Twin/Edge
+// (Section 2), Alg. 2's reflection for each of the three fetches of Alg. 3
+// (own quad at (u, v), Next quad at (v, -u), Prev quad at (-v, u)), the
+// OpenGL level pair for trilinear filtering, the bilinear taps of each level
+// with a zero border, and the float32 blend normalized by the summed
+// border-normalization channel (computed from the in-bounds tap weights, so
+// it costs no memory).  This is a gather bound by HBM bandwidth: no MFMA.
+//
+// Integer tap bases are exact for every float32 input.  A quad coordinate
+// is x = sigma * c + rho with c the query's u or v, sigma = +-1 and rho in
+// {0, 1} (Alg. 2 and the neighbour maps).  With t = |c| n (exact: n is a
+// power of two), q = floor(t) and r = t - q (exact), x n - 1/2 equals
+// rho n + q + r - 1/2 when sigma c >= 0 and rho n - q - r - 1/2 otherwise, so
+// floor and fraction follow from q, r and the comparison of r with 1/2,
+// without ever forming 1 - c (which would round).
+#include <hip/hip_runtime.h>
+
+#include "htex_internal.h"
+
+namespace htex {
+namespace {
+
+constexpr int kBlock = 256;
+
+struct AxisTaps {
+    int32_t i0;  // floor(x n - 1/2)
+    float w0;    // weight of tap i0:     1 - a, a = x n - 1/2 - i0
+    float w1;    // weight of tap i0 + 1: a
+};
+
+// x = (neg ? -1 : 1) * c + rho, sampled on a level of n = 2^m texels.  Both
+// weights are formed from the exact fraction r without cancellation (each
+// within an ulp of its exact value, however close to 0 it is).
+__device__ __forceinline__ AxisTaps axis_taps(float c, bool neg, int rho, int m)
+{
+    const bool eneg = neg != ((__float_as_uint(c) >> 31) != 0u);
+    const float t = ldexpf(fminf(fabsf(c), 4.0f), m);
+    const float qf = floorf(t);
+    const float r = t - qf;
+    const int32_t q = (int32_t)qf;
+    const int32_t rn = rho << m;
+    AxisTaps o;
+    if (!eneg) {
+        const bool up = r >= 0.5f;   // x n - 1/2 = rn + q + (r - 1/2)
+        o.i0 = rn + q - 1 + (up ? 1 : 0);
+        o.w1 = up ? r - 0.5f : r + 0.5f;
+        o.w0 = up ? 1.5f - r : 0.5f - r;
+    } else {
+        const bool up = r > 0.5f;    // x n - 1/2 = rn - q - (r + 1/2)
+        o.i0 = rn - q - 1 - (up ? 1 : 0);
+        o.w1 = up ? 1.5f - r : 0.5f - r;
+        o.w0 = up ? r - 0.5f : r + 0.5f;
+    }
+    return o;
+}
+
+template <int DT>
+__device__ __forceinline__ float4 load_texel(const void *tex, int64_t idx)
+{
+    if constexpr (DT == HTEX_F32) {
+        return reinterpret_cast<const float4 *>(tex)[idx];
+    } else if constexpr (DT == HTEX_BF16) {
+        const uint2 p = reinterpret_cast<const uint2 *>(tex)[idx];
+        return make_float4(__uint_as_float(p.x << 16), __uint_as_float(p.x & 0xffff0000u),
+                           __uint_as_float(p.y << 16), __uint_as_float(p.y & 0xffff0000u));
+    } else {
+        const uint32_t p = reinterpret_cast<const uint32_t *>(tex)[idx];
+        auto dec = [](uint32_t b) -> float {
+            // OCP E4M3: exponent field 0 -> subnormal m * 2^-9; S.1111.111 -> NaN
+            const uint32_t mag = b & 0x7fu;
+            const uint32_t e = mag >> 3, mm = mag & 7u;
+            float v = (e == 0) ? (float)mm * 0x1p-9f
+                               : __uint_as_float(((e + 120u) << 23) | (mm << 20));
+            v = (mag == 0x7fu) ? __uint_as_float(0x7fc00000u) : v;
+            return (b & 0x80u) ? -v : v;
+        };
+        return make_float4(dec(p & 0xffu), dec((p >> 8) & 0xffu), dec((p >> 16) & 0xffu),
+                           dec(p >> 24));
+    }
+}
+
+// Trilinear level selection from the footprint: f = m 2^E, m in [1, 2);
+// floor(lambda) = E + k, frac(lambda) = log2(m).  `mode`: 0 = level 0 only,
+// 1 = coarsest level only, 2 = level pair (E + k, E + k + 1) unless clamped
+// per fetch.  The blend weights phi = log2(m) and 1 - phi = -log2(1 - y/2)
+// with y = 2 - m are both evaluated through log1p of exact arguments, so
+// each keeps full relative precision when it is close to zero.
+struct Lod {
+    int mode;
+    int E;
+    float phi;   // weight of the coarser level
+    float om0;   // weight of the finer level, 1 - phi
+};
+
+__device__ __forceinline__ Lod lod_of(float f)
+{
+    Lod L{0, 0, 0.0f, 1.0f};
+    const uint32_t b = __float_as_uint(f);
+    if (!(f > 0.0f)) return L;                 // <= 0 or NaN
+    if (b == 0x7f800000u) { L.mode = 1; return L; }
+    const uint32_t ex = (b >> 23) & 0xffu;
+    if (ex == 0) return L;                     // subnormal: magnification
+    L.mode = 2;
+    L.E = (int)ex - 127;
+    const float m = __uint_as_float((b & 0x7fffffu) | 0x3f800000u);
+    constexpr float kInvLn2 = 1.44269504088896340736f;
+    L.phi = log1pf(m - 1.0f) * kInvLn2;            // m - 1 exact
+    L.om0 = -log1pf(-0.5f * (2.0f - m)) * kInvLn2;  // 2 - m exact
+    return L;
+}
+
+// Levels and weights of one fetch on a texture of log2 resolution k.
+__device__ __forceinline__ int fetch_levels(const Lod &L, int k, int lv[2], float om[2])
+{
+    lv[1] = -1;
+    om[1] = 0.0f;
+    if (L.mode == 0) { lv[0] = 0; om[0] = 1.0f; return 1; }
+    if (L.mode == 1) { lv[0] = k; om[0] = 1.0f; return 1; }
+    const int li = L.E + k;
+    if (li < 0) { lv[0] = 0; om[0] = 1.0f; return 1; }
+    if (li >= k) { lv[0] = k; om[0] = 1.0f; return 1; }
+    lv[0] = li;
+    om[0] = L.om0;
+    lv[1] = li + 1;
+    om[1] = L.phi;
+    return 2;
+}
+
+// The three fetches of Alg. 3: halfedge and (raw coordinate, negated?) for x, y.
+struct FetchSpec {
+    int32_t g;
+    float cx, cy;
+    bool nx, ny;
+};
+
+__device__ __forceinline__ void fetch_specs(int32_t h, int32_t n1, int32_t p1, float u, float v,
+                                            FetchSpec fs[3])
+{
+    fs[0] = {h, u, v, false, false};    // own quad at (u, v)
+    fs[1] = {n1, v, u, false, true};    // Next quad at (v, -u)
+    fs[2] = {p1, v, u, true, false};    // Prev quad at (-v, u)
+}
+
+// XCD-aware block order: hardware deals consecutive workgroups to the 8 XCDs
+// in turn; give each XCD a contiguous share of the (sorted) query range so
+// neighbouring queries -- which read the same textures -- meet in one L2.
+__device__ __forceinline__ int64_t logical_block(int64_t nblocks_real)
+{
+    const int64_t G = gridDim.x;          // multiple of 8
+    const int64_t b = blockIdx.x;
+    const int64_t per = G >> 3;
+    const int64_t lb = (b & 7) * per + (b >> 3);
+    return lb < nblocks_real ? lb : -1;
+}
+
+template <int DT, bool TRI, bool DBG>
+__global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a, int64_t nblocks_real)
+{
+    const int64_t lb = logical_block(nblocks_real);
+    if (lb < 0) return;
+    const int64_t q = lb * kBlock + threadIdx.x;
+    if (q >= a.Q) return;
+    const int32_t h = a.qh[q];
+    const float u = a.qu[q], v = a.qv[q];
+    float4 *out4 = reinterpret_cast<float4 *>(a.out);
+    if (!((uint32_t)h < (uint32_t)a.H) || !isfinite(u) || !isfinite(v)) {
+        const float nan = __uint_as_float(0x7fc00000u);
+        out4[q] = make_float4(nan, nan, nan, nan);
+        if (a.err) atomicAdd(a.err, 1);
+        if constexpr (DBG) {
+            htex_debug_rec d = {};
+            d.next = d.prev = -1;
+            for (int s = 0; s < 3; ++s) {
+                d.edge[s] = -1;
+                d.level[s][0] = d.level[s][1] = -1;
+            }
+            a.dbg[q] = d;
+        }
+        return;
+    }
+    const int32_t n1 = a.next[h], p1 = a.prev[h];
+    Lod L{0, 0, 0.0f, 1.0f};
+    if constexpr (TRI) L = lod_of(a.qf[q]);
+    FetchSpec fs[3];
+    fetch_specs(h, n1, p1, u, v, fs);
+    float4 C = make_float4(0.f, 0.f, 0.f, 0.f);
+    float W = 0.0f;
+    htex_debug_rec d;
+    if constexpr (DBG) {
+        d = {};
+        d.next = n1;
+        d.prev = p1;
+        d.phi = L.phi;
+    }
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int32_t g = fs[s].g;
+        const bool flip = !(g > a.twin[g]);
+        const int32_t e = a.edge[g];
+        const int k = a.log2res[e];
+        const int64_t eb = a.base[e];
+        int lv[2];
+        float om[2];
+        const int nlev = fetch_levels(L, k, lv, om);
+        float4 Cf = make_float4(0.f, 0.f, 0.f, 0.f);
+        float Wf = 0.0f;
+        for (int sl = 0; sl < nlev; ++sl) {
+            const int m = k - lv[sl];
+            const int32_t n = 1 << m;
+            const AxisTaps X = axis_taps(fs[s].cx, fs[s].nx ^ flip, flip ? 1 : 0, m);
+            const AxisTaps Y = axis_taps(fs[s].cy, fs[s].ny ^ flip, flip ? 1 : 0, m);
+            const int64_t lvb = eb + level_offset(k, lv[sl]);
+            int mask = 0;
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj) {
+                const int32_t j = Y.i0 + dj;
+                const float wy = dj ? Y.w1 : Y.w0;
+#pragma unroll
+                for (int di = 0; di < 2; ++di) {
+                    const int32_t i = X.i0 + di;
+                    if ((uint32_t)i < (uint32_t)n && (uint32_t)j < (uint32_t)n) {
+                        const float w = om[sl] * ((di ? X.w1 : X.w0) * wy);
+                        const float4 T = load_texel<DT>(a.texels, lvb + (int64_t)j * n + i);
+                        Cf.x += w * T.x;
+                        Cf.y += w * T.y;
+                        Cf.z += w * T.z;
+                        Cf.w += w * T.w;
+                        Wf += w;
+                        mask |= 1 << (dj * 2 + di);
+                    }
+                }
+            }
+            if constexpr (DBG) {
+                d.i0[s][sl] = X.i0;
+                d.j0[s][sl] = Y.i0;
+                d.inb[s][sl] = mask;
+            }
+        }
+        if constexpr (DT == HTEX_FP8_E4M3) {
+            const float sc = a.scale[e];
+            Cf.x *= sc;
+            Cf.y *= sc;
+            Cf.z *= sc;
+            Cf.w *= sc;
+        }
+        C.x += Cf.x;
+        C.y += Cf.y;
+        C.z += Cf.z;
+        C.w += Cf.w;
+        W += Wf;
+        if constexpr (DBG) {
+            d.edge[s] = e;
+            d.flip[s] = flip ? 1 : 0;
+            d.level[s][0] = lv[0];
+            d.level[s][1] = lv[1];
+            d.wf[s] = Wf;
+        }
+    }
+    const float r = 1.0f / W;
+    out4[q] = make_float4(C.x * r, C.y * r, C.z * r, C.w * r);
+    if constexpr (DBG) {
+        d.W = W;
+        a.dbg[q] = d;
+    }
+}
+
+// Backward: out_c = sum over taps (om w / W) T_c, so dL/dT_c at each tap
+// receives (om w / W) dL/dout_c.  First the normalization W (weights only,
+// no texel reads), then the scatter with float32 atomics.
+template <bool TRI>
+__global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a, int64_t nblocks_real)
+{
+    const int64_t lb = logical_block(nblocks_real);
+    if (lb < 0) return;
+    const int64_t q = lb * kBlock + threadIdx.x;
+    if (q >= a.Q) return;
+    const int32_t h = a.qh[q];
+    const float u = a.qu[q], v = a.qv[q];
+    if (!((uint32_t)h < (uint32_t)a.H) || !isfinite(u) || !isfinite(v)) return;
+    const int32_t n1 = a.next[h], p1 = a.prev[h];
+    Lod L{0, 0, 0.0f, 1.0f};
+    if constexpr (TRI) L = lod_of(a.qf[q]);
+    FetchSpec fs[3];
+    fetch_specs(h, n1, p1, u, v, fs);
+    int32_t es[3], ks[3];
+    bool flips[3];
+    float W = 0.0f;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int32_t g = fs[s].g;
+        flips[s] = !(g > a.twin[g]);
+        es[s] = a.edge[g];
+        ks[s] = a.log2res[es[s]];
+        int lv[2];
+        float om[2];
+        const int nlev = fetch_levels(L, ks[s], lv, om);
+        for (int sl = 0; sl < nlev; ++sl) {
+            const int m = ks[s] - lv[sl];
+            const int32_t n = 1 << m;
+            const AxisTaps X = axis_taps(fs[s].cx, fs[s].nx ^ flips[s], flips[s] ? 1 : 0, m);
+            const AxisTaps Y = axis_taps(fs[s].cy, fs[s].ny ^ flips[s], flips[s] ? 1 : 0, m);
+            for (int dj = 0; dj < 2; ++dj)
+                for (int di = 0; di < 2; ++di) {
+                    const int32_t i = X.i0 + di, j = Y.i0 + dj;
+                    if ((uint32_t)i < (uint32_t)n && (uint32_t)j < (uint32_t)n)
+                        W += om[sl] * ((di ? X.w1 : X.w0) * (dj ? Y.w1 : Y.w0));
+                }
+        }
+    }
+    const float4 g4 = reinterpret_cast<const float4 *>(a.dout)[q];
+    const float r = 1.0f / W;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        int lv[2];
+        float om[2];
+        const int nlev = fetch_levels(L, ks[s], lv, om);
+        const int64_t eb = a.base[es[s]];
+        for (int sl = 0; sl < nlev; ++sl) {
+            const int m = ks[s] - lv[sl];
+            const int32_t n = 1 << m;
+            const AxisTaps X = axis_taps(fs[s].cx, fs[s].nx ^ flips[s], flips[s] ? 1 : 0, m);
+            const AxisTaps Y = axis_taps(fs[s].cy, fs[s].ny ^ flips[s], flips[s] ? 1 : 0, m);
+            const int64_t lvb = eb + level_offset(ks[s], lv[sl]);
+            for (int dj = 0; dj < 2; ++dj)
+                for (int di = 0; di < 2; ++di) {
+                    const int32_t i = X.i0 + di, j = Y.i0 + dj;
+                    if ((uint32_t)i < (uint32_t)n && (uint32_t)j < (uint32_t)n) {
+                        const float w =
+                            om[sl] * ((di ? X.w1 : X.w0) * (dj ? Y.w1 : Y.w0)) * r;
+                        float *p = a.dtex + 4 * (lvb + (int64_t)j * n + i);
+                        unsafeAtomicAdd(p + 0, w * g4.x);
+                        unsafeAtomicAdd(p + 1, w * g4.y);
+                        unsafeAtomicAdd(p + 2, w * g4.z);
+                        unsafeAtomicAdd(p + 3, w * g4.w);
+                    }
+                }
+        }
+    }
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <int DT, bool TRI>
+hipError_t launch_fwd(const SampleArgs &a, hipStream_t s)
+{
+    const int64_t nb = ceil_div(a.Q, kBlock);
+    const int64_t G = ceil_div(nb, 8) * 8;
+    if (a.dbg)
+        hipLaunchKernelGGL((k_sample<DT, TRI, true>), dim3((uint32_t)G), dim3(kBlock), 0, s, a, nb);
+    else
+        hipLaunchKernelGGL((k_sample<DT, TRI, false>), dim3((uint32_t)G), dim3(kBlock), 0, s, a, nb);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t s)
+{
+    if (a.Q == 0) return hipSuccess;
+    const bool tri = filter == HTEX_TRILINEAR;
+    switch (dtype) {
+    case HTEX_F32: return tri ? launch_fwd<HTEX_F32, true>(a, s) : launch_fwd<HTEX_F32, false>(a, s);
+    case HTEX_BF16: return tri ? launch_fwd<HTEX_BF16, true>(a, s) : launch_fwd<HTEX_BF16, false>(a, s);
+    default: return tri ? launch_fwd<HTEX_FP8_E4M3, true>(a, s) : launch_fwd<HTEX_FP8_E4M3, false>(a, s);
+    }
+}
+
+hipError_t launch_backward(const SampleArgs &a, int filter, hipStream_t s)
+{
+    if (a.Q == 0) return hipSuccess;
+    const int64_t nb = ceil_div(a.Q, kBlock);
+    const int64_t G = ceil_div(nb, 8) * 8;
+    if (filter == HTEX_TRILINEAR)
+        hipLaunchKernelGGL((k_backward<true>), dim3((uint32_t)G), dim3(kBlock), 0, s, a, nb);
+    else
+        hipLaunchKernelGGL((k_backward<false>), dim3((uint32_t)G), dim3(kBlock), 0, s, a, nb);
+    return hipGetLastError();
+}
+
+}  // namespace htex

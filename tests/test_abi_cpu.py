@@ -1,0 +1,137 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry
+point declared in include/htex.h, computes the pool layout, and rejects bad
+arguments before launching anything (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from htexgen import pool as gpool
+from tests.conftest import ROOT
+
+import paper_2207_05618_amd as htex
+from paper_2207_05618_amd import _lib
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "htex.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(htex_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.load()
+    names = declared_symbols()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.SIGNATURES)
+
+
+def test_generator_library_exports_fill():
+    import ctypes
+    from htexgen import build as gb
+    assert ctypes.CDLL(gb.LIB).htexgen_fill_level0
+
+
+def test_status_strings():
+    L = _lib.load()
+    for code in range(0, -8, -1):
+        assert L.htex_status_string(code).decode() not in ("", "unknown status")
+    assert L.htex_status_string(-99).decode() == "unknown status"
+
+
+@pytest.mark.parametrize("mips", [False, True])
+def test_pool_layout_matches_format(mips):
+    rng = np.random.default_rng(0)
+    lr = rng.integers(0, 8, 500).astype(np.uint8)
+    base, total = htex.htex_pool_layout(lr, mips)
+    b2, t2 = gpool.layout(lr, mips)
+    np.testing.assert_array_equal(base, b2)
+    assert total == t2
+    assert (base % 16 == 0).all()
+    cnt = ((4 << (2 * lr.astype(np.int64))) - 1) // 3 if mips else (1 << (2 * lr.astype(np.int64)))
+    assert (np.diff(np.append(base, total)) >= cnt).all()
+
+
+def test_pool_layout_rejects_oversized_resolution():
+    lr = np.array([3, 16], np.uint8)
+    with pytest.raises(_lib.HtexError) as ei:
+        htex.htex_pool_layout(lr, True)
+    assert ei.value.status == -3
+
+
+def _mesh(H=4, E=2, null=False):
+    return _lib.htex_mesh(H, E, None if null else 8, 8, 8, 8)
+
+
+def _pool(E=2, dtype=0, tex=16, mips=1, maxk=2, scale=None):
+    return _lib.htex_pool(E, dtype, mips, maxk, 64, 8, 8, tex, scale)
+
+
+def _q(Q=1, f=None):
+    return _lib.htex_queries(Q, 8, 8, 8, f)
+
+
+@pytest.mark.parametrize("case, status", [
+    ("null_mesh_array", -1), ("E_mismatch", -1), ("bad_dtype", -1), ("misaligned_texels", -1),
+    ("fp8_no_scale", -1), ("bad_filter", -1), ("tri_no_footprint", -1), ("tri_no_mips", -1),
+    ("neg_Q", -1), ("misaligned_out", -1), ("bad_flags", -1), ("big_k", -3),
+])
+def test_sample_rejects_bad_arguments_without_launching(case, status):
+    L = _lib.load()
+    mesh, pool, q = _mesh(), _pool(), _q()
+    filt, flags, out = 0, 0, 16
+    if case == "null_mesh_array":
+        mesh = _mesh(null=True)
+    elif case == "E_mismatch":
+        pool = _pool(E=3)
+    elif case == "bad_dtype":
+        pool = _pool(dtype=7)
+    elif case == "misaligned_texels":
+        pool = _pool(tex=24)
+    elif case == "fp8_no_scale":
+        pool = _pool(dtype=2)
+    elif case == "bad_filter":
+        filt = 5
+    elif case == "tri_no_footprint":
+        filt = 1
+    elif case == "tri_no_mips":
+        filt, pool, q = 1, _pool(mips=0), _q(f=8)
+    elif case == "neg_Q":
+        q = _q(Q=-1)
+    elif case == "misaligned_out":
+        out = 20
+    elif case == "bad_flags":
+        flags = 1 << 7
+    elif case == "big_k":
+        pool = _pool(maxk=16)
+    st = L.htex_sample(C.byref(mesh), C.byref(pool), C.byref(q), filt, flags, out, None, None,
+                       None)
+    assert st == status
+    assert L.htex_last_error().decode() != ""
+
+
+def test_backward_rejects_quantized_pool():
+    L = _lib.load()
+    st = L.htex_sample_backward(C.byref(_mesh()), C.byref(_pool(dtype=1, tex=8)),
+                                C.byref(_q()), 0, 0, 16, 16, None)
+    assert st == -5
+
+
+def test_quantize_and_mips_argument_checks():
+    L = _lib.load()
+    assert L.htex_quantize(C.byref(_pool()), 9, 16, 16, None) == -1
+    assert L.htex_quantize(C.byref(_pool(dtype=1, tex=8)), 1, 16, None, None) == -1
+    assert L.htex_build_mips(C.byref(_pool(mips=0)), 16, None) == -1
+    assert L.htex_build_mips(C.byref(_pool()), 32, None) == -1
+    assert L.htex_build_mips(C.byref(_pool(dtype=1, tex=8)), 8, None) == -5
+
+
+def test_product_path_refuses_cpu_tensors():
+    import torch
+    m = htex
+    with pytest.raises(TypeError):
+        m._dev(torch.zeros(3, dtype=torch.int32), torch.int32, "h")

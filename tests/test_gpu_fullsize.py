@@ -1,0 +1,117 @@
+"""Parity at the benchmark's full size, in the launch the benchmark times:
+the ~194k-face sphere with 64x64 RGBA float32 textures and mips (34.8 GB),
+8,294,400 sorted queries, trilinear.  The oracle cannot take the whole frame,
+so it checks sampled outputs -- a contiguous slice of the sorted batch and
+queries drawn across it -- with its texels from the host generator and its
+own FP64 mips; properties that hold at any size (batch independence,
+quantization error bounds) cover the rest.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2207_05618_amd as htex
+from htexgen import device as gdev
+from htexgen import pool as gpool
+from htexgen.mesh import sphere_mesh
+from htexgen.queries import uniform_queries
+from tests.gpu_helpers import assert_debug_equal, assert_rel, t
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def frame():
+    mesh = sphere_mesh(n=183, seed=201)
+    lr = np.full(mesh.E, 6, np.uint8)
+    pool = htex.Pool(lr, True, htex.HTEX_F32)
+    gdev.fill_level0(pool.texels, 1, 202, pool.log2res, pool.base, mesh.boundary_edges())
+    htex.htex_build_mips(pool)
+    q = uniform_queries(mesh.H, 3840 * 2160, 203, log2f=(-3.2, -1.2), sort=True)
+    dm = htex.Mesh.of(mesh)
+    out, _ = htex.htex_sample(dm, pool, t(q.h), t(q.u), t(q.v), t(q.f),
+                              filter=htex.HTEX_TRILINEAR, flags=htex.HTEX_QUERIES_SORTED)
+    torch.cuda.synchronize()
+    yield mesh, lr, pool, dm, q, out.cpu().numpy()
+    del pool
+    torch.cuda.empty_cache()
+
+
+def _oracle_for(mesh, lr, qs):
+    """Oracle mesh + pool restricted to the edges the queries touch (texels
+    from the host generator, mips by the oracle)."""
+    hs = np.unique(np.concatenate([qs.h, mesh.next[qs.h], mesh.prev[qs.h]]))
+    edges = np.unique(mesh.edge[hs])
+    remap = np.full(mesh.E, -1, np.int32)
+    remap[edges] = np.arange(len(edges), dtype=np.int32)
+    sub = lr[edges]
+    base, total = gpool.layout(sub, True)
+    lvl0 = np.zeros((total, 4), np.float32)
+    bnd = mesh.boundary_edges()[edges]
+    # fill edge by edge group (host generator keyed by the ORIGINAL edge id)
+    from htexgen.texels import texel_values
+    n = 1 << int(sub[0])
+    jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    for chunk in np.array_split(np.arange(len(edges)), max(1, len(edges) // 256)):
+        vals = texel_values(1, 202, edges[chunk][:, None, None], n, bnd[chunk][:, None, None],
+                            ii.reshape(-1)[None, :, None], jj.reshape(-1)[None, :, None],
+                            np.arange(4)[None, None, :])
+        rows = base[chunk][:, None] + np.arange(n * n)[None, :]
+        lvl0[rows.reshape(-1)] = vals.reshape(-1, 4)
+    op = oracle.Pool(sub, base, lvl0.astype(np.float64), True)
+    op = oracle.Pool(sub, base, oracle.build_mips(op), True)
+    om = oracle.Mesh(mesh.twin, mesh.next, mesh.prev, remap[mesh.edge], len(edges))
+    return om, op, remap
+
+
+def _samples(q):
+    rng = np.random.default_rng(7)
+    lo = q.Q // 3
+    idx = np.concatenate([np.arange(lo, lo + 3000), rng.choice(q.Q, 400, replace=False)])
+    return np.unique(idx)
+
+
+def test_frame_sampled_parity(frame):
+    mesh, lr, pool, dm, q, out = frame
+    idx = _samples(q)
+    qs = q.take(idx)
+    om, op, remap = _oracle_for(mesh, lr, qs)
+    ref, errs, do = oracle.sample(om, op, qs.h, qs.u, qs.v, qs.f, filter=oracle.TRILINEAR,
+                                  debug=True)
+    assert errs == 0
+    assert_rel(out[idx], ref, 1e-5)
+    # integer trace of the same queries (debug launch), edges mapped back
+    _, dbg = htex.htex_sample(dm, pool, t(qs.h), t(qs.u), t(qs.v), t(qs.f),
+                              filter=htex.HTEX_TRILINEAR, debug=True)
+    dg = htex.debug_records(dbg).copy()
+    dg["edge"] = remap[dg["edge"]]
+    assert_debug_equal(dg, do)
+
+
+def test_frame_unsorted_equals_sorted(frame):
+    """Results do not depend on the batch or on the order: the shuffled frame
+    gives the same bits per query."""
+    mesh, lr, pool, dm, q, out = frame
+    perm = np.random.default_rng(204).permutation(q.Q)
+    qu = q.take(perm)
+    o2, _ = htex.htex_sample(dm, pool, t(qu.h), t(qu.u), t(qu.v), t(qu.f),
+                             filter=htex.HTEX_TRILINEAR)
+    np.testing.assert_array_equal(o2.cpu().numpy(), out[perm])
+
+
+def test_frame_quantized_error_bounds(frame):
+    """BF16 and FP8 storage of the full pool: sampled error against the
+    oracle on the float32 texels within 4e-3 and 6e-2 relative."""
+    mesh, lr, pool, dm, q, out = frame
+    idx = _samples(q)[:1500]
+    qs = q.take(idx)
+    om, op, _ = _oracle_for(mesh, lr, qs)
+    ref, _, _ = oracle.sample(om, op, qs.h, qs.u, qs.v, qs.f, filter=oracle.TRILINEAR)
+    for dtype, tol in ((htex.HTEX_BF16, 4e-3), (htex.HTEX_FP8_E4M3, 6e-2)):
+        qp = htex.htex_quantize(pool, dtype)
+        g, _ = htex.htex_sample(dm, qp, t(qs.h), t(qs.u), t(qs.v), t(qs.f),
+                                filter=htex.HTEX_TRILINEAR)
+        assert_rel(g.cpu().numpy(), ref, tol)
+        del qp
+        torch.cuda.empty_cache()

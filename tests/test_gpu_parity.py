@@ -1,0 +1,403 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bar: integer debug fields (navigation, edges, reflections, mip levels, tap
+bases, in-bounds masks) bit-exact; float32 colours within 1e-5 relative
+(|got - ref| <= 1e-5 max(|ref|, 1e-6)); BF16 / FP8 storage within 4e-3 /
+6e-2 of the oracle on the float32 pool; gradients within 1e-4 of the sum of
+absolute contributions per texel channel.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2207_05618_amd as htex
+from htexgen import pool as gpool
+from htexgen.mesh import cube_mesh, sphere_mesh
+from htexgen.queries import Queries, uniform_queries
+from tests.fixtures import tiny_meshes
+from tests.gpu_helpers import Setup, assert_debug_equal, assert_rel, t
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    """96-quad cube (8 splits, 4 hexagons), 16x16 RGBA float32, no mips."""
+    return Setup(cube_mesh(), np.full(196, 4), has_mips=False, kind=0, seed=102)
+
+
+def test_cfg1_bilinear_parity(cfg1):
+    q = uniform_queries(cfg1.m.H, 65536, 103)
+    got, dg = cfg1.gpu(q, debug=True)
+    ref, errs, do = cfg1.ref(q, debug=True)
+    assert errs == 0
+    assert_debug_equal(dg, do)
+    assert_rel(got, ref, TOL)
+    got2, _ = cfg1.gpu(q)          # the non-debug kernel gives the same bits
+    np.testing.assert_array_equal(got, got2)
+
+
+@pytest.mark.parametrize("Q", [0, 1, 63, 255, 257, 1000, 4097])
+def test_ragged_batches(cfg1, Q):
+    q = uniform_queries(cfg1.m.H, Q, 900 + Q)
+    got, _ = cfg1.gpu(q)
+    assert got.shape == (Q, 4)
+    if Q:
+        ref, _, _ = cfg1.ref(q)
+        assert_rel(got, ref, TOL)
+
+
+@pytest.mark.parametrize("mesh_i", [0, 1, 2, 3])
+def test_trilinear_mixed_resolutions(mesh_i):
+    m = tiny_meshes()[mesh_i]
+    rng = np.random.default_rng(40 + mesh_i)
+    s = Setup(m, rng.integers(0, 7, m.E), has_mips=True, kind=1, seed=7)
+    q = uniform_queries(m.H, 20000, 41 + mesh_i, log2f=(-9, 1.5))
+    got, dg = s.gpu(q, htex.HTEX_TRILINEAR, debug=True)
+    ref, _, do = s.ref(q, oracle.TRILINEAR, debug=True)
+    assert_debug_equal(dg, do)
+    assert_rel(got, ref, TOL)
+    gb, db = s.gpu(q, htex.HTEX_BILINEAR, debug=True)
+    rb, _, ob = s.ref(q, oracle.BILINEAR, debug=True)
+    assert_debug_equal(db, ob)
+    assert_rel(gb, rb, TOL)
+
+
+def _adversarial(n):
+    from fractions import Fraction
+    vals = []
+    for m_ in range(0, n + 1):
+        for off in (Fraction(1, 2), Fraction(0)):
+            f = np.float32(float((m_ + off) / n))
+            for d in range(-3, 4):
+                g = f
+                for _ in range(abs(d)):
+                    g = np.nextafter(g, np.float32(2 if d > 0 else -2), dtype=np.float32)
+                vals.append(g)
+    return np.array(vals, np.float32)
+
+
+@pytest.mark.parametrize("k", [0, 3, 6])
+def test_exact_tap_bases_on_adversarial_coordinates(k):
+    """Coordinates a few ulps around texel centres and texel edges: the GPU's
+    integer rule must give the same floor(x n - 1/2) as exact arithmetic."""
+    m = cube_mesh()
+    s = Setup(m, np.full(m.E, k), has_mips=True, kind=0)
+    rng = np.random.default_rng(k)
+    c = _adversarial(1 << k)
+    c = np.concatenate([c, -c[:50], np.array([0.0, -0.0, 1e-40, 2 ** -30], np.float32)])
+    u, v = rng.permutation(c), rng.permutation(c)
+    h = rng.integers(0, m.H, len(u)).astype(np.int32)
+    f = np.exp2(rng.uniform(-8, 1, len(u))).astype(np.float32)
+    q = Queries(h, u, v, f)
+    for filt in (htex.HTEX_BILINEAR, htex.HTEX_TRILINEAR):
+        got, dg = s.gpu(q, filt, debug=True)
+        ref, _, do = s.ref(q, filt, debug=True)
+        assert_debug_equal(dg, do)
+        assert_rel(got, ref, TOL)
+
+
+def test_out_of_domain_and_invalid_queries(cfg1):
+    m = cfg1.m
+    h = np.array([0, -1, m.H, 3, 4, 5, 6, 7, 8, 9], np.int32)
+    u = np.array([0.2, 0.2, 0.2, np.nan, 0.1, -0.3, 1.7, 3.9, -3.999, -0.0], np.float32)
+    v = np.array([0.2, 0.2, 0.2, 0.1, np.inf, 0.2, -0.4, -3.9, 0.1, 0.0], np.float32)
+    q = Queries(h, u, v, None)
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    got, dg = cfg1.gpu(q, debug=True, err=err)
+    ref, errs, do = cfg1.ref(q, debug=True)
+    assert int(err.item()) == errs == 4
+    assert_debug_equal(dg, do)
+    assert_rel(got, ref, TOL)   # includes NaN rows where W = 0 (far outside)
+
+
+def test_special_footprints():
+    m = cube_mesh()
+    s = Setup(m, np.full(m.E, 5), has_mips=True, kind=1)
+    f = np.array([0.0, -1.0, np.nan, np.inf, -np.inf, 1e-42, 1.0, 0.5, 2.0 ** -5, 2.0 ** -6,
+                  3e38], np.float32)
+    n = len(f)
+    q = Queries(np.arange(n, dtype=np.int32), np.full(n, 0.3, np.float32),
+                np.full(n, 0.25, np.float32), f)
+    got, dg = s.gpu(q, htex.HTEX_TRILINEAR, debug=True)
+    ref, _, do = s.ref(q, oracle.TRILINEAR, debug=True)
+    assert_debug_equal(dg, do)
+    assert_rel(got, ref, TOL)
+
+
+@pytest.mark.parametrize("mesh_i", [0, 1, 3])
+def test_seams_bit_identical_on_gpu(mesh_i):
+    """Twin diagonal and Next/Prev legs: both sides give the same bits."""
+    m = tiny_meshes()[mesh_i]
+    s = Setup(m, np.full(m.E, 4), has_mips=False, kind=1)
+    tt = (np.arange(9, 60) / 64.0).astype(np.float32)
+    L = len(tt)
+    hs, us, vs, h2, u2, v2 = [], [], [], [], [], []
+    for h in range(m.H):
+        for eps in (0.0, 1.0 / 128):
+            e = np.float32(eps)
+            hs += [h] * L; us += list(np.full(L, -e)); vs += list(tt)
+            h2 += [m.next[h]] * L; u2 += list(tt); v2 += list(np.full(L, e))
+            hs += [h] * L; us += list(tt); vs += list(np.full(L, -e))
+            h2 += [m.prev[h]] * L; u2 += list(np.full(L, e)); v2 += list(tt)
+        if m.twin[h] >= 0:
+            uu = (np.arange(2, 63) / 64.0).astype(np.float32)
+            hs += [h] * len(uu); us += list(uu); vs += list(1 - uu)
+            h2 += [m.twin[h]] * len(uu); u2 += list(1 - uu); v2 += list(uu)
+    A = Queries(np.array(hs, np.int32), np.array(us, np.float32), np.array(vs, np.float32), None)
+    B = Queries(np.array(h2, np.int32), np.array(u2, np.float32), np.array(v2, np.float32), None)
+    ga, _ = s.gpu(A)
+    gb, _ = s.gpu(B)
+    np.testing.assert_array_equal(ga, gb)
+
+
+def test_deterministic_and_batch_independent(cfg1):
+    q = uniform_queries(cfg1.m.H, 50000, 5)
+    a, _ = cfg1.gpu(q)
+    b, _ = cfg1.gpu(q)
+    np.testing.assert_array_equal(a, b)
+    idx = np.random.default_rng(1).choice(q.Q, 777, replace=False)
+    c, _ = cfg1.gpu(q.take(idx))
+    np.testing.assert_array_equal(a[idx], c)
+
+
+def test_linear_ramp_closed_form_on_gpu():
+    """Bilinear filtering reproduces (x, y, 1, x y) at interior quad points,
+    with (x, y) given by Alg. 2 -- checked without the oracle."""
+    m = cube_mesh()
+    k = 4
+    n = 1 << k
+    lr = np.full(m.E, k, np.uint8)
+    base, total = gpool.layout(lr, False)
+    xc = (np.arange(n) + 0.5) / n
+    ramp = np.stack(np.broadcast_arrays(xc[None, :], xc[:, None], 1.0,
+                                        xc[None, :] * xc[:, None]), -1).reshape(-1, 4)
+    T = np.zeros((total, 4), np.float32)
+    for e in range(m.E):
+        T[base[e]:base[e] + n * n] = ramp
+    pool = htex.Pool(lr, False, texels=t(T))
+    dm = htex.Mesh.of(m)
+    rng = np.random.default_rng(2)
+    lo = 0.5 / n + 1e-3
+    h = rng.integers(0, m.H, 5000).astype(np.int32)
+    u = rng.uniform(lo, 1 - 2 * lo, 5000)
+    v = rng.uniform(lo, 1 - lo - u)
+    u, v = u.astype(np.float32), v.astype(np.float32)
+    out, _ = htex.htex_sample(dm, pool, t(h), t(u), t(v))
+    out = out.cpu().numpy()
+    keep = h > m.twin[h]
+    x = np.where(keep, u, 1 - u.astype(np.float64))
+    y = np.where(keep, v, 1 - v.astype(np.float64))
+    np.testing.assert_allclose(out, np.stack([x, y, np.ones_like(x), x * y], -1), atol=2e-6)
+
+
+def test_mips_match_oracle():
+    m = cube_mesh()
+    rng = np.random.default_rng(9)
+    s = Setup(m, rng.integers(0, 9, m.E), has_mips=True, kind=0)
+    got = s.pool.texels.cpu().numpy().astype(np.float64)
+    ref = s.opool.texels
+    # box means of float32 values: a few ulps of float32
+    assert_rel(got, ref, 1e-6)
+
+
+def test_max_resolution_edges():
+    """Edges up to 2048 x 2048 (k = 11) next to 1 x 1 ones."""
+    m = cube_mesh(n=2, seed=7, n_split=3, n_merge=1)
+    lr = np.zeros(m.E, np.uint8)
+    lr[::3] = 11
+    lr[1::3] = 0
+    lr[2::3] = 6
+    s = Setup(m, lr, has_mips=True, kind=0)
+    q = uniform_queries(m.H, 30000, 77, log2f=(-13, 1))
+    for filt in (htex.HTEX_BILINEAR, htex.HTEX_TRILINEAR):
+        got, dg = s.gpu(q, filt, debug=True)
+        ref, _, do = s.ref(q, filt, debug=True)
+        assert_debug_equal(dg, do)
+        assert_rel(got, ref, TOL)
+
+
+# ----------------------------------------------------- precision forms ---
+
+@pytest.fixture(scope="module")
+def cfg3():
+    s = Setup(cube_mesh(), np.full(196, 4), has_mips=False, kind=0, seed=102)
+    return s
+
+
+def test_quantize_codes_bit_exact(cfg3):
+    src = cfg3.pool.texels.cpu().numpy()
+    qb = htex.htex_quantize(cfg3.pool, htex.HTEX_BF16)
+    torch.cuda.synchronize()
+    got_b = qb.texels.cpu().numpy().view(np.uint16)
+    np.testing.assert_array_equal(got_b.reshape(-1), oracle.f32_to_bf16(src))
+    q8 = htex.htex_quantize(cfg3.pool, htex.HTEX_FP8_E4M3)
+    torch.cuda.synchronize()
+    codes, scale = oracle.quantize_e4m3(cfg3.log2res, cfg3.pool.base_host, False, src)
+    np.testing.assert_array_equal(q8.scale.cpu().numpy(), scale)
+    np.testing.assert_array_equal(q8.texels.cpu().numpy(), codes)
+
+
+def test_quantize_fp8_edge_cases():
+    """Zero edges, values near the subnormal/normal boundary and ties."""
+    m = cube_mesh(n=2, seed=7, n_split=3, n_merge=1)
+    lr = np.full(m.E, 2, np.uint8)
+    base, total = gpool.layout(lr, True)
+    rng = np.random.default_rng(4)
+    T = np.zeros((total, 4), np.float32)
+    tab = oracle.e4m3_table()
+    fin = np.unique(np.abs(tab[np.isfinite(tab)]))
+    mids = ((fin[1:] + fin[:-1]) / 2).astype(np.float32)
+    for e in range(1, m.E):
+        cnt = 21 * 4
+        vals = np.concatenate([mids, -mids, fin.astype(np.float32), rng.standard_normal(cnt)])
+        vals = rng.choice(vals, cnt).astype(np.float32) * np.float32(2.0 ** rng.integers(-12, 12))
+        T[base[e]:base[e] + 21] = vals.reshape(21, 4)
+    pool = htex.Pool(lr, True, texels=t(T))
+    q8 = htex.htex_quantize(pool, htex.HTEX_FP8_E4M3)
+    torch.cuda.synchronize()
+    codes, scale = oracle.quantize_e4m3(lr, base, True, T)
+    np.testing.assert_array_equal(q8.scale.cpu().numpy(), scale)
+    np.testing.assert_array_equal(q8.texels.cpu().numpy(), codes)
+    assert scale[0] == 0
+
+
+def test_quantized_sampling_parity_and_error(cfg3):
+    """The 1M-query precision study: each stored format sampled on the GPU
+    matches the oracle on the same stored values (1e-5), and its error
+    against the oracle on the float32 pool stays within 4e-3 (BF16) and
+    6e-2 (FP8)."""
+    q = uniform_queries(cfg3.m.H, 1 << 20, 301)
+    ref32, _, _ = cfg3.ref(q)
+    src = cfg3.pool.texels.cpu().numpy()
+    qb = htex.htex_quantize(cfg3.pool, htex.HTEX_BF16)
+    gb, _ = cfg3.gpu(q, pool=qb)
+    ob = oracle.Pool(cfg3.log2res, cfg3.pool.base_host,
+                     oracle.bf16_to_f64(qb.texels.cpu().numpy().view(np.uint16)), False)
+    rb, _, _ = cfg3.ref(q, opool=ob)
+    assert_rel(gb, rb, TOL)
+    assert_rel(gb, ref32, 4e-3)
+    q8 = htex.htex_quantize(cfg3.pool, htex.HTEX_FP8_E4M3)
+    g8, _ = cfg3.gpu(q, pool=q8)
+    o8 = oracle.Pool(cfg3.log2res, cfg3.pool.base_host,
+                     oracle.e4m3_pool_to_f64(cfg3.log2res, cfg3.pool.base_host, False,
+                                             q8.texels.cpu().numpy(), q8.scale.cpu().numpy()),
+                     False)
+    r8, _, _ = cfg3.ref(q, opool=o8)
+    assert_rel(g8, r8, TOL)
+    assert_rel(g8, ref32, 6e-2)
+    assert src.dtype == np.float32
+
+
+@pytest.mark.parametrize("dtype", [htex.HTEX_BF16, htex.HTEX_FP8_E4M3])
+def test_quantized_trilinear_debug(dtype):
+    m = tiny_meshes()[1]
+    s = Setup(m, np.random.default_rng(3).integers(0, 6, m.E), has_mips=True, kind=1)
+    qp = htex.htex_quantize(s.pool, dtype)
+    torch.cuda.synchronize()
+    if dtype == htex.HTEX_BF16:
+        vals = oracle.bf16_to_f64(qp.texels.cpu().numpy().view(np.uint16))
+    else:
+        vals = oracle.e4m3_pool_to_f64(s.log2res, s.pool.base_host, True, qp.texels.cpu().numpy(),
+                                       qp.scale.cpu().numpy())
+    op = oracle.Pool(s.log2res, s.pool.base_host, vals, True)
+    q = uniform_queries(m.H, 10000, 5, log2f=(-8, 1))
+    got, dg = s.gpu(q, htex.HTEX_TRILINEAR, debug=True, pool=qp)
+    ref, _, do = s.ref(q, oracle.TRILINEAR, debug=True, opool=op)
+    assert_debug_equal(dg, do)
+    assert_rel(got, ref, TOL)
+
+
+# ------------------------------------------------------------ backward ---
+
+@pytest.mark.parametrize("filt", [htex.HTEX_BILINEAR, htex.HTEX_TRILINEAR])
+def test_backward_matches_oracle_gradient(filt):
+    m = cube_mesh()
+    mips = filt == htex.HTEX_TRILINEAR
+    s = Setup(m, np.full(m.E, 5 if mips else 4), has_mips=mips, kind=1)
+    q = uniform_queries(m.H, 200000, 403, log2f=(-7, 0) if mips else None, sort=True)
+    g = np.random.default_rng(404).standard_normal((q.Q, 4)).astype(np.float32)
+    f = t(q.f) if q.f is not None else None
+    d = htex.htex_sample_backward(s.dmesh, s.pool, t(q.h), t(q.u), t(q.v), t(g), f, filter=filt)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy().astype(np.float64)
+    ref, dabs = oracle.backward(s.omesh, s.opool, q.h, q.u, q.v, g, q.f, filter=filt,
+                                with_abs=True)
+    err = np.abs(got - ref)
+    assert (err <= 1e-4 * dabs + 1e-12).all(), float((err / np.maximum(dabs, 1e-30)).max())
+
+
+def test_backward_adjoint_on_gpu():
+    """<g, J dT> = <J^T g, dT>: GPU forward on a random pool against the GPU
+    backward, accumulated in float64 on the host."""
+    m = tiny_meshes()[1]
+    rng = np.random.default_rng(6)
+    lr = rng.integers(1, 5, m.E).astype(np.uint8)
+    base, total = gpool.layout(lr, True)
+    dT = rng.standard_normal((total, 4)).astype(np.float32)
+    pool = htex.Pool(lr, True, texels=t(dT))
+    dm = htex.Mesh.of(m)
+    q = uniform_queries(m.H, 100000, 8, log2f=(-6, 0))
+    g = rng.standard_normal((q.Q, 4)).astype(np.float32)
+    out, _ = htex.htex_sample(dm, pool, t(q.h), t(q.u), t(q.v), t(q.f), htex.HTEX_TRILINEAR)
+    gT = htex.htex_sample_backward(dm, pool, t(q.h), t(q.u), t(q.v), t(g), t(q.f),
+                                   htex.HTEX_TRILINEAR)
+    o64 = out.cpu().numpy().astype(np.float64)
+    g64 = gT.cpu().numpy().astype(np.float64)
+    lhs = (o64 * g).sum()
+    rhs = (g64 * dT).sum()
+    scale = np.abs(o64 * g).sum() + np.abs(g64 * dT).sum()
+    assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+def test_autograd_function():
+    m = cube_mesh()
+    s = Setup(m, np.full(m.E, 3), has_mips=False, kind=0)
+    q = uniform_queries(m.H, 5000, 3)
+    tex = s.pool.texels.requires_grad_(True)
+    out = htex.HtexSample.apply(tex, s.dmesh, s.pool, t(q.h), t(q.u), t(q.v), None,
+                                htex.HTEX_BILINEAR)
+    (out * out).sum().backward()
+    g = 2 * out.detach()
+    ref = htex.htex_sample_backward(s.dmesh, s.pool, t(q.h), t(q.u), t(q.v), g.contiguous())
+    assert torch.allclose(tex.grad, ref, rtol=1e-5, atol=1e-7)
+    tex.requires_grad_(False)
+
+
+# ----------------------------------------------------- generators / mesh -
+
+def test_device_fill_matches_host_generator():
+    from htexgen import device as gdev
+    m = cube_mesh(n=3, seed=5, n_split=4, n_merge=2)
+    rng = np.random.default_rng(1)
+    lr = rng.integers(0, 7, m.E).astype(np.uint8)
+    for kind in (0, 1):
+        base, total = gpool.layout(lr, True)
+        ref = gpool.fill_level0_host(kind, 77, lr, base, total, m.boundary_edges(), True)
+        dev = torch.zeros((total, 4), dtype=torch.float32, device="cuda")
+        gdev.fill_level0(dev, kind, 77, t(lr), t(base), m.boundary_edges())
+        np.testing.assert_array_equal(dev.cpu().numpy(), ref)
+
+
+def test_mesh_validate_on_gpu():
+    for m in tiny_meshes() + [sphere_mesh(n=12, seed=3)]:
+        ok, bad = htex.htex_mesh_validate(htex.Mesh.of(m))
+        assert ok and bad == -1
+    m = cube_mesh()
+    for plant in range(4):
+        tw, nx, pv, ed = m.twin.copy(), m.next.copy(), m.prev.copy(), m.edge.copy()
+        if plant == 0:
+            tw[5] = tw[6]
+        elif plant == 1:
+            nx[3], nx[4] = nx[4], nx[3]
+        elif plant == 2:
+            ed[7] = (ed[7] + 1) % m.E
+        else:
+            pv[0] = m.H
+        ok, bad = htex.htex_mesh_validate(htex.Mesh(tw, nx, pv, ed, m.E))
+        rc, obad = oracle.validate(oracle.Mesh(tw, nx, pv, ed, m.E))
+        assert not ok and rc != 0
+        assert bad >= 0
