@@ -33,7 +33,8 @@ struct AxisTaps {
 
 // x = (neg ? -1 : 1) * c + rho, sampled on a level of n = 2^m texels.  Both
 // weights are formed from the exact fraction r without cancellation (each
-// within an ulp of its exact value, however close to 0 it is).
+// within an ulp of its exact value, however close to 0 it is).  Written with
+// selects only, so lanes with different signs do not diverge.
 __device__ __forceinline__ AxisTaps axis_taps(float c, bool neg, int rho, int m)
 {
     const bool eneg = neg != ((__float_as_uint(c) >> 31) != 0u);
@@ -41,25 +42,22 @@ __device__ __forceinline__ AxisTaps axis_taps(float c, bool neg, int rho, int m)
     const float qf = floorf(t);
     const float r = t - qf;
     const int32_t q = (int32_t)qf;
-    const int32_t rn = rho << m;
+    // x n - 1/2 = rn + q + r - 1/2 (eneg false) or rn - q - r - 1/2 (eneg true)
+    const bool up = (r > 0.5f) | ((!eneg) & (r == 0.5f));
+    const float fr = r + (up ? -0.5f : 0.5f);   // exact when up
+    const float cf = (up ? 1.5f : 0.5f) - r;    // exact when up
     AxisTaps o;
-    if (!eneg) {
-        const bool up = r >= 0.5f;   // x n - 1/2 = rn + q + (r - 1/2)
-        o.i0 = rn + q - 1 + (up ? 1 : 0);
-        o.w1 = up ? r - 0.5f : r + 0.5f;
-        o.w0 = up ? 1.5f - r : 0.5f - r;
-    } else {
-        const bool up = r > 0.5f;    // x n - 1/2 = rn - q - (r + 1/2)
-        o.i0 = rn - q - 1 - (up ? 1 : 0);
-        o.w1 = up ? 1.5f - r : 0.5f - r;
-        o.w0 = up ? r - 0.5f : r + 0.5f;
-    }
+    o.w1 = eneg ? cf : fr;
+    o.w0 = eneg ? fr : cf;
+    const int32_t G = q + (up ? 1 : 0);
+    o.i0 = (rho << m) - 1 + (eneg ? -G : G);
     return o;
 }
 
 template <int DT>
 __device__ __forceinline__ float4 load_texel(const void *tex, int64_t idx)
 {
+    // idx counts texels from `tex`
     if constexpr (DT == HTEX_F32) {
         return reinterpret_cast<const float4 *>(tex)[idx];
     } else if constexpr (DT == HTEX_BF16) {
@@ -82,12 +80,32 @@ __device__ __forceinline__ float4 load_texel(const void *tex, int64_t idx)
     }
 }
 
+// log2(z) for z in [1/2, 2] through the series of atanh:
+// log2(z) = (2 / ln 2) atanh(s), s = (z - 1) / (z + 1), here with
+// |s| <= 1/3 so eight odd terms leave a relative truncation error below
+// 2e-9.  The result keeps full relative precision when it is near zero, as
+// long as z - 1 is passed exactly (numerator and denominator separately).
+__device__ __forceinline__ float log2_atanh(float num, float den)
+{
+    const float s = num * __builtin_amdgcn_rcpf(den);
+    const float s2 = s * s;
+    float p = 1.923593388e-01f;
+    p = fmaf(p, s2, 2.219530832e-01f);
+    p = fmaf(p, s2, 2.623081893e-01f);
+    p = fmaf(p, s2, 3.205988980e-01f);
+    p = fmaf(p, s2, 4.121985831e-01f);
+    p = fmaf(p, s2, 5.770780164e-01f);
+    p = fmaf(p, s2, 9.617966939e-01f);
+    p = fmaf(p, s2, 2.885390082e+00f);
+    return s * p;
+}
+
 // Trilinear level selection from the footprint: f = m 2^E, m in [1, 2);
 // floor(lambda) = E + k, frac(lambda) = log2(m).  `mode`: 0 = level 0 only,
 // 1 = coarsest level only, 2 = level pair (E + k, E + k + 1) unless clamped
-// per fetch.  The blend weights phi = log2(m) and 1 - phi = -log2(1 - y/2)
-// with y = 2 - m are both evaluated through log1p of exact arguments, so
-// each keeps full relative precision when it is close to zero.
+// per fetch.  The blend weights phi = log2(m) and 1 - phi = log2(2 / m) are
+// each evaluated directly (m - 1 and 2 - m are exact), so each keeps full
+// relative precision when it is close to zero.
 struct Lod {
     int mode;
     int E;
@@ -99,34 +117,28 @@ __device__ __forceinline__ Lod lod_of(float f)
 {
     Lod L{0, 0, 0.0f, 1.0f};
     const uint32_t b = __float_as_uint(f);
-    if (!(f > 0.0f)) return L;                 // <= 0 or NaN
-    if (b == 0x7f800000u) { L.mode = 1; return L; }
     const uint32_t ex = (b >> 23) & 0xffu;
-    if (ex == 0) return L;                     // subnormal: magnification
-    L.mode = 2;
+    const bool finite_pos_normal = (f > 0.0f) & (ex != 0u) & (ex != 0xffu);
+    L.mode = finite_pos_normal ? 2 : (b == 0x7f800000u ? 1 : 0);
     L.E = (int)ex - 127;
     const float m = __uint_as_float((b & 0x7fffffu) | 0x3f800000u);
-    constexpr float kInvLn2 = 1.44269504088896340736f;
-    L.phi = log1pf(m - 1.0f) * kInvLn2;            // m - 1 exact
-    L.om0 = -log1pf(-0.5f * (2.0f - m)) * kInvLn2;  // 2 - m exact
+    L.phi = finite_pos_normal ? log2_atanh(m - 1.0f, m + 1.0f) : 0.0f;
+    L.om0 = finite_pos_normal ? log2_atanh(2.0f - m, 2.0f + m) : 1.0f;
     return L;
 }
 
-// Levels and weights of one fetch on a texture of log2 resolution k.
+// Levels and weights of one fetch on a texture of log2 resolution k
+// (selects only).  Returns the number of levels (1 or 2).
 __device__ __forceinline__ int fetch_levels(const Lod &L, int k, int lv[2], float om[2])
 {
-    lv[1] = -1;
-    om[1] = 0.0f;
-    if (L.mode == 0) { lv[0] = 0; om[0] = 1.0f; return 1; }
-    if (L.mode == 1) { lv[0] = k; om[0] = 1.0f; return 1; }
     const int li = L.E + k;
-    if (li < 0) { lv[0] = 0; om[0] = 1.0f; return 1; }
-    if (li >= k) { lv[0] = k; om[0] = 1.0f; return 1; }
-    lv[0] = li;
-    om[0] = L.om0;
-    lv[1] = li + 1;
-    om[1] = L.phi;
-    return 2;
+    const bool pair = (L.mode == 2) && li >= 0 && li < k;
+    const bool coarsest = (L.mode == 1) || (L.mode == 2 && li >= k);
+    lv[0] = pair ? li : (coarsest ? k : 0);
+    lv[1] = pair ? li + 1 : -1;
+    om[0] = pair ? L.om0 : 1.0f;
+    om[1] = pair ? L.phi : 0.0f;
+    return pair ? 2 : 1;
 }
 
 // The three fetches of Alg. 3: halfedge and (raw coordinate, negated?) for x, y.
@@ -154,6 +166,67 @@ __device__ __forceinline__ int64_t logical_block(int64_t nblocks_real)
     const int64_t per = G >> 3;
     const int64_t lb = (b & 7) * per + (b >> 3);
     return lb < nblocks_real ? lb : -1;
+}
+
+// Texel offset of level l inside an edge of log2 resolution k, 32-bit:
+// sum_{m<l} 4^(k-m) = 4^(k-l+1) (4^l - 1) / 3, and (4^l - 1) / 3 is the bit
+// pattern 0101...01 with l ones (at most 1.43e9 texels for k = 15).
+__device__ __forceinline__ uint32_t level_offset32(int k, int l)
+{
+    const uint32_t ones = l ? (0x55555555u >> (32 - 2 * l)) : 0u;
+    return ones << (2 * (k - l) + 2);
+}
+
+template <int DT> struct TexelBytes;
+template <> struct TexelBytes<HTEX_F32> { static constexpr int v = 16; };
+template <> struct TexelBytes<HTEX_BF16> { static constexpr int v = 8; };
+template <> struct TexelBytes<HTEX_FP8_E4M3> { static constexpr int v = 4; };
+
+// One mip level of one fetch: the bilinear taps (i0 + di, j0 + dj) with the
+// level weight `om` folded into the row weights.  Out-of-bounds taps get
+// weight 0; when at least one tap is in bounds the four loads read clamped,
+// in-bounds addresses of the same level (so the zero-weight ones are
+// harmless), otherwise nothing is read.  The normalization channel of the
+// level is om (wx0 + wx1)(wy0 + wy1) over the in-bounds weights.
+struct LevelOut {
+    int32_t i0, j0;
+    int mask;
+};
+
+template <int DT>
+__device__ __forceinline__ LevelOut sample_level(const char *ep, int k, int l, float om,
+                                                 const FetchSpec &fs, bool flip, float4 &Cf,
+                                                 float &Wf)
+{
+    const int m = k - l;
+    const int32_t n = 1 << m;
+    const AxisTaps X = axis_taps(fs.cx, fs.nx ^ flip, flip ? 1 : 0, m);
+    const AxisTaps Y = axis_taps(fs.cy, fs.ny ^ flip, flip ? 1 : 0, m);
+    const bool bx0 = (uint32_t)X.i0 < (uint32_t)n, bx1 = (uint32_t)(X.i0 + 1) < (uint32_t)n;
+    const bool by0 = (uint32_t)Y.i0 < (uint32_t)n, by1 = (uint32_t)(Y.i0 + 1) < (uint32_t)n;
+    LevelOut o{X.i0, Y.i0,
+               (bx0 && by0 ? 1 : 0) | (bx1 && by0 ? 2 : 0) | (bx0 && by1 ? 4 : 0) |
+                   (bx1 && by1 ? 8 : 0)};
+    if ((bx0 || bx1) && (by0 || by1)) {
+        const float wx0 = bx0 ? X.w0 : 0.0f, wx1 = bx1 ? X.w1 : 0.0f;
+        const float wy0 = by0 ? om * Y.w0 : 0.0f, wy1 = by1 ? om * Y.w1 : 0.0f;
+        const int32_t ic0 = max(X.i0, 0), ic1 = min(X.i0 + 1, n - 1);
+        const int32_t jc0 = max(Y.i0, 0), jc1 = min(Y.i0 + 1, n - 1);
+        const uint32_t lo = level_offset32(k, l);
+        const uint32_t r0 = lo + (uint32_t)(jc0 << m), r1 = lo + (uint32_t)(jc1 << m);
+        constexpr int TB = TexelBytes<DT>::v;
+        const float4 t00 = load_texel<DT>(ep + (uint64_t)(r0 + ic0) * TB, 0);
+        const float4 t01 = load_texel<DT>(ep + (uint64_t)(r0 + ic1) * TB, 0);
+        const float4 t10 = load_texel<DT>(ep + (uint64_t)(r1 + ic0) * TB, 0);
+        const float4 t11 = load_texel<DT>(ep + (uint64_t)(r1 + ic1) * TB, 0);
+        const float w00 = wx0 * wy0, w01 = wx1 * wy0, w10 = wx0 * wy1, w11 = wx1 * wy1;
+        Cf.x += w00 * t00.x; Cf.y += w00 * t00.y; Cf.z += w00 * t00.z; Cf.w += w00 * t00.w;
+        Cf.x += w01 * t01.x; Cf.y += w01 * t01.y; Cf.z += w01 * t01.z; Cf.w += w01 * t01.w;
+        Cf.x += w10 * t10.x; Cf.y += w10 * t10.y; Cf.z += w10 * t10.z; Cf.w += w10 * t10.w;
+        Cf.x += w11 * t11.x; Cf.y += w11 * t11.y; Cf.z += w11 * t11.z; Cf.w += w11 * t11.w;
+        Wf += (wx0 + wx1) * (wy0 + wy1);
+    }
+    return o;
 }
 
 template <int DT, bool TRI, bool DBG>
@@ -195,50 +268,23 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a, int64_t nblocks
         d.prev = p1;
         d.phi = L.phi;
     }
+    constexpr int TB = TexelBytes<DT>::v;
+    const char *tex = static_cast<const char *>(a.texels);
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
         const int32_t g = fs[s].g;
         const bool flip = !(g > a.twin[g]);
         const int32_t e = a.edge[g];
         const int k = a.log2res[e];
-        const int64_t eb = a.base[e];
+        const char *ep = tex + a.base[e] * TB;
         int lv[2];
         float om[2];
         const int nlev = fetch_levels(L, k, lv, om);
         float4 Cf = make_float4(0.f, 0.f, 0.f, 0.f);
         float Wf = 0.0f;
-        for (int sl = 0; sl < nlev; ++sl) {
-            const int m = k - lv[sl];
-            const int32_t n = 1 << m;
-            const AxisTaps X = axis_taps(fs[s].cx, fs[s].nx ^ flip, flip ? 1 : 0, m);
-            const AxisTaps Y = axis_taps(fs[s].cy, fs[s].ny ^ flip, flip ? 1 : 0, m);
-            const int64_t lvb = eb + level_offset(k, lv[sl]);
-            int mask = 0;
-#pragma unroll
-            for (int dj = 0; dj < 2; ++dj) {
-                const int32_t j = Y.i0 + dj;
-                const float wy = dj ? Y.w1 : Y.w0;
-#pragma unroll
-                for (int di = 0; di < 2; ++di) {
-                    const int32_t i = X.i0 + di;
-                    if ((uint32_t)i < (uint32_t)n && (uint32_t)j < (uint32_t)n) {
-                        const float w = om[sl] * ((di ? X.w1 : X.w0) * wy);
-                        const float4 T = load_texel<DT>(a.texels, lvb + (int64_t)j * n + i);
-                        Cf.x += w * T.x;
-                        Cf.y += w * T.y;
-                        Cf.z += w * T.z;
-                        Cf.w += w * T.w;
-                        Wf += w;
-                        mask |= 1 << (dj * 2 + di);
-                    }
-                }
-            }
-            if constexpr (DBG) {
-                d.i0[s][sl] = X.i0;
-                d.j0[s][sl] = Y.i0;
-                d.inb[s][sl] = mask;
-            }
-        }
+        const LevelOut o0 = sample_level<DT>(ep, k, lv[0], om[0], fs[s], flip, Cf, Wf);
+        LevelOut o1{0, 0, 0};
+        if (TRI && nlev == 2) o1 = sample_level<DT>(ep, k, lv[1], om[1], fs[s], flip, Cf, Wf);
         if constexpr (DT == HTEX_FP8_E4M3) {
             const float sc = a.scale[e];
             Cf.x *= sc;
@@ -256,10 +302,18 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a, int64_t nblocks
             d.flip[s] = flip ? 1 : 0;
             d.level[s][0] = lv[0];
             d.level[s][1] = lv[1];
+            d.i0[s][0] = o0.i0;
+            d.j0[s][0] = o0.j0;
+            d.inb[s][0] = o0.mask;
+            if (nlev == 2) {
+                d.i0[s][1] = o1.i0;
+                d.j0[s][1] = o1.j0;
+                d.inb[s][1] = o1.mask;
+            }
             d.wf[s] = Wf;
         }
     }
-    const float r = 1.0f / W;
+    const float r = __builtin_amdgcn_rcpf(W);
     out4[q] = make_float4(C.x * r, C.y * r, C.z * r, C.w * r);
     if constexpr (DBG) {
         d.W = W;
