@@ -65,18 +65,12 @@ __device__ __forceinline__ float4 load_texel(const void *tex, int64_t idx)
         return make_float4(__uint_as_float(p.x << 16), __uint_as_float(p.x & 0xffff0000u),
                            __uint_as_float(p.y << 16), __uint_as_float(p.y & 0xffff0000u));
     } else {
-        const uint32_t p = reinterpret_cast<const uint32_t *>(tex)[idx];
-        auto dec = [](uint32_t b) -> float {
-            // OCP E4M3: exponent field 0 -> subnormal m * 2^-9; S.1111.111 -> NaN
-            const uint32_t mag = b & 0x7fu;
-            const uint32_t e = mag >> 3, mm = mag & 7u;
-            float v = (e == 0) ? (float)mm * 0x1p-9f
-                               : __uint_as_float(((e + 120u) << 23) | (mm << 20));
-            v = (mag == 0x7fu) ? __uint_as_float(0x7fc00000u) : v;
-            return (b & 0x80u) ? -v : v;
-        };
-        return make_float4(dec(p & 0xffu), dec((p >> 8) & 0xffu), dec((p >> 16) & 0xffu),
-                           dec(p >> 24));
+        // OCP E4M3 -> float32 with gfx950's packed converter (exact for all
+        // 256 codes, subnormals and NaN included)
+        const int p = reinterpret_cast<const int *>(tex)[idx];
+        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(p, false);
+        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(p, true);
+        return make_float4(lo[0], lo[1], hi[0], hi[1]);
     }
 }
 
@@ -156,18 +150,6 @@ __device__ __forceinline__ void fetch_specs(int32_t h, int32_t n1, int32_t p1, f
     fs[2] = {p1, v, u, true, false};    // Prev quad at (-v, u)
 }
 
-// XCD-aware block order: hardware deals consecutive workgroups to the 8 XCDs
-// in turn; give each XCD a contiguous share of the (sorted) query range so
-// neighbouring queries -- which read the same textures -- meet in one L2.
-__device__ __forceinline__ int64_t logical_block(int64_t nblocks_real)
-{
-    const int64_t G = gridDim.x;          // multiple of 8
-    const int64_t b = blockIdx.x;
-    const int64_t per = G >> 3;
-    const int64_t lb = (b & 7) * per + (b >> 3);
-    return lb < nblocks_real ? lb : -1;
-}
-
 // Texel offset of level l inside an edge of log2 resolution k, 32-bit:
 // sum_{m<l} 4^(k-m) = 4^(k-l+1) (4^l - 1) / 3, and (4^l - 1) / 3 is the bit
 // pattern 0101...01 with l ones (at most 1.43e9 texels for k = 15).
@@ -182,21 +164,22 @@ template <> struct TexelBytes<HTEX_F32> { static constexpr int v = 16; };
 template <> struct TexelBytes<HTEX_BF16> { static constexpr int v = 8; };
 template <> struct TexelBytes<HTEX_FP8_E4M3> { static constexpr int v = 4; };
 
-// One mip level of one fetch: the bilinear taps (i0 + di, j0 + dj) with the
-// level weight `om` folded into the row weights.  Out-of-bounds taps get
-// weight 0; when at least one tap is in bounds the four loads read clamped,
-// in-bounds addresses of the same level (so the zero-weight ones are
-// harmless), otherwise nothing is read.  The normalization channel of the
-// level is om (wx0 + wx1)(wy0 + wy1) over the in-bounds weights.
-struct LevelOut {
+// One mip level of one fetch, planned before any texel is read: the
+// bilinear taps (i0 + di, j0 + dj), their weights with the level weight `om`
+// folded into the row weights and zeroed for out-of-bounds taps, and four
+// clamped in-bounds texel offsets (so the loads of a partly covered level
+// are harmless for the zero-weight taps).  `act` is false when no tap is in
+// bounds; such a level is not read at all.  The level's normalization
+// channel is om (wx0 + wx1)(wy0 + wy1).
+struct LevelPlan {
+    bool act;
     int32_t i0, j0;
-    int mask;
+    int mask;  // in-bounds taps, bit 2 dj + di
+    float wx0, wx1, wy0, wy1;
+    uint32_t o00, o01, o10, o11;
 };
 
-template <int DT>
-__device__ __forceinline__ LevelOut sample_level(const char *ep, int k, int l, float om,
-                                                 const FetchSpec &fs, bool flip, float4 &Cf,
-                                                 float &Wf)
+__device__ __forceinline__ LevelPlan plan_level(int k, int l, float om, const FetchSpec &fs, bool flip)
 {
     const int m = k - l;
     const int32_t n = 1 << m;
@@ -204,44 +187,116 @@ __device__ __forceinline__ LevelOut sample_level(const char *ep, int k, int l, f
     const AxisTaps Y = axis_taps(fs.cy, fs.ny ^ flip, flip ? 1 : 0, m);
     const bool bx0 = (uint32_t)X.i0 < (uint32_t)n, bx1 = (uint32_t)(X.i0 + 1) < (uint32_t)n;
     const bool by0 = (uint32_t)Y.i0 < (uint32_t)n, by1 = (uint32_t)(Y.i0 + 1) < (uint32_t)n;
-    LevelOut o{X.i0, Y.i0,
-               (bx0 && by0 ? 1 : 0) | (bx1 && by0 ? 2 : 0) | (bx0 && by1 ? 4 : 0) |
-                   (bx1 && by1 ? 8 : 0)};
-    if ((bx0 || bx1) && (by0 || by1)) {
-        const float wx0 = bx0 ? X.w0 : 0.0f, wx1 = bx1 ? X.w1 : 0.0f;
-        const float wy0 = by0 ? om * Y.w0 : 0.0f, wy1 = by1 ? om * Y.w1 : 0.0f;
-        const int32_t ic0 = max(X.i0, 0), ic1 = min(X.i0 + 1, n - 1);
-        const int32_t jc0 = max(Y.i0, 0), jc1 = min(Y.i0 + 1, n - 1);
-        const uint32_t lo = level_offset32(k, l);
-        const uint32_t r0 = lo + (uint32_t)(jc0 << m), r1 = lo + (uint32_t)(jc1 << m);
-        constexpr int TB = TexelBytes<DT>::v;
-        const float4 t00 = load_texel<DT>(ep + (uint64_t)(r0 + ic0) * TB, 0);
-        const float4 t01 = load_texel<DT>(ep + (uint64_t)(r0 + ic1) * TB, 0);
-        const float4 t10 = load_texel<DT>(ep + (uint64_t)(r1 + ic0) * TB, 0);
-        const float4 t11 = load_texel<DT>(ep + (uint64_t)(r1 + ic1) * TB, 0);
-        const float w00 = wx0 * wy0, w01 = wx1 * wy0, w10 = wx0 * wy1, w11 = wx1 * wy1;
-        Cf.x += w00 * t00.x; Cf.y += w00 * t00.y; Cf.z += w00 * t00.z; Cf.w += w00 * t00.w;
-        Cf.x += w01 * t01.x; Cf.y += w01 * t01.y; Cf.z += w01 * t01.z; Cf.w += w01 * t01.w;
-        Cf.x += w10 * t10.x; Cf.y += w10 * t10.y; Cf.z += w10 * t10.z; Cf.w += w10 * t10.w;
-        Cf.x += w11 * t11.x; Cf.y += w11 * t11.y; Cf.z += w11 * t11.z; Cf.w += w11 * t11.w;
-        Wf += (wx0 + wx1) * (wy0 + wy1);
-    }
-    return o;
+    LevelPlan p;
+    p.act = (bx0 | bx1) & (by0 | by1);
+    p.i0 = X.i0;
+    p.j0 = Y.i0;
+    p.mask = ((bx0 & by0) ? 1 : 0) | ((bx1 & by0) ? 2 : 0) | ((bx0 & by1) ? 4 : 0) | ((bx1 & by1) ? 8 : 0);
+    p.wx0 = bx0 ? X.w0 : 0.0f;
+    p.wx1 = bx1 ? X.w1 : 0.0f;
+    p.wy0 = by0 ? om * Y.w0 : 0.0f;
+    p.wy1 = by1 ? om * Y.w1 : 0.0f;
+    const int32_t ic0 = min(max(X.i0, 0), n - 1), ic1 = min(max(X.i0 + 1, 0), n - 1);
+    const int32_t jc0 = min(max(Y.i0, 0), n - 1), jc1 = min(max(Y.i0 + 1, 0), n - 1);
+    const uint32_t lo = level_offset32(k, l);
+    const uint32_t r0 = lo + (uint32_t)(jc0 << m), r1 = lo + (uint32_t)(jc1 << m);
+    p.o00 = r0 + ic0;
+    p.o01 = r0 + ic1;
+    p.o10 = r1 + ic0;
+    p.o11 = r1 + ic1;
+    return p;
 }
 
-template <int DT, bool TRI, bool DBG>
-__global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a, int64_t nblocks_real)
+__device__ __forceinline__ void accumulate(const LevelPlan &p, const float4 &t00, const float4 &t01,
+                                           const float4 &t10, const float4 &t11, float4 &Cf,
+                                           float &Wf)
 {
-    const int64_t lb = logical_block(nblocks_real);
-    if (lb < 0) return;
-    const int64_t q = lb * kBlock + threadIdx.x;
+    const float w00 = p.wx0 * p.wy0, w01 = p.wx1 * p.wy0, w10 = p.wx0 * p.wy1, w11 = p.wx1 * p.wy1;
+    Cf.x += w00 * t00.x; Cf.y += w00 * t00.y; Cf.z += w00 * t00.z; Cf.w += w00 * t00.w;
+    Cf.x += w01 * t01.x; Cf.y += w01 * t01.y; Cf.z += w01 * t01.z; Cf.w += w01 * t01.w;
+    Cf.x += w10 * t10.x; Cf.y += w10 * t10.y; Cf.z += w10 * t10.z; Cf.w += w10 * t10.w;
+    Cf.x += w11 * t11.x; Cf.y += w11 * t11.y; Cf.z += w11 * t11.z; Cf.w += w11 * t11.w;
+    Wf += (p.wx0 + p.wx1) * (p.wy0 + p.wy1);
+}
+
+// One of Alg. 3's fetches: Texture(Edge(g), TriangleToQuadUV(g, <x, y>)),
+// colour and normalization channel.  Both mip levels are planned first and
+// read under a single branch, so their eight loads are in flight together.
+template <int DT, bool TRI, bool DBG>
+__device__ __forceinline__ void fetch(const SampleArgs &a, const Lod &L, const FetchSpec &f,
+                                      float4 &Cf, float &Wf, htex_debug_rec *d, int s)
+{
+    constexpr int TB = TexelBytes<DT>::v;
+    const int32_t g = f.g;
+    const bool flip = !(g > a.twin[g]);
+    const int32_t e = a.edge[g];
+    const int k = a.log2res[e];
+    const char *ep = static_cast<const char *>(a.texels) + a.base[e] * TB;
+    int lv[2];
+    float om[2];
+    const int nlev = fetch_levels(L, k, lv, om);
+    const LevelPlan p0 = plan_level(k, lv[0], om[0], f, flip);
+    LevelPlan p1;
+    if constexpr (TRI) {
+        p1 = plan_level(k, nlev == 2 ? lv[1] : lv[0], om[1], f, flip);
+        p1.act = p1.act & (nlev == 2);
+    }
+    if (p0.act | (TRI && p1.act)) {
+        const float4 t00 = load_texel<DT>(ep + (uint64_t)p0.o00 * TB, 0);
+        const float4 t01 = load_texel<DT>(ep + (uint64_t)p0.o01 * TB, 0);
+        const float4 t10 = load_texel<DT>(ep + (uint64_t)p0.o10 * TB, 0);
+        const float4 t11 = load_texel<DT>(ep + (uint64_t)p0.o11 * TB, 0);
+        if constexpr (TRI) {
+            const float4 u00 = load_texel<DT>(ep + (uint64_t)p1.o00 * TB, 0);
+            const float4 u01 = load_texel<DT>(ep + (uint64_t)p1.o01 * TB, 0);
+            const float4 u10 = load_texel<DT>(ep + (uint64_t)p1.o10 * TB, 0);
+            const float4 u11 = load_texel<DT>(ep + (uint64_t)p1.o11 * TB, 0);
+            if (p0.act) accumulate(p0, t00, t01, t10, t11, Cf, Wf);
+            if (p1.act) accumulate(p1, u00, u01, u10, u11, Cf, Wf);
+        } else {
+            accumulate(p0, t00, t01, t10, t11, Cf, Wf);
+        }
+        if constexpr (DT == HTEX_FP8_E4M3) {
+            const float sc = a.scale[e];
+            Cf.x *= sc;
+            Cf.y *= sc;
+            Cf.z *= sc;
+            Cf.w *= sc;
+        }
+    }
+    if constexpr (DBG) {
+        d->edge[s] = e;
+        d->flip[s] = flip ? 1 : 0;
+        d->level[s][0] = lv[0];
+        d->level[s][1] = lv[1];
+        d->i0[s][0] = p0.i0;
+        d->j0[s][0] = p0.j0;
+        d->inb[s][0] = p0.mask;
+        if (TRI && nlev == 2) {
+            d->i0[s][1] = p1.i0;
+            d->j0[s][1] = p1.j0;
+            d->inb[s][1] = p1.mask;
+        }
+        d->wf[s] = Wf;
+    }
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int DT, bool TRI, bool DBG>
+__global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q >= a.Q) return;
-    const int32_t h = a.qh[q];
-    const float u = a.qu[q], v = a.qv[q];
-    float4 *out4 = reinterpret_cast<float4 *>(a.out);
+    // queries and results stream through once: keep them out of the caches
+    const int32_t h = __builtin_nontemporal_load(a.qh + q);
+    const float u = __builtin_nontemporal_load(a.qu + q);
+    const float v = __builtin_nontemporal_load(a.qv + q);
+    f32x4 *out4 = reinterpret_cast<f32x4 *>(a.out);
     if (!((uint32_t)h < (uint32_t)a.H) || !isfinite(u) || !isfinite(v)) {
         const float nan = __uint_as_float(0x7fc00000u);
-        out4[q] = make_float4(nan, nan, nan, nan);
+        const f32x4 nv = {nan, nan, nan, nan};
+        __builtin_nontemporal_store(nv, out4 + q);
         if (a.err) atomicAdd(a.err, 1);
         if constexpr (DBG) {
             htex_debug_rec d = {};
@@ -256,11 +311,9 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a, int64_t nblocks
     }
     const int32_t n1 = a.next[h], p1 = a.prev[h];
     Lod L{0, 0, 0.0f, 1.0f};
-    if constexpr (TRI) L = lod_of(a.qf[q]);
+    if constexpr (TRI) L = lod_of(__builtin_nontemporal_load(a.qf + q));
     FetchSpec fs[3];
     fetch_specs(h, n1, p1, u, v, fs);
-    float4 C = make_float4(0.f, 0.f, 0.f, 0.f);
-    float W = 0.0f;
     htex_debug_rec d;
     if constexpr (DBG) {
         d = {};
@@ -268,53 +321,23 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a, int64_t nblocks
         d.prev = p1;
         d.phi = L.phi;
     }
-    constexpr int TB = TexelBytes<DT>::v;
-    const char *tex = static_cast<const char *>(a.texels);
+    // Alg. 3: c <- c + Texture(...) for the own quad, then Next, then Prev
+    float4 C = make_float4(0.f, 0.f, 0.f, 0.f);
+    float W = 0.0f;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-        const int32_t g = fs[s].g;
-        const bool flip = !(g > a.twin[g]);
-        const int32_t e = a.edge[g];
-        const int k = a.log2res[e];
-        const char *ep = tex + a.base[e] * TB;
-        int lv[2];
-        float om[2];
-        const int nlev = fetch_levels(L, k, lv, om);
         float4 Cf = make_float4(0.f, 0.f, 0.f, 0.f);
         float Wf = 0.0f;
-        const LevelOut o0 = sample_level<DT>(ep, k, lv[0], om[0], fs[s], flip, Cf, Wf);
-        LevelOut o1{0, 0, 0};
-        if (TRI && nlev == 2) o1 = sample_level<DT>(ep, k, lv[1], om[1], fs[s], flip, Cf, Wf);
-        if constexpr (DT == HTEX_FP8_E4M3) {
-            const float sc = a.scale[e];
-            Cf.x *= sc;
-            Cf.y *= sc;
-            Cf.z *= sc;
-            Cf.w *= sc;
-        }
+        fetch<DT, TRI, DBG>(a, L, fs[s], Cf, Wf, &d, s);
         C.x += Cf.x;
         C.y += Cf.y;
         C.z += Cf.z;
         C.w += Cf.w;
         W += Wf;
-        if constexpr (DBG) {
-            d.edge[s] = e;
-            d.flip[s] = flip ? 1 : 0;
-            d.level[s][0] = lv[0];
-            d.level[s][1] = lv[1];
-            d.i0[s][0] = o0.i0;
-            d.j0[s][0] = o0.j0;
-            d.inb[s][0] = o0.mask;
-            if (nlev == 2) {
-                d.i0[s][1] = o1.i0;
-                d.j0[s][1] = o1.j0;
-                d.inb[s][1] = o1.mask;
-            }
-            d.wf[s] = Wf;
-        }
     }
     const float r = __builtin_amdgcn_rcpf(W);
-    out4[q] = make_float4(C.x * r, C.y * r, C.z * r, C.w * r);
+    const f32x4 ov = {C.x * r, C.y * r, C.z * r, C.w * r};
+    __builtin_nontemporal_store(ov, out4 + q);
     if constexpr (DBG) {
         d.W = W;
         a.dbg[q] = d;
@@ -325,11 +348,9 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a, int64_t nblocks
 // receives (om w / W) dL/dout_c.  First the normalization W (weights only,
 // no texel reads), then the scatter with float32 atomics.
 template <bool TRI>
-__global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a, int64_t nblocks_real)
+__global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
 {
-    const int64_t lb = logical_block(nblocks_real);
-    if (lb < 0) return;
-    const int64_t q = lb * kBlock + threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q >= a.Q) return;
     const int32_t h = a.qh[q];
     const float u = a.qu[q], v = a.qv[q];
@@ -400,12 +421,11 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 template <int DT, bool TRI>
 hipError_t launch_fwd(const SampleArgs &a, hipStream_t s)
 {
-    const int64_t nb = ceil_div(a.Q, kBlock);
-    const int64_t G = ceil_div(nb, 8) * 8;
+    const uint32_t G = (uint32_t)ceil_div(a.Q, kBlock);
     if (a.dbg)
-        hipLaunchKernelGGL((k_sample<DT, TRI, true>), dim3((uint32_t)G), dim3(kBlock), 0, s, a, nb);
+        hipLaunchKernelGGL((k_sample<DT, TRI, true>), dim3(G), dim3(kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL((k_sample<DT, TRI, false>), dim3((uint32_t)G), dim3(kBlock), 0, s, a, nb);
+        hipLaunchKernelGGL((k_sample<DT, TRI, false>), dim3(G), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
@@ -425,12 +445,11 @@ hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t
 hipError_t launch_backward(const SampleArgs &a, int filter, hipStream_t s)
 {
     if (a.Q == 0) return hipSuccess;
-    const int64_t nb = ceil_div(a.Q, kBlock);
-    const int64_t G = ceil_div(nb, 8) * 8;
+    const uint32_t G = (uint32_t)ceil_div(a.Q, kBlock);
     if (filter == HTEX_TRILINEAR)
-        hipLaunchKernelGGL((k_backward<true>), dim3((uint32_t)G), dim3(kBlock), 0, s, a, nb);
+        hipLaunchKernelGGL((k_backward<true>), dim3(G), dim3(kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL((k_backward<false>), dim3((uint32_t)G), dim3(kBlock), 0, s, a, nb);
+        hipLaunchKernelGGL((k_backward<false>), dim3(G), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
