@@ -116,9 +116,9 @@ def algorithmic_bytes(dbg, h, log2res, base, total, Q):
                     idx = eb + lofs + (j0 + dj) * n + (i0 + di)
                     mark[idx[ok]] = True
     texels = int(np.count_nonzero(mark))
-    seg = np.zeros((total + 3) // 4, dtype=np.bool_)
-    seg[np.nonzero(mark)[0] >> 2] = True
-    segments = int(np.count_nonzero(seg))
+    nz = np.nonzero(mark)[0]
+    segments = int(len(np.unique(nz >> 2)))      # 64-byte segments
+    lines128 = int(len(np.unique(nz >> 3)))      # 128-byte lines
     # Next/Prev of each distinct h; Twin/Edge of each distinct h, Next h, Prev h;
     # log2res/base of each distinct edge
     n_h = len(np.unique(h))
@@ -128,8 +128,9 @@ def algorithmic_bytes(dbg, h, log2res, base, total, Q):
     total_bytes = 16 * Q + 16 * Q + topo + 16 * texels
     return {"bytes": int(total_bytes), "bytes_per_query": total_bytes / Q,
             "texel_bytes_per_query": 16 * texels / Q, "unique_texels": texels,
-            "unique_64B_segments": segments,
-            "segment_bytes_per_query": (32 * Q + topo + 64 * segments) / Q}
+            "unique_64B_segments": segments, "unique_128B_lines": lines128,
+            "segment_bytes_per_query": (32 * Q + topo + 64 * segments) / Q,
+            "line128_bytes_per_query": (32 * Q + topo + 128 * lines128) / Q}
 
 
 # ----------------------------------------------------------- CPU oracle --
@@ -222,6 +223,8 @@ def main():
     htex.htex_build_mips(pool)
     torch.cuda.synchronize()
     log(f"pool {pool.nbytes() / 1e9:.2f} GB filled + mips ({time.perf_counter() - t_start:.1f}s)")
+    prep = htex.Prepared(dmesh, pool)       # per (mesh, pool layout), like the mips
+    torch.cuda.synchronize()
     dev_batches = [to_dev(b) for b in batches]
     Q = batches[0].Q
     out = torch.empty((Q, 4), dtype=torch.float32, device="cuda")
@@ -236,8 +239,8 @@ def main():
 
     def step(i, p=pool, bs=dev_batches):
         h, u, v, f = bs[i % len(bs)]
-        htex.htex_sample(dmesh, p, h, u, v, f, filter=htex.HTEX_TRILINEAR,
-                         flags=htex.HTEX_QUERIES_SORTED, out=out)
+        htex.htex_sample_prepared(prep, p, h, u, v, f, filter=htex.HTEX_TRILINEAR,
+                                  flags=htex.HTEX_QUERIES_SORTED, out=out)
 
     for i in range(args.warmup):
         step(i)
@@ -295,11 +298,13 @@ def main():
         traffic = recorded_traffic()
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                    "kernel": "htex::k_sample<f32,trilinear>",
+                    "kernel": "htex::k_sample_prep<f32,trilinear>",
                     "avg_kernel_us": avg_kernel_s * 1e6,
                     "alg_bytes_per_query": alg["bytes_per_query"],
                     "alg_texel_bytes_per_query": alg["texel_bytes_per_query"],
-                    "segment64_bytes_per_query": alg["segment_bytes_per_query"]}
+                    "segment64_bytes_per_query": alg["segment_bytes_per_query"],
+                    "line128_bytes_per_query": alg["line128_bytes_per_query"],
+                    "unique_128B_texel_lines": alg["unique_128B_lines"]}
         log(f"algorithmic bytes/query {alg['bytes_per_query']:.1f} "
             f"(texels {alg['texel_bytes_per_query']:.1f}); achieved {achieved:.0f} GB/s")
 

@@ -192,6 +192,32 @@ htex_status htex_sample_backward(const htex_mesh *mesh, const htex_pool *pool,
                                  uint32_t flags, const float *dout, float *dtexels,
                                  void *stream);
 
+/* Prepared fetch descriptors: the halfedge navigation of Alg. 3 resolved
+ * once per (mesh, pool) so that a query reads one record instead of walking
+ * Next/Prev/Twin/Edge and the edge table.  Record h (HTEX_PREP_BYTES bytes,
+ * 16-byte aligned, layout private to the library) holds, for each of the
+ * three fetches of halfedge h (own quad, Next(h), Prev(h)), the edge, the texture
+ * base, its log2 resolution and the reflection bit of Alg. 2, plus Next(h)
+ * and Prev(h).  It depends on the mesh and on the pool's log2res/base (not
+ * on the texels: a quantized copy with the same layout shares it); rebuild
+ * it when either changes.  Requires total_texels < 2^40. */
+#define HTEX_PREP_BYTES 48
+
+/* Writes H descriptor records to `prep` (device, caller-allocated, H *
+ * HTEX_PREP_BYTES bytes, 16-byte aligned).  Trusts the mesh (validate it
+ * first). */
+htex_status htex_prepare(const htex_mesh *mesh, const htex_pool *pool, void *prep,
+                         void *stream);
+
+/* Same result as htex_sample (bit for bit) from prepared descriptors: the
+ * fast path for repeated sampling of one mesh.  `H` is the number of
+ * halfedges the records cover (queries with h outside [0, H) are invalid as
+ * in htex_sample).  No debug trace. */
+htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *pool,
+                                 const htex_queries *queries, int32_t filter,
+                                 uint32_t flags, float *out, int32_t *err_count,
+                                 void *stream);
+
 #ifdef __cplusplus
 }
 #endif

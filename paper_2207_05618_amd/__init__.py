@@ -19,6 +19,7 @@ from ._lib import (DEBUG_FIELDS, HTEX_BF16, HTEX_BILINEAR, HTEX_F32, HTEX_FP8_E4
 
 __all__ = ["Mesh", "Pool", "htex_pool_layout", "htex_mesh_validate", "htex_build_mips",
            "htex_quantize", "htex_sample", "htex_sample_backward", "HtexSample",
+           "htex_prepare", "htex_sample_prepared", "Prepared",
            "debug_records", "HtexError"]
 
 DEBUG_DTYPE = np.dtype(DEBUG_FIELDS)
@@ -162,6 +163,38 @@ def htex_sample(mesh: Mesh, pool: Pool, h, u, v, footprint=None, filter=HTEX_BIL
                              err_count.data_ptr() if err_count is not None else None,
                              _stream(stream)))
     return out, dbg
+
+
+class Prepared:
+    """Per-halfedge fetch records of one (mesh, pool layout) pair (device)."""
+
+    def __init__(self, mesh: Mesh, pool: Pool, stream=None):
+        self.H = mesh.H
+        n = max(mesh.H, 1) * _lib.HTEX_PREP_BYTES // 16
+        self.buf = torch.empty((n, 4), dtype=torch.int32, device=mesh.twin.device)
+        htex_prepare(mesh, pool, self, stream)
+
+
+def htex_prepare(mesh: Mesh, pool: Pool, prep: "Prepared", stream=None):
+    check(load().htex_prepare(C.byref(mesh.c), C.byref(pool.c), prep.buf.data_ptr(),
+                              _stream(stream)))
+
+
+def htex_sample_prepared(prep: "Prepared", pool: Pool, h, u, v, footprint=None,
+                         filter=HTEX_BILINEAR, flags=0, out=None, err_count=None,
+                         stream=None):
+    """htex_sample from prepared records (bit-identical results) -> out [Q, 4]."""
+    q, Q = _queries(h, u, v, footprint)
+    if out is None:
+        out = torch.empty((Q, 4), dtype=torch.float32, device=h.device)
+    _dev(out, torch.float32, "out")
+    if err_count is not None:
+        _dev(err_count, torch.int32, "err_count")
+    check(load().htex_sample_prepared(prep.H, prep.buf.data_ptr(), C.byref(pool.c), C.byref(q),
+                                      int(filter), int(flags), out.data_ptr(),
+                                      err_count.data_ptr() if err_count is not None else None,
+                                      _stream(stream)))
+    return out
 
 
 def debug_records(dbg: torch.Tensor) -> np.ndarray:

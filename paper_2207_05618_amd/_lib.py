@@ -59,7 +59,11 @@ SIGNATURES = {
     "htex_quantize": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
     "htex_sample": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_uint32, _P, _P, _P, _P]),
     "htex_sample_backward": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_uint32, _P, _P, _P]),
+    "htex_prepare": (C.c_int32, [_P, _P, _P, _P]),
+    "htex_sample_prepared": (C.c_int32, [C.c_int32, _P, _P, _P, C.c_int32, C.c_uint32, _P, _P,
+                                         _P]),
 }
+HTEX_PREP_BYTES = 48
 
 _lib = None
 

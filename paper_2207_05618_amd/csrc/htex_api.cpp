@@ -270,4 +270,51 @@ htex_status htex_sample_backward(const htex_mesh *mesh, const htex_pool *pool,
                     "backward launch");
 }
 
+htex_status htex_prepare(const htex_mesh *mesh, const htex_pool *pool, void *prep, void *stream)
+{
+    htex_status st = check_mesh(mesh);
+    if (!st) st = check_pool(pool, mesh);
+    if (st) return st;
+    if (pool->total_texels >= (int64_t(1) << 40))
+        return fail(HTEX_E_RANGE, "prepared records address pools below 2^40 texels");
+    if (mesh->H > 0 && (!prep || !aligned(prep, 16)))
+        return fail(HTEX_E_ARG, "prep must be non-NULL and 16-byte aligned");
+    htex_queries none{};
+    htex::SampleArgs a = make_args(mesh, pool, &none);
+    return from_hip(htex::launch_prepare(a, prep, static_cast<hipStream_t>(stream)), "prepare launch");
+}
+
+htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *pool,
+                                 const htex_queries *queries, int32_t filter, uint32_t flags,
+                                 float *out, int32_t *err_count, void *stream)
+{
+    htex_status st = check_pool(pool, nullptr);
+    if (!st) st = check_queries(queries, filter);
+    if (st) return st;
+    if (H < 0) return fail(HTEX_E_ARG, "negative H");
+    if (flags & ~HTEX_QUERIES_SORTED) return fail(HTEX_E_ARG, "unknown flags 0x%x", flags);
+    if (filter == HTEX_TRILINEAR && !pool->has_mips)
+        return fail(HTEX_E_ARG, "trilinear filtering needs a pool with mips");
+    if (queries->Q > 0) {
+        if (H == 0) return fail(HTEX_E_ARG, "queries on an empty mesh");
+        if (!prep || !aligned(prep, 16)) return fail(HTEX_E_ARG, "prep must be 16-byte aligned");
+        if (!out || !aligned(out, 16)) return fail(HTEX_E_ARG, "out must be 16-byte aligned");
+    }
+    htex::SampleArgs a{};
+    a.H = H;
+    a.texels = pool->texels;
+    a.scale = pool->scale;
+    a.Q = queries->Q;
+    a.qh = queries->h;
+    a.qu = queries->u;
+    a.qv = queries->v;
+    a.qf = queries->footprint;
+    a.out = out;
+    a.err = err_count;
+    a.prep = prep;
+    return from_hip(htex::launch_sample_prepared(a, pool->dtype, filter,
+                                                 static_cast<hipStream_t>(stream)),
+                    "prepared sample launch");
+}
+
 }  // extern "C"

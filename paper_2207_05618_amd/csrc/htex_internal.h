@@ -25,6 +25,7 @@ struct SampleArgs {
     int32_t *err;               // forward, nullable
     const float *dout;          // backward: [Q][4]
     float *dtex;                // backward: pool-shaped float32
+    const void *prep;           // prepared descriptors (fast path), nullable
 };
 
 // Offset of mip level l inside an edge of log2 resolution k, in texels:
@@ -37,6 +38,8 @@ __host__ __device__ inline int64_t level_offset(int k, int l)
 
 hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t s);
 hipError_t launch_backward(const SampleArgs &a, int filter, hipStream_t s);
+hipError_t launch_prepare(const SampleArgs &a, void *prep, hipStream_t s);
+hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, hipStream_t s);
 hipError_t launch_build_mips(float *texels, const uint8_t *log2res, const int64_t *base,
                              int32_t E, int max_k, hipStream_t s);
 hipError_t launch_quantize_bf16(const float *src, uint16_t *dst, int64_t count,

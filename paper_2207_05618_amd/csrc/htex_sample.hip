@@ -219,19 +219,38 @@ __device__ __forceinline__ void accumulate(const LevelPlan &p, const float4 &t00
     Wf += (p.wx0 + p.wx1) * (p.wy0 + p.wy1);
 }
 
+// A fetch with its halfedge resolved: the quad's edge e, its log2
+// resolution k, the reflection of Alg. 2 and the address of its level 0.
+struct Resolved {
+    int32_t e;
+    int k;
+    bool flip;
+    const char *ep;
+};
+
+template <int DT>
+__device__ __forceinline__ Resolved resolve_plain(const SampleArgs &a, int32_t g)
+{
+    Resolved r;
+    r.flip = !(g > a.twin[g]);
+    r.e = a.edge[g];
+    r.k = a.log2res[r.e];
+    r.ep = static_cast<const char *>(a.texels) + a.base[r.e] * TexelBytes<DT>::v;
+    return r;
+}
+
 // One of Alg. 3's fetches: Texture(Edge(g), TriangleToQuadUV(g, <x, y>)),
 // colour and normalization channel.  Both mip levels are planned first and
 // read under a single branch, so their eight loads are in flight together.
 template <int DT, bool TRI, bool DBG>
 __device__ __forceinline__ void fetch(const SampleArgs &a, const Lod &L, const FetchSpec &f,
-                                      float4 &Cf, float &Wf, htex_debug_rec *d, int s)
+                                      const Resolved &R, float4 &Cf, float &Wf,
+                                      htex_debug_rec *d, int s)
 {
     constexpr int TB = TexelBytes<DT>::v;
-    const int32_t g = f.g;
-    const bool flip = !(g > a.twin[g]);
-    const int32_t e = a.edge[g];
-    const int k = a.log2res[e];
-    const char *ep = static_cast<const char *>(a.texels) + a.base[e] * TB;
+    const int k = R.k;
+    const bool flip = R.flip;
+    const char *ep = R.ep;
     int lv[2];
     float om[2];
     const int nlev = fetch_levels(L, k, lv, om);
@@ -257,7 +276,7 @@ __device__ __forceinline__ void fetch(const SampleArgs &a, const Lod &L, const F
             accumulate(p0, t00, t01, t10, t11, Cf, Wf);
         }
         if constexpr (DT == HTEX_FP8_E4M3) {
-            const float sc = a.scale[e];
+            const float sc = a.scale[R.e];
             Cf.x *= sc;
             Cf.y *= sc;
             Cf.z *= sc;
@@ -265,7 +284,7 @@ __device__ __forceinline__ void fetch(const SampleArgs &a, const Lod &L, const F
         }
     }
     if constexpr (DBG) {
-        d->edge[s] = e;
+        d->edge[s] = R.e;
         d->flip[s] = flip ? 1 : 0;
         d->level[s][0] = lv[0];
         d->level[s][1] = lv[1];
@@ -279,6 +298,26 @@ __device__ __forceinline__ void fetch(const SampleArgs &a, const Lod &L, const F
         }
         d->wf[s] = Wf;
     }
+}
+
+// Prepared record of halfedge h: for its three fetches the packed word
+// base | k << 40 | flip << 45 and the edge id, then Next(h) and Prev(h).
+struct alignas(16) PrepRec {
+    uint64_t w[3];
+    int32_t e[3];
+    int32_t next, prev, pad;
+};
+static_assert(sizeof(PrepRec) == HTEX_PREP_BYTES, "record size");
+
+template <int DT>
+__device__ __forceinline__ Resolved resolve_prepared(const SampleArgs &a, uint64_t w, int32_t e)
+{
+    Resolved r;
+    r.e = e;
+    r.k = (int)((w >> 40) & 31u);
+    r.flip = ((w >> 45) & 1u) != 0;
+    r.ep = static_cast<const char *>(a.texels) + (int64_t)(w & 0xffffffffffull) * TexelBytes<DT>::v;
+    return r;
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -328,7 +367,7 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a)
     for (int s = 0; s < 3; ++s) {
         float4 Cf = make_float4(0.f, 0.f, 0.f, 0.f);
         float Wf = 0.0f;
-        fetch<DT, TRI, DBG>(a, L, fs[s], Cf, Wf, &d, s);
+        fetch<DT, TRI, DBG>(a, L, fs[s], resolve_plain<DT>(a, fs[s].g), Cf, Wf, &d, s);
         C.x += Cf.x;
         C.y += Cf.y;
         C.z += Cf.z;
@@ -342,6 +381,69 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a)
         d.W = W;
         a.dbg[q] = d;
     }
+}
+
+// Fast path: the same arithmetic as k_sample with the navigation read from
+// one prepared record per query (bit-identical results).
+template <int DT, bool TRI>
+__global__ void __launch_bounds__(kBlock) k_sample_prep(SampleArgs a)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= a.Q) return;
+    const int32_t h = __builtin_nontemporal_load(a.qh + q);
+    const float u = __builtin_nontemporal_load(a.qu + q);
+    const float v = __builtin_nontemporal_load(a.qv + q);
+    f32x4 *out4 = reinterpret_cast<f32x4 *>(a.out);
+    if (!((uint32_t)h < (uint32_t)a.H) || !isfinite(u) || !isfinite(v)) {
+        const float nan = __uint_as_float(0x7fc00000u);
+        const f32x4 nv = {nan, nan, nan, nan};
+        __builtin_nontemporal_store(nv, out4 + q);
+        if (a.err) atomicAdd(a.err, 1);
+        return;
+    }
+    const PrepRec rec = static_cast<const PrepRec *>(a.prep)[h];
+    Lod L{0, 0, 0.0f, 1.0f};
+    if constexpr (TRI) L = lod_of(__builtin_nontemporal_load(a.qf + q));
+    FetchSpec fs[3];
+    fetch_specs(h, rec.next, rec.prev, u, v, fs);
+    float4 C = make_float4(0.f, 0.f, 0.f, 0.f);
+    float W = 0.0f;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        float4 Cf = make_float4(0.f, 0.f, 0.f, 0.f);
+        float Wf = 0.0f;
+        fetch<DT, TRI, false>(a, L, fs[s], resolve_prepared<DT>(a, rec.w[s], rec.e[s]), Cf, Wf,
+                              nullptr, s);
+        C.x += Cf.x;
+        C.y += Cf.y;
+        C.z += Cf.z;
+        C.w += Cf.w;
+        W += Wf;
+    }
+    const float r = __builtin_amdgcn_rcpf(W);
+    const f32x4 ov = {C.x * r, C.y * r, C.z * r, C.w * r};
+    __builtin_nontemporal_store(ov, out4 + q);
+}
+
+// One record per halfedge: resolve Next/Prev, the edges, reflections,
+// resolutions and texture bases of its three fetches.
+__global__ void __launch_bounds__(kBlock) k_prepare(SampleArgs a, PrepRec *out)
+{
+    const int64_t h = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (h >= a.H) return;
+    PrepRec r;
+    r.next = a.next[h];
+    r.prev = a.prev[h];
+    r.pad = 0;
+    const int32_t g[3] = {(int32_t)h, r.next, r.prev};
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const bool flip = !(g[s] > a.twin[g[s]]);
+        const int32_t e = a.edge[g[s]];
+        r.e[s] = e;
+        r.w[s] = (uint64_t)a.base[e] | ((uint64_t)a.log2res[e] << 40) | ((uint64_t)(flip ? 1 : 0) << 45);
+    }
+    out[h] = r;
 }
 
 // Backward: out_c = sum over taps (om w / W) T_c, so dL/dT_c at each tap
@@ -429,7 +531,34 @@ hipError_t launch_fwd(const SampleArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int DT, bool TRI>
+hipError_t launch_fwd_prep(const SampleArgs &a, hipStream_t s)
+{
+    const uint32_t G = (uint32_t)ceil_div(a.Q, kBlock);
+    hipLaunchKernelGGL((k_sample_prep<DT, TRI>), dim3(G), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_prepare(const SampleArgs &a, void *prep, hipStream_t s)
+{
+    if (a.H == 0) return hipSuccess;
+    const uint32_t G = (uint32_t)ceil_div(a.H, kBlock);
+    hipLaunchKernelGGL(k_prepare, dim3(G), dim3(kBlock), 0, s, a, static_cast<PrepRec *>(prep));
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, hipStream_t s)
+{
+    if (a.Q == 0) return hipSuccess;
+    const bool tri = filter == HTEX_TRILINEAR;
+    switch (dtype) {
+    case HTEX_F32: return tri ? launch_fwd_prep<HTEX_F32, true>(a, s) : launch_fwd_prep<HTEX_F32, false>(a, s);
+    case HTEX_BF16: return tri ? launch_fwd_prep<HTEX_BF16, true>(a, s) : launch_fwd_prep<HTEX_BF16, false>(a, s);
+    default: return tri ? launch_fwd_prep<HTEX_FP8_E4M3, true>(a, s) : launch_fwd_prep<HTEX_FP8_E4M3, false>(a, s);
+    }
+}
 
 hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t s)
 {

@@ -100,6 +100,17 @@ def test_frame_unsorted_equals_sorted(frame):
     np.testing.assert_array_equal(o2.cpu().numpy(), out[perm])
 
 
+def test_frame_prepared_equals_plain(frame):
+    """The prepared fast path (what the benchmark times) gives the plain
+    path's bits on the whole frame."""
+    mesh, lr, pool, dm, q, out = frame
+    prep = htex.Prepared(dm, pool)
+    o2 = htex.htex_sample_prepared(prep, pool, t(q.h), t(q.u), t(q.v), t(q.f),
+                                   filter=htex.HTEX_TRILINEAR, flags=htex.HTEX_QUERIES_SORTED)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(o2.cpu().numpy(), out)
+
+
 def test_frame_quantized_error_bounds(frame):
     """BF16 and FP8 storage of the full pool: sampled error against the
     oracle on the float32 texels within 4e-3 and 6e-2 relative."""

@@ -401,3 +401,43 @@ def test_mesh_validate_on_gpu():
         rc, obad = oracle.validate(oracle.Mesh(tw, nx, pv, ed, m.E))
         assert not ok and rc != 0
         assert bad >= 0
+
+
+# ------------------------------------------------------ prepared records -
+
+@pytest.mark.parametrize("mesh_i", [0, 1, 2, 3])
+@pytest.mark.parametrize("dtype", [htex.HTEX_F32, htex.HTEX_BF16, htex.HTEX_FP8_E4M3])
+def test_prepared_path_is_bit_identical(mesh_i, dtype):
+    """htex_sample_prepared reads the navigation from per-halfedge records;
+    its results must equal htex_sample's bit for bit (and so the oracle's to
+    the same tolerance), for every storage type and filter, including
+    invalid queries."""
+    m = tiny_meshes()[mesh_i]
+    rng = np.random.default_rng(70 + mesh_i)
+    s = Setup(m, rng.integers(0, 7, m.E), has_mips=True, kind=1)
+    pool = s.pool if dtype == htex.HTEX_F32 else htex.htex_quantize(s.pool, dtype)
+    prep = htex.Prepared(s.dmesh, pool)
+    q = uniform_queries(m.H, 9001, 71 + mesh_i, log2f=(-9, 1.5))
+    q.h[:5] = [-1, m.H, 0, 1, 2]
+    q.u[2] = np.nan
+    q.v[3] = np.inf
+    for filt in (htex.HTEX_BILINEAR, htex.HTEX_TRILINEAR):
+        a, _ = s.gpu(q, filt, pool=pool)
+        err = torch.zeros(1, dtype=torch.int32, device="cuda")
+        b = htex.htex_sample_prepared(prep, pool, t(q.h), t(q.u), t(q.v), t(q.f), filter=filt,
+                                      err_count=err)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(b.cpu().numpy(), a)
+        assert int(err.item()) == 4
+
+
+@pytest.mark.parametrize("Q", [0, 1, 255, 257])
+def test_prepared_ragged(cfg1, Q):
+    prep = htex.Prepared(cfg1.dmesh, cfg1.pool)
+    q = uniform_queries(cfg1.m.H, Q, 500 + Q)
+    b = htex.htex_sample_prepared(prep, cfg1.pool, t(q.h), t(q.u), t(q.v))
+    torch.cuda.synchronize()
+    assert b.shape == (Q, 4)
+    if Q:
+        ref, _, _ = cfg1.ref(q)
+        assert_rel(b.cpu().numpy(), ref, TOL)
