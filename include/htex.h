@@ -218,6 +218,77 @@ htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *p
                                  uint32_t flags, float *out, int32_t *err_count,
                                  void *stream);
 
+/* ------------------------------------------------------------- serving --
+ * A continuous-batching server over resident meshes.  Requests (a mesh id
+ * and a batch of queries in host memory) are admitted in arrival order as
+ * request slots and device memory (an arena of arena_bytes, 32 bytes per
+ * query) free up; admitted requests are copied to the device and gathered
+ * into batches, each computed by one launch over a list of 256-query tiles
+ * that mixes requests and meshes; up to compute_streams launches run at
+ * once, and requests arriving meanwhile join the next batch.  Results are
+ * copied back into the caller's host buffer; a request is complete when its
+ * result is in host memory.  Every query is computed by the same device code
+ * as htex_sample_prepared, so results are identical alone and in any mix.
+ * A scheduler thread inside the library drives the device; the calls below
+ * are thread-safe.  Not part of the paper (which renders frames); this is
+ * the batched serving form of its sampling. */
+typedef struct htex_server htex_server;
+
+typedef struct htex_server_config {
+    int32_t dtype;            /* texel storage of every mesh                   */
+    int32_t filter;           /* HTEX_BILINEAR or HTEX_TRILINEAR              */
+    int32_t max_inflight;     /* request slots (admitted, not yet complete)    */
+    int32_t compute_streams;  /* concurrent batch launches, 1..4               */
+    int64_t arena_bytes;      /* device bytes for request buffers (> 0)        */
+    int64_t max_batch_queries;/* queries gathered into one launch (> 0)        */
+    int32_t grid_blocks;      /* blocks per launch; 0 = 4 per compute unit     */
+    int32_t max_meshes;       /* resident meshes (> 0)                         */
+} htex_server_config;
+
+typedef struct htex_server_stats {
+    int64_t submitted, completed, rejected;
+    int64_t batches, queries_done;
+    int64_t arena_peak_bytes;
+    int32_t invalid_queries;  /* queries answered with NaN (bad h or u, v)     */
+    int32_t pad;
+} htex_server_stats;
+
+/* Creates a server on the current device; allocates the arena and staging
+ * buffers.  *out receives the handle. */
+htex_status htex_server_create(const htex_server_config *cfg, htex_server **out);
+
+/* Registers a resident mesh: its prepared records (htex_prepare, H records)
+ * and its pool (dtype must match the server's; trilinear needs mips).  The
+ * device memory stays owned by the caller and must outlive the server.  Up
+ * to max_meshes calls; *mesh_id receives 0, 1, ... */
+htex_status htex_server_add_mesh(htex_server *srv, int32_t H, const void *prep,
+                                 const htex_pool *pool, int32_t *mesh_id);
+
+/* Queues a request of Q queries on mesh `mesh_id`: h, u, v (and footprint
+ * for trilinear) are HOST arrays of Q entries, out a HOST array of Q x 4
+ * floats; all must stay valid until the request completes (page-locked
+ * memory gives asynchronous copies).  Never blocks.  Returns HTEX_E_NOMEM
+ * if the request alone exceeds the arena, HTEX_E_ARG for a bad mesh id or
+ * pointer.  *request_id receives a number increasing from 0. */
+htex_status htex_server_submit(htex_server *srv, int32_t mesh_id, int64_t Q, const int32_t *h,
+                               const float *u, const float *v, const float *footprint,
+                               float *out, int64_t *request_id);
+
+/* Non-blocking: moves up to `max` completed requests into ids[] and their
+ * latency (seconds from submit to result in host memory) into latency_s[];
+ * *n receives the count. */
+htex_status htex_server_poll(htex_server *srv, int32_t max, int64_t *ids, double *latency_s,
+                             int32_t *n);
+
+/* Waits until every submitted request is complete (HTEX_E_BUSY after
+ * timeout_s seconds). */
+htex_status htex_server_drain(htex_server *srv, double timeout_s);
+
+htex_status htex_server_stats_get(htex_server *srv, htex_server_stats *stats);
+
+/* Finishes outstanding work, stops the scheduler and frees the server. */
+htex_status htex_server_destroy(htex_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

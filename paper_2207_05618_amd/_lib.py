@@ -65,6 +65,31 @@ SIGNATURES = {
 }
 HTEX_PREP_BYTES = 48
 
+
+class htex_server_config(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("filter", C.c_int32), ("max_inflight", C.c_int32),
+                ("compute_streams", C.c_int32), ("arena_bytes", C.c_int64),
+                ("max_batch_queries", C.c_int64), ("grid_blocks", C.c_int32),
+                ("max_meshes", C.c_int32)]
+
+
+class htex_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
+                ("batches", C.c_int64), ("queries_done", C.c_int64),
+                ("arena_peak_bytes", C.c_int64), ("invalid_queries", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+SIGNATURES.update({
+    "htex_server_create": (C.c_int32, [_P, _P]),
+    "htex_server_add_mesh": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
+    "htex_server_submit": (C.c_int32, [_P, C.c_int32, C.c_int64, _P, _P, _P, _P, _P, _P]),
+    "htex_server_poll": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
+    "htex_server_drain": (C.c_int32, [_P, C.c_double]),
+    "htex_server_stats_get": (C.c_int32, [_P, _P]),
+    "htex_server_destroy": (C.c_int32, [_P]),
+})
+
 _lib = None
 
 

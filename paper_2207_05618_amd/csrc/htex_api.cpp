@@ -12,10 +12,12 @@
 #include "htex_internal.h"
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-htex_status fail(htex_status st, const char *fmt, ...)
+namespace htex {
+
+htex_status set_error(htex_status st, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -26,9 +28,17 @@ htex_status fail(htex_status st, const char *fmt, ...)
     return st;
 }
 
+void clear_error() { g_last_error.clear(); }
+
+}  // namespace htex
+
+namespace {
+
+#define fail htex::set_error
+
 htex_status ok()
 {
-    g_last_error.clear();
+    htex::clear_error();
     return HTEX_OK;
 }
 

@@ -9,6 +9,10 @@
 
 namespace htex {
 
+// Thread-local last-error message shared by every entry point of libhtex.
+htex_status set_error(htex_status st, const char *fmt, ...);
+void clear_error();
+
 // Everything one sampling or backward launch needs, by value.
 struct SampleArgs {
     int32_t H;
@@ -36,7 +40,29 @@ __host__ __device__ inline int64_t level_offset(int k, int l)
     return ((int64_t(1) << (2 * k + 2)) - (int64_t(1) << (2 * (k - l) + 2))) / 3;
 }
 
+// Serving: a resident mesh (prepared records + pool) and a tile of one
+// request's queries.
+struct ServeMesh {
+    const void *prep;
+    const void *texels;
+    const float *scale;
+    int32_t H;
+    int32_t pad;
+};
+
+struct ServeTile {
+    const int32_t *h;
+    const float *u, *v, *f;
+    float *out;
+    int64_t q0;        // first query of the tile inside the request's arrays
+    int32_t mesh;
+    int32_t count;     // 1..kTileQueries
+};
+constexpr int kTileQueries = 256;
+
 hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t s);
+hipError_t launch_serve(const ServeMesh *meshes, const ServeTile *tiles, int32_t ntiles,
+                        int32_t grid, int dtype, int filter, int32_t *err, hipStream_t s);
 hipError_t launch_backward(const SampleArgs &a, int filter, hipStream_t s);
 hipError_t launch_prepare(const SampleArgs &a, void *prep, hipStream_t s);
 hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, hipStream_t s);

@@ -384,12 +384,12 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a)
 }
 
 // Fast path: the same arithmetic as k_sample with the navigation read from
-// one prepared record per query (bit-identical results).
+// one prepared record per query (bit-identical results).  Shared by the
+// batch kernel and the serving kernel, so a query's result does not depend
+// on which launch, batch or tile computes it.
 template <int DT, bool TRI>
-__global__ void __launch_bounds__(kBlock) k_sample_prep(SampleArgs a)
+__device__ __forceinline__ void sample_one_prepared(const SampleArgs &a, int64_t q)
 {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q >= a.Q) return;
     const int32_t h = __builtin_nontemporal_load(a.qh + q);
     const float u = __builtin_nontemporal_load(a.qu + q);
     const float v = __builtin_nontemporal_load(a.qv + q);
@@ -423,6 +423,42 @@ __global__ void __launch_bounds__(kBlock) k_sample_prep(SampleArgs a)
     const float r = __builtin_amdgcn_rcpf(W);
     const f32x4 ov = {C.x * r, C.y * r, C.z * r, C.w * r};
     __builtin_nontemporal_store(ov, out4 + q);
+}
+
+template <int DT, bool TRI>
+__global__ void __launch_bounds__(kBlock) k_sample_prep(SampleArgs a)
+{
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= a.Q) return;
+    sample_one_prepared<DT, TRI>(a, q);
+}
+
+// Serving: one launch covers a list of tiles, each up to kBlock queries of
+// one request on one resident mesh.  A fixed grid walks the list (block b
+// takes tiles b, b + G, ...), so every block exits once the list is done.
+template <int DT, bool TRI>
+__global__ void __launch_bounds__(kBlock) k_serve(const ServeMesh *meshes, const ServeTile *tiles,
+                                                  int32_t ntiles, int32_t *err)
+{
+    for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const ServeTile T = tiles[t];
+        if ((int32_t)threadIdx.x < T.count) {
+            const ServeMesh M = meshes[T.mesh];
+            SampleArgs a{};
+            a.H = M.H;
+            a.prep = M.prep;
+            a.texels = M.texels;
+            a.scale = M.scale;
+            a.Q = T.q0 + T.count;
+            a.qh = T.h;
+            a.qu = T.u;
+            a.qv = T.v;
+            a.qf = T.f;
+            a.out = T.out;
+            a.err = err;
+            sample_one_prepared<DT, TRI>(a, T.q0 + threadIdx.x);
+        }
+    }
 }
 
 // One record per halfedge: resolve Next/Prev, the edges, reflections,
@@ -540,6 +576,23 @@ hipError_t launch_fwd_prep(const SampleArgs &a, hipStream_t s)
 }
 
 }  // namespace
+
+hipError_t launch_serve(const ServeMesh *meshes, const ServeTile *tiles, int32_t ntiles,
+                        int32_t grid, int dtype, int filter, int32_t *err, hipStream_t s)
+{
+    if (ntiles == 0) return hipSuccess;
+    const uint32_t G = (uint32_t)(grid < ntiles ? grid : ntiles);
+    const bool tri = filter == HTEX_TRILINEAR;
+#define HTEX_SERVE(DTV, TRV) \
+    hipLaunchKernelGGL((k_serve<DTV, TRV>), dim3(G), dim3(kBlock), 0, s, meshes, tiles, ntiles, err)
+    switch (dtype) {
+    case HTEX_F32: if (tri) HTEX_SERVE(HTEX_F32, true); else HTEX_SERVE(HTEX_F32, false); break;
+    case HTEX_BF16: if (tri) HTEX_SERVE(HTEX_BF16, true); else HTEX_SERVE(HTEX_BF16, false); break;
+    default: if (tri) HTEX_SERVE(HTEX_FP8_E4M3, true); else HTEX_SERVE(HTEX_FP8_E4M3, false); break;
+    }
+#undef HTEX_SERVE
+    return hipGetLastError();
+}
 
 hipError_t launch_prepare(const SampleArgs &a, void *prep, hipStream_t s)
 {

@@ -1,0 +1,86 @@
+"""Continuous-batching Htex server (binding of the htex_server_* C ABI).
+
+The scheduler runs inside libhtex (a native thread); this class only
+marshals arguments.  Query arrays and result buffers are page-locked host
+tensors owned by the caller until the request completes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, load
+
+
+class Server:
+    def __init__(self, dtype, filter, arena_bytes=1 << 30, max_inflight=64,
+                 compute_streams=2, max_batch_queries=1 << 22, grid_blocks=0,
+                 max_meshes=64):
+        cfg = _lib.htex_server_config(int(dtype), int(filter), int(max_inflight),
+                                      int(compute_streams), int(arena_bytes),
+                                      int(max_batch_queries), int(grid_blocks), int(max_meshes))
+        self._h = C.c_void_p()
+        check(load().htex_server_create(C.byref(cfg), C.byref(self._h)))
+        self.filter = filter
+        self._keep = {}       # request id -> tensors that must stay alive
+        self._meshes = []
+
+    def add_mesh(self, prep, pool) -> int:
+        mid = C.c_int32()
+        check(load().htex_server_add_mesh(self._h, prep.H, prep.buf.data_ptr(),
+                                          C.byref(pool.c), C.byref(mid)))
+        self._meshes.append((prep, pool))
+        return mid.value
+
+    @staticmethod
+    def pinned(a, dtype):
+        t = torch.empty(len(a) if np.ndim(a) == 1 else a.shape, dtype=dtype, pin_memory=True)
+        t.numpy()[...] = a
+        return t
+
+    def submit(self, mesh_id, h, u, v, f=None, out=None) -> int:
+        """h, u, v, f: page-locked CPU tensors; returns the request id."""
+        Q = h.numel()
+        if out is None:
+            out = torch.empty((Q, 4), dtype=torch.float32, pin_memory=True)
+        rid = C.c_int64()
+        check(load().htex_server_submit(self._h, int(mesh_id), Q, h.data_ptr(), u.data_ptr(),
+                                        v.data_ptr(), f.data_ptr() if f is not None else None,
+                                        out.data_ptr(), C.byref(rid)))
+        self._keep[rid.value] = (h, u, v, f, out)
+        return rid.value
+
+    def result(self, rid):
+        return self._keep[rid][4]
+
+    def release(self, rid):
+        self._keep.pop(rid, None)
+
+    def poll(self, max_n=4096):
+        ids = (C.c_int64 * max_n)()
+        lat = (C.c_double * max_n)()
+        n = C.c_int32()
+        check(load().htex_server_poll(self._h, max_n, ids, lat, C.byref(n)))
+        return [(ids[i], lat[i]) for i in range(n.value)]
+
+    def drain(self, timeout_s=60.0):
+        check(load().htex_server_drain(self._h, float(timeout_s)))
+
+    def stats(self) -> dict:
+        st = _lib.htex_server_stats()
+        check(load().htex_server_stats_get(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_ if k != "pad"}
+
+    def close(self):
+        if self._h:
+            check(load().htex_server_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,102 @@
+"""The continuous-batching server: every request's result equals the same
+queries sampled alone (bit for bit), requests are admitted under a small
+memory budget, oversized ones are refused, invalid queries are counted."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2207_05618_amd as htex
+from htexgen.mesh import cube_mesh, sphere_mesh
+from htexgen.queries import uniform_queries
+from paper_2207_05618_amd.serve import Server
+from tests.gpu_helpers import Setup, t
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def meshes():
+    out = []
+    for i, (m, k) in enumerate([(cube_mesh(), 4), (sphere_mesh(n=10, seed=3), 5),
+                                (cube_mesh(n=3, seed=9, n_split=4, n_merge=2), 6)]):
+        s = Setup(m, np.full(m.E, k), has_mips=True, kind=1, seed=500 + i)
+        qb = htex.htex_quantize(s.pool, htex.HTEX_BF16)
+        prep = htex.Prepared(s.dmesh, qb)
+        out.append((m, qb, prep))
+    torch.cuda.synchronize()
+    return out
+
+
+def _requests(meshes, n, seed, lo=1, hi=50000):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        mid = int(rng.integers(0, len(meshes)))
+        Q = int(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        q = uniform_queries(meshes[mid][0].H, Q, seed * 1000 + i, log2f=(-6, 0), sort=True)
+        reqs.append((mid, q))
+    return reqs
+
+
+def _alone(meshes, mid, q):
+    m, pool, prep = meshes[mid]
+    o = htex.htex_sample_prepared(prep, pool, t(q.h), t(q.u), t(q.v), t(q.f),
+                                  filter=htex.HTEX_TRILINEAR)
+    torch.cuda.synchronize()
+    return o.cpu().numpy()
+
+
+@pytest.mark.parametrize("arena", [1 << 28, 1 << 20])
+def test_results_identical_alone_and_in_the_mix(meshes, arena):
+    srv = Server(htex.HTEX_BF16, htex.HTEX_TRILINEAR, arena_bytes=arena, max_inflight=16,
+                 compute_streams=2, max_batch_queries=1 << 16)
+    ids = [srv.add_mesh(prep, pool) for _, pool, prep in meshes]
+    assert ids == [0, 1, 2]
+    reqs = _requests(meshes, 60, 11, hi=30000 if arena > 1 << 20 else 20000)
+    rids = []
+    for mid, q in reqs:
+        P = Server.pinned
+        rids.append(srv.submit(mid, P(q.h, torch.int32), P(q.u, torch.float32),
+                               P(q.v, torch.float32), P(q.f, torch.float32)))
+    srv.drain(120)
+    done = srv.poll()
+    assert sorted(r for r, _ in done) == rids
+    assert all(lat > 0 for _, lat in done)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["batches"] >= 1
+    assert st["arena_peak_bytes"] <= arena
+    for rid, (mid, q) in zip(rids, reqs):
+        np.testing.assert_array_equal(srv.result(rid).numpy(), _alone(meshes, mid, q))
+    srv.close()
+
+
+def test_oversized_request_is_refused_and_bad_mesh_rejected(meshes):
+    srv = Server(htex.HTEX_BF16, htex.HTEX_TRILINEAR, arena_bytes=1 << 16)
+    srv.add_mesh(meshes[0][2], meshes[0][1])
+    q = uniform_queries(meshes[0][0].H, 10000, 1, log2f=(-6, 0))
+    P = Server.pinned
+    args = (P(q.h, torch.int32), P(q.u, torch.float32), P(q.v, torch.float32),
+            P(q.f, torch.float32))
+    with pytest.raises(htex.HtexError) as ei:
+        srv.submit(0, *args)
+    assert ei.value.status == -7
+    with pytest.raises(htex.HtexError):
+        srv.submit(3, *args)
+    assert srv.stats()["rejected"] == 1
+    srv.close()
+
+
+def test_invalid_queries_in_requests(meshes):
+    srv = Server(htex.HTEX_BF16, htex.HTEX_TRILINEAR)
+    srv.add_mesh(meshes[0][2], meshes[0][1])
+    q = uniform_queries(meshes[0][0].H, 1000, 2, log2f=(-6, 0))
+    q.h[:3] = [-5, meshes[0][0].H, 10]
+    q.u[2] = np.nan
+    P = Server.pinned
+    rid = srv.submit(0, P(q.h, torch.int32), P(q.u, torch.float32), P(q.v, torch.float32),
+                     P(q.f, torch.float32))
+    srv.drain(30)
+    out = srv.result(rid).numpy()
+    assert np.isnan(out[:3]).all() and np.isfinite(out[3:]).all()
+    assert srv.stats()["invalid_queries"] == 3
+    srv.close()
