@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-bytes", action="store_true",
                     help="skip the exact algorithmic-byte count (roofline left null)")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving benchmark (200 GB of resident meshes)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -181,6 +183,263 @@ def cpu_baseline(mesh, log2res, base, pool_dev, batch, has_mips=True, want_s=10.
                       f"({len(edges)} edges, FP64, median of {len(times)} runs)"}
 
 
+# ------------------------------------------------------- differentiation --
+
+def grad_benchmark(steps=200):
+    """Differentiation form: the tiny cube with 32x32 RGBA float32 textures,
+    8,294,400 queries sorted by halfedge; forward and backward rates with
+    N(0,1) upstream gradients, then Adam fitting the textures (start 0.5) to
+    the samples of a seeded smooth target pool (MSE)."""
+    import numpy as np
+    import torch
+
+    import paper_2207_05618_amd as htex
+    from htexgen import pool as gpool
+    from htexgen.mesh import cube_mesh
+    from htexgen.queries import uniform_queries
+
+    m = cube_mesh()
+    lr = np.full(m.E, 5, np.uint8)
+    dm = htex.Mesh.of(m)
+    base, total = gpool.layout(lr, False)
+    target = htex.Pool(lr, False, texels=torch.from_numpy(
+        gpool.fill_level0_host(1, 401, lr, base, total, m.boundary_edges(), False)).cuda())
+    q = uniform_queries(m.H, 3840 * 2160, 405, sort=True)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    h, u, v = T(q.h), T(q.u), T(q.v)
+    y, _ = htex.htex_sample(dm, target, h, u, v)
+    tex = torch.full((total, 4), 0.5, dtype=torch.float32, device="cuda")
+    pool = htex.Pool(lr, False, texels=tex)
+    g = torch.from_numpy(np.random.default_rng(403).standard_normal((q.Q, 4)).astype(
+        np.float32)).cuda()
+    out = torch.empty_like(y)
+    dtex = torch.zeros_like(tex)
+
+    def timed(fn, n=10):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n / 1e3
+
+    t_fwd = timed(lambda: htex.htex_sample(dm, pool, h, u, v, out=out))
+    t_bwd = timed(lambda: htex.htex_sample_backward(dm, pool, h, u, v, g, dtexels=dtex))
+    tex.requires_grad_(True)
+    opt = torch.optim.Adam([tex], lr=0.02)
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(steps):
+        opt.zero_grad(set_to_none=False)
+        o = htex.HtexSample.apply(tex, dm, pool, h, u, v, None, htex.HTEX_BILINEAR)
+        loss = ((o - y) ** 2).mean()
+        loss.backward()
+        opt.step()
+        if it % 20 == 0 or it == steps - 1:
+            losses.append(float(loss.item()))
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t0
+    tex.requires_grad_(False)
+    return {"queries": q.Q, "edges": int(m.E), "texels": int(total),
+            "forward_samples_per_s": q.Q / t_fwd, "backward_samples_per_s": q.Q / t_bwd,
+            "forward_us": t_fwd * 1e6, "backward_us": t_bwd * 1e6,
+            "adam_steps": steps, "adam_seconds": fit_s, "loss_first": losses[0],
+            "loss_last": losses[-1], "loss_reduction": losses[0] / max(losses[-1], 1e-30),
+            "loss_curve_every_20": losses}
+
+
+# -------------------------------------------------------------- serving --
+
+def _gen_sphere(args):
+    n, seed = args
+    from htexgen.mesh import sphere_mesh
+    m = sphere_mesh(n=n, seed=seed)
+    return (m.twin, m.next, m.prev, m.edge, m.E, m.F, m.boundary_edges())
+
+
+def _bf16_pool_chunked(htex, gdev, log2res, boundary, seed, chunk_texels=1 << 29):
+    """BF16 pool with mips filled on the device in float32 chunks of edges
+    (fill, box mips, quantize, copy), so the float32 copy never exists
+    whole."""
+    import numpy as np
+    import torch
+    big = htex.Pool(log2res, True, htex.HTEX_BF16)
+    E = len(log2res)
+    base = big.base_host
+    e0 = 0
+    ci = 0
+    while e0 < E:
+        e1 = max(e0 + 1, int(np.searchsorted(base, base[e0] + chunk_texels)))
+        e1 = min(e1, E)
+        sub = htex.Pool(log2res[e0:e1], True, htex.HTEX_F32)
+        gdev.fill_level0(sub.texels, 1, seed * 4096 + ci, sub.log2res, sub.base, boundary[e0:e1])
+        htex.htex_build_mips(sub)
+        q = htex.htex_quantize(sub, htex.HTEX_BF16)
+        big.texels[base[e0]:base[e0] + sub.total].copy_(q.texels)
+        del sub, q
+        e0 = e1
+        ci += 1
+    torch.cuda.synchronize()
+    return big
+
+
+def serve_meshes(seed=501):
+    """The 16 serving meshes (5k-500k faces, log-uniform), generated in worker
+    processes; called before this process touches the GPU."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    faces = np.exp(rng.uniform(np.log(5e3), np.log(5e5), 16))
+    ns = np.maximum(4, np.round(np.sqrt(faces * 1.025 / 6 / 0.99))).astype(int)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_gen_sphere, [(int(n), seed * 100 + i) for i, n in enumerate(ns)]))
+
+
+def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9), run_s=2.0):
+    """Serving form: 16 resident meshes (5k-500k faces, log-uniform) with
+    BF16 textures + mips sized to about 200 GB, Poisson streams of requests
+    of 4k-2M queries (log-uniform, frame-like, sorted by halfedge) to random
+    meshes at 0.3 / 0.6 / 0.9 of the measured saturation throughput."""
+    import numpy as np
+    import torch
+
+    import paper_2207_05618_amd as htex
+    from htexgen import device as gdev
+    from htexgen.queries import uniform_queries
+    from paper_2207_05618_amd.serve import Server
+
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(seed + 1)
+    # per-mesh resolution, downgraded on the largest meshes to reach the budget
+    ks = rng.choice([5, 6, 7], 16)
+
+    def bytes_of(i, k):
+        return htex.htex_pool_layout(np.full(meshes[i][4], k, np.uint8), True)[1] * 8
+
+    while sum(bytes_of(i, ks[i]) for i in range(16)) > target_bytes * 1.05:
+        i = int(np.argmax([bytes_of(i, ks[i]) if ks[i] > 4 else -1 for i in range(16)]))
+        ks[i] -= 1
+    while True:
+        tot = sum(bytes_of(i, ks[i]) for i in range(16))
+        cands = [i for i in range(16) if ks[i] < 7
+                 and tot - bytes_of(i, ks[i]) + bytes_of(i, ks[i] + 1) <= target_bytes * 1.05]
+        if tot >= target_bytes * 0.95 or not cands:
+            break
+        i = min(cands, key=lambda j: bytes_of(j, ks[j]))
+        ks[i] += 1
+    resident = []
+    for i, (tw, nx, pv, ed, E, F, bnd) in enumerate(meshes):
+        dm = htex.Mesh(tw, nx, pv, ed, E)
+        pool = _bf16_pool_chunked(htex, gdev, np.full(E, ks[i], np.uint8), bnd, seed * 100 + i)
+        prep = htex.Prepared(dm, pool)
+        resident.append((dm, pool, prep, len(tw)))
+    torch.cuda.synchronize()
+    pool_bytes = sum(r[1].nbytes() for r in resident)
+    log(f"serve: {pool_bytes / 1e9:.1f} GB BF16 resident ({time.perf_counter() - t0:.1f}s)")
+
+    # request payloads (page-locked), reused by the streams
+    P = Server.pinned
+    payloads = []
+    for j in range(48):
+        mid = int(rng.integers(0, 16))
+        Q = int(np.exp(rng.uniform(np.log(4096), np.log(2097152))))
+        q = uniform_queries(resident[mid][3], Q, seed * 1000 + j, log2f=(-3.2, -1.2), sort=True)
+        payloads.append((mid, Q, P(q.h, torch.int32), P(q.u, torch.float32),
+                         P(q.v, torch.float32), P(q.f, torch.float32),
+                         torch.empty((Q, 4), dtype=torch.float32, pin_memory=True)))
+    mean_q = float(np.mean([p[1] for p in payloads]))
+    log(f"serve: 48 payloads, mean {mean_q:.0f} queries ({time.perf_counter() - t0:.1f}s)")
+
+    # one request at a time: copy in, sample, copy out, wait (no batching)
+    seq_lat = []
+    alone = {}
+    for j in range(16):
+        mid, Q, h, u, v, f, _ = payloads[j]
+        _, pool, prep, _ = resident[mid]
+        ts = time.perf_counter()
+        dh, du, dv, df = (x.to("cuda", non_blocking=True) for x in (h, u, v, f))
+        o = htex.htex_sample_prepared(prep, pool, dh, du, dv, df, filter=htex.HTEX_TRILINEAR,
+                                      flags=htex.HTEX_QUERIES_SORTED)
+        oh = torch.empty((Q, 4), dtype=torch.float32, pin_memory=True)
+        oh.copy_(o, non_blocking=True)
+        torch.cuda.synchronize()
+        seq_lat.append(time.perf_counter() - ts)
+        alone[j] = oh
+    seq_rate = sum(payloads[j][1] for j in range(16)) / sum(seq_lat)
+
+    srv = Server(htex.HTEX_BF16, htex.HTEX_TRILINEAR, arena_bytes=4 << 30, max_inflight=64,
+                 compute_streams=2, max_batch_queries=1 << 22, max_meshes=16)
+    for dm, pool, prep, _ in resident:
+        srv.add_mesh(prep, pool)
+
+    def submit(j):
+        mid, Q, h, u, v, f, out = payloads[j]
+        return srv.submit(mid, h, u, v, f, out)
+
+    # saturation: a burst of 3 x 48 requests
+    ids = {}
+    tb = time.perf_counter()
+    for r in range(3):
+        for j in range(48):
+            ids[submit(j)] = j
+    srv.drain(300)
+    sat_rate = 3 * sum(p[1] for p in payloads) / (time.perf_counter() - tb)
+    for rid, _ in srv.poll(1 << 16):
+        srv.release(rid)
+    same = all(np.array_equal(payloads[j][6].numpy(), alone[j].numpy()) for j in range(16))
+    log(f"serve: saturation {sat_rate:.3e} samples/s; sequential {seq_rate:.3e}; "
+        f"mix==alone {same}")
+
+    out = {"resident_bytes": pool_bytes, "meshes": 16,
+           "faces": int(sum(m[5] for m in meshes)), "edges": int(sum(m[4] for m in meshes)),
+           "log2res": [int(k) for k in ks], "mean_queries_per_request": mean_q,
+           "saturation_samples_per_s": sat_rate, "sequential_samples_per_s": seq_rate,
+           "sequential_p50_ms": float(np.percentile(seq_lat, 50) * 1e3),
+           "speedup_vs_sequential": sat_rate / seq_rate, "results_mix_equal_alone": bool(same),
+           "rates": []}
+    lam_sat = sat_rate / mean_q
+    for frac in rates:
+        lam = frac * lam_sat
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=int(lam * run_s) + 1))
+        arr = arr[arr < run_s]
+        picks = rng.integers(0, 48, size=len(arr))
+        start = time.perf_counter()
+        nq = 0
+        for a, j in zip(arr, picks):
+            while time.perf_counter() - start < a:
+                pass
+            submit(int(j))
+            nq += payloads[int(j)][1]
+        srv.drain(300)
+        wall = time.perf_counter() - start
+        done = srv.poll(1 << 20)
+        lat = np.array([l for _, l in done])
+        for rid, _ in done:
+            srv.release(rid)
+        rec = {"load": frac, "requests": int(len(arr)), "offered_req_per_s": lam,
+               "achieved_samples_per_s": nq / wall,
+               "p50_ms": float(np.percentile(lat, 50) * 1e3),
+               "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+        out["rates"].append(rec)
+        log(f"serve: load {frac}: {len(arr)} requests, p50 {rec['p50_ms']:.2f} ms, "
+            f"p99 {rec['p99_ms']:.2f} ms, {rec['achieved_samples_per_s']:.3e} samples/s")
+    st = srv.stats()
+    srv.close()
+    out["batches"] = st["batches"]
+    out["arena_peak_bytes"] = st["arena_peak_bytes"]
+    del resident, payloads, alone
+    torch.cuda.empty_cache()
+    return out
+
+
 # ------------------------------------------------------------- profiles --
 
 def recorded_traffic():
@@ -213,6 +472,11 @@ def main():
     from htexgen import device as gdev
 
     t_start = time.perf_counter()
+    smeshes = None
+    if not args.no_serve and args.workload == "frame4k":
+        smeshes = serve_meshes()
+        log(f"serve meshes: {sum(m[5] for m in smeshes)} faces "
+            f"({time.perf_counter() - t_start:.1f}s)")
     mesh, log2res, batches, unsorted, kind, tex_seed = build_workload(args.workload)
     log(f"mesh H={mesh.H} E={mesh.E} F={mesh.F}; {len(batches)} batches of {batches[0].Q}"
         f" queries ({time.perf_counter() - t_start:.1f}s)")
@@ -273,6 +537,27 @@ def main():
     extra = {}
     if not args.no_extra:
         extra["unsorted_samples_per_s"] = rate(pool, [to_dev(unsorted)])
+        # unsorted batch put in halfedge order first (sort, permute, sample,
+        # results back to input order), timed as a whole
+        hu, uu, vu, fu = to_dev(unsorted)
+        sorted_out = torch.empty_like(out)
+
+        def sorted_step():
+            perm = htex.htex_sort_queries(mesh.H, hu)
+            h2, u2, v2, f2 = htex.htex_permute_queries(perm, hu, uu, vu, fu)
+            htex.htex_sample_prepared(prep, pool, h2, u2, v2, f2, filter=htex.HTEX_TRILINEAR,
+                                      flags=htex.HTEX_QUERIES_SORTED, out=sorted_out)
+            htex.htex_unpermute_results(perm, sorted_out, out=out)
+
+        for _ in range(2):
+            sorted_step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            sorted_step()
+        torch.cuda.synchronize()
+        extra["unsorted_via_sort_samples_per_s"] = 5 * Q / (time.perf_counter() - t1)
+        del hu, uu, vu, fu, sorted_out
         qb = htex.htex_quantize(pool, htex.HTEX_BF16)
         extra["bf16_samples_per_s"] = rate(qb, dev_batches)
         del qb
@@ -308,10 +593,23 @@ def main():
         log(f"algorithmic bytes/query {alg['bytes_per_query']:.1f} "
             f"(texels {alg['texel_bytes_per_query']:.1f}); achieved {achieved:.0f} GB/s")
 
+    if not args.no_extra:
+        extra["differentiation"] = grad_benchmark()
+        d = extra["differentiation"]
+        log(f"grad: fwd {d['forward_us']:.0f} us, bwd {d['backward_us']:.0f} us, Adam loss "
+            f"{d['loss_first']:.3e} -> {d['loss_last']:.3e}")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(mesh, log2res, pool.base_host, pool.texels, batches[0])
         log(f"cpu oracle {cpu['value']:.3e} samples/s on {cpu['cores']} cores")
+
+    pool_bytes = pool.nbytes()
+    serving = None
+    if not args.no_serve and args.workload == "frame4k":
+        del prep, out, dev_batches, pool
+        torch.cuda.empty_cache()
+        serving = serve_benchmark(smeshes)
 
     fs = mesh.face_sizes()
     rec = {
@@ -328,10 +626,10 @@ def main():
             "face_mix": {"tri": float((fs == 3).mean()), "quad": float((fs == 4).mean()),
                          "5to8": float((fs >= 5).mean())},
             "boundary_edge_frac": float(mesh.boundary_edges().mean()),
-            "queries_per_step": Q, "pool_bytes": pool.nbytes(), "filter": "trilinear",
+            "queries_per_step": Q, "pool_bytes": pool_bytes, "filter": "trilinear",
             "log2_footprint": [-3.2, -1.2] if args.workload == "frame4k" else [-6, 0],
             "sorted": True, "batches_rotated": len(batches)},
-        "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
+        "roofline": roofline, "cpu_baseline": cpu, "extra": extra, "serving": serving,
     }
     print(json.dumps(rec), flush=True)
 

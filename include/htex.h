@@ -192,6 +192,32 @@ htex_status htex_sample_backward(const htex_mesh *mesh, const htex_pool *pool,
                                  uint32_t flags, const float *dout, float *dtexels,
                                  void *stream);
 
+/* --------------------------------------------------------- query order --
+ * Optional step before sampling: the paper's fragments arrive from a
+ * rasterizer in triangle order (Section 4.4, "Rendering"); a batch in any
+ * other order can be put in halfedge order so that neighbouring queries read
+ * the same textures.  Sampling results do not depend on the order. */
+
+/* Bytes of device workspace htex_sort_queries needs for Q queries. */
+size_t htex_sort_workspace_bytes(int64_t Q);
+
+/* perm[0..Q) = the stable ordering of the queries by h (queries with h
+ * outside [0, H) last, in input order).  h: device int32 [Q]; perm: device
+ * int32 [Q]; ws: device workspace of at least htex_sort_workspace_bytes(Q)
+ * bytes, 256-byte aligned.  Q < 2^31. */
+htex_status htex_sort_queries(int32_t H, int64_t Q, const int32_t *h, int32_t *perm, void *ws,
+                              size_t ws_bytes, void *stream);
+
+/* Sorted copy of a batch: h_out[i] = h[perm[i]], same for u, v and the
+ * footprint (f_out may be NULL when the batch has none). */
+htex_status htex_permute_queries(const htex_queries *in, const int32_t *perm, int32_t *h_out,
+                                 float *u_out, float *v_out, float *f_out, void *stream);
+
+/* Results back to input order: out[perm[i]] = in[i] (float32 Q x 4, both
+ * 16-byte aligned, not overlapping). */
+htex_status htex_unpermute_results(int64_t Q, const int32_t *perm, const float *in, float *out,
+                                   void *stream);
+
 /* Prepared fetch descriptors: the halfedge navigation of Alg. 3 resolved
  * once per (mesh, pool) so that a query reads one record instead of walking
  * Next/Prev/Twin/Edge and the edge table.  Record h (HTEX_PREP_BYTES bytes,
@@ -222,7 +248,9 @@ htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *p
  * A continuous-batching server over resident meshes.  Requests (a mesh id
  * and a batch of queries in host memory) are admitted in arrival order as
  * request slots and device memory (an arena of arena_bytes, 32 bytes per
- * query) free up; admitted requests are copied to the device and gathered
+ * query) free up; admitted requests are copied to the device (on
+ * copy_streams upload streams; results come back on as many download
+ * streams, both directions at once) and gathered
  * into batches, each computed by one launch over a list of 256-query tiles
  * that mixes requests and meshes; up to compute_streams launches run at
  * once, and requests arriving meanwhile join the next batch.  Results are
@@ -243,6 +271,8 @@ typedef struct htex_server_config {
     int64_t max_batch_queries;/* queries gathered into one launch (> 0)        */
     int32_t grid_blocks;      /* blocks per launch; 0 = 4 per compute unit     */
     int32_t max_meshes;       /* resident meshes (> 0)                         */
+    int32_t copy_streams;     /* host<->device copy streams per direction, 1..4 */
+    int32_t reserved;         /* 0                                             */
 } htex_server_config;
 
 typedef struct htex_server_stats {

@@ -20,6 +20,7 @@ from ._lib import (DEBUG_FIELDS, HTEX_BF16, HTEX_BILINEAR, HTEX_F32, HTEX_FP8_E4
 __all__ = ["Mesh", "Pool", "htex_pool_layout", "htex_mesh_validate", "htex_build_mips",
            "htex_quantize", "htex_sample", "htex_sample_backward", "HtexSample",
            "htex_prepare", "htex_sample_prepared", "Prepared",
+           "htex_sort_queries", "htex_permute_queries", "htex_unpermute_results",
            "debug_records", "HtexError"]
 
 DEBUG_DTYPE = np.dtype(DEBUG_FIELDS)
@@ -194,6 +195,43 @@ def htex_sample_prepared(prep: "Prepared", pool: Pool, h, u, v, footprint=None,
                                       int(filter), int(flags), out.data_ptr(),
                                       err_count.data_ptr() if err_count is not None else None,
                                       _stream(stream)))
+    return out
+
+
+def htex_sort_queries(H: int, h, stream=None):
+    """perm (int32 [Q], device): the stable order of the queries by halfedge."""
+    h = _dev(h, torch.int32, "h")
+    Q = h.numel()
+    perm = torch.empty(Q, dtype=torch.int32, device=h.device)
+    nbytes = int(load().htex_sort_workspace_bytes(Q))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=h.device)
+    check(load().htex_sort_queries(int(H), Q, h.data_ptr(), perm.data_ptr(), ws.data_ptr(),
+                                   nbytes, _stream(stream)))
+    return perm
+
+
+def htex_permute_queries(perm, h, u, v, footprint=None, stream=None):
+    """(h, u, v, footprint) gathered into the order `perm`."""
+    q, Q = _queries(h, u, v, footprint)
+    _dev(perm, torch.int32, "perm")
+    ho = torch.empty_like(h)
+    uo = torch.empty_like(u)
+    vo = torch.empty_like(v)
+    fo = torch.empty_like(footprint) if footprint is not None else None
+    check(load().htex_permute_queries(C.byref(q), perm.data_ptr(), ho.data_ptr(), uo.data_ptr(),
+                                      vo.data_ptr(), fo.data_ptr() if fo is not None else None,
+                                      _stream(stream)))
+    return ho, uo, vo, fo
+
+
+def htex_unpermute_results(perm, out_sorted, out=None, stream=None):
+    """Results of a permuted batch back in input order."""
+    _dev(perm, torch.int32, "perm")
+    _dev(out_sorted, torch.float32, "out_sorted")
+    if out is None:
+        out = torch.empty_like(out_sorted)
+    check(load().htex_unpermute_results(perm.numel(), perm.data_ptr(), out_sorted.data_ptr(),
+                                        out.data_ptr(), _stream(stream)))
     return out
 
 

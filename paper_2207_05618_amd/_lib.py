@@ -60,6 +60,10 @@ SIGNATURES = {
     "htex_sample": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_uint32, _P, _P, _P, _P]),
     "htex_sample_backward": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_uint32, _P, _P, _P]),
     "htex_prepare": (C.c_int32, [_P, _P, _P, _P]),
+    "htex_sort_workspace_bytes": (C.c_size_t, [C.c_int64]),
+    "htex_sort_queries": (C.c_int32, [C.c_int32, C.c_int64, _P, _P, _P, C.c_size_t, _P]),
+    "htex_permute_queries": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P]),
+    "htex_unpermute_results": (C.c_int32, [C.c_int64, _P, _P, _P, _P]),
     "htex_sample_prepared": (C.c_int32, [C.c_int32, _P, _P, _P, C.c_int32, C.c_uint32, _P, _P,
                                          _P]),
 }
@@ -70,7 +74,7 @@ class htex_server_config(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("filter", C.c_int32), ("max_inflight", C.c_int32),
                 ("compute_streams", C.c_int32), ("arena_bytes", C.c_int64),
                 ("max_batch_queries", C.c_int64), ("grid_blocks", C.c_int32),
-                ("max_meshes", C.c_int32)]
+                ("max_meshes", C.c_int32), ("copy_streams", C.c_int32), ("reserved", C.c_int32)]
 
 
 class htex_server_stats(C.Structure):

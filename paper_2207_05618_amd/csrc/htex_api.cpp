@@ -280,6 +280,50 @@ htex_status htex_sample_backward(const htex_mesh *mesh, const htex_pool *pool,
                     "backward launch");
 }
 
+size_t htex_sort_workspace_bytes(int64_t Q) { return htex::sort_workspace_bytes(Q < 0 ? 0 : Q); }
+
+htex_status htex_sort_queries(int32_t H, int64_t Q, const int32_t *h, int32_t *perm, void *ws,
+                              size_t ws_bytes, void *stream)
+{
+    if (H < 0 || Q < 0) return fail(HTEX_E_ARG, "negative size");
+    if (Q >= (int64_t(1) << 31)) return fail(HTEX_E_RANGE, "sorting needs Q < 2^31");
+    if (Q == 0) return ok();
+    if (!h || !perm || !ws) return fail(HTEX_E_ARG, "NULL argument");
+    if (!aligned(ws, 256)) return fail(HTEX_E_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < htex::sort_workspace_bytes(Q))
+        return fail(HTEX_E_ARG, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
+                    htex::sort_workspace_bytes(Q));
+    return from_hip(htex::launch_sort(h, H, Q, perm, ws, static_cast<hipStream_t>(stream)),
+                    "sort launch");
+}
+
+htex_status htex_permute_queries(const htex_queries *in, const int32_t *perm, int32_t *h_out,
+                                 float *u_out, float *v_out, float *f_out, void *stream)
+{
+    if (!in || in->Q < 0) return fail(HTEX_E_ARG, "bad queries");
+    if (in->Q == 0) return ok();
+    if (!in->h || !in->u || !in->v || !perm || !h_out || !u_out || !v_out)
+        return fail(HTEX_E_ARG, "NULL argument");
+    if (in->footprint && !f_out) return fail(HTEX_E_ARG, "f_out is NULL");
+    return from_hip(htex::launch_gather_queries(perm, in->Q, in->h, in->u, in->v, in->footprint,
+                                                h_out, u_out, v_out,
+                                                in->footprint ? f_out : nullptr,
+                                                static_cast<hipStream_t>(stream)),
+                    "permute launch");
+}
+
+htex_status htex_unpermute_results(int64_t Q, const int32_t *perm, const float *in, float *out,
+                                   void *stream)
+{
+    if (Q < 0) return fail(HTEX_E_ARG, "negative Q");
+    if (Q == 0) return ok();
+    if (!perm || !in || !out || !aligned(in, 16) || !aligned(out, 16))
+        return fail(HTEX_E_ARG, "in/out must be non-NULL and 16-byte aligned");
+    if (in == out) return fail(HTEX_E_ARG, "in and out must not overlap");
+    return from_hip(htex::launch_unpermute(perm, Q, in, out, static_cast<hipStream_t>(stream)),
+                    "unpermute launch");
+}
+
 htex_status htex_prepare(const htex_mesh *mesh, const htex_pool *pool, void *prep, void *stream)
 {
     htex_status st = check_mesh(mesh);

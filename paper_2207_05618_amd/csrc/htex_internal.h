@@ -61,6 +61,14 @@ struct ServeTile {
 constexpr int kTileQueries = 256;
 
 hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t s);
+size_t sort_workspace_bytes(int64_t Q);
+hipError_t launch_sort(const int32_t *h, int32_t H, int64_t Q, int32_t *perm, void *ws,
+                       hipStream_t s);
+hipError_t launch_gather_queries(const int32_t *perm, int64_t Q, const int32_t *h, const float *u,
+                                 const float *v, const float *f, int32_t *ho, float *uo, float *vo,
+                                 float *fo, hipStream_t s);
+hipError_t launch_unpermute(const int32_t *perm, int64_t Q, const float *in, float *out,
+                            hipStream_t s);
 hipError_t launch_serve(const ServeMesh *meshes, const ServeTile *tiles, int32_t ntiles,
                         int32_t grid, int dtype, int filter, int32_t *err, hipStream_t s);
 hipError_t launch_backward(const SampleArgs &a, int filter, hipStream_t s);

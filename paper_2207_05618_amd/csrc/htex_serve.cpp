@@ -119,7 +119,8 @@ struct htex_server {
     htex::ServeMesh *meshes_dev = nullptr;
     std::vector<htex::ServeMesh> meshes;
     int32_t *err_dev = nullptr;
-    hipStream_t s_up = nullptr, s_down = nullptr;
+    std::vector<hipStream_t> s_up, s_down;   // copy streams (both directions run at once)
+    int up_rr = 0, down_rr = 0;
     std::vector<Batch> batches;
 
     std::mutex mu;                 // guards inbox, done, counters, meshes
@@ -147,6 +148,7 @@ namespace {
 
 hipError_t upload(htex_server *S, Request *r)
 {
+    hipStream_t su = S->s_up[S->up_rr++ % S->s_up.size()];
     const bool tri = S->cfg.filter == HTEX_TRILINEAR;
     const int64_t Q = r->Q;
     char *base = S->arena_dev + r->arena_off;
@@ -160,13 +162,13 @@ hipError_t upload(htex_server *S, Request *r)
     r->dv = reinterpret_cast<float *>(carve(4 * Q));
     r->df = tri ? reinterpret_cast<float *>(carve(4 * Q)) : nullptr;
     r->dout = reinterpret_cast<float *>(carve(16 * Q));
-    hipError_t e = hipMemcpyAsync(r->dh, r->h, 4 * Q, hipMemcpyHostToDevice, S->s_up);
-    if (!e) e = hipMemcpyAsync(r->du, r->u, 4 * Q, hipMemcpyHostToDevice, S->s_up);
-    if (!e) e = hipMemcpyAsync(r->dv, r->v, 4 * Q, hipMemcpyHostToDevice, S->s_up);
-    if (!e && tri) e = hipMemcpyAsync(r->df, r->f, 4 * Q, hipMemcpyHostToDevice, S->s_up);
+    hipError_t e = hipMemcpyAsync(r->dh, r->h, 4 * Q, hipMemcpyHostToDevice, su);
+    if (!e) e = hipMemcpyAsync(r->du, r->u, 4 * Q, hipMemcpyHostToDevice, su);
+    if (!e) e = hipMemcpyAsync(r->dv, r->v, 4 * Q, hipMemcpyHostToDevice, su);
+    if (!e && tri) e = hipMemcpyAsync(r->df, r->f, 4 * Q, hipMemcpyHostToDevice, su);
     if (!e) e = hipEventCreateWithFlags(&r->ev_up, hipEventDisableTiming);
     if (!e) e = hipEventCreateWithFlags(&r->ev_down, hipEventDisableTiming);
-    if (!e) e = hipEventRecord(r->ev_up, S->s_up);
+    if (!e) e = hipEventRecord(r->ev_up, su);
     return e;
 }
 
@@ -250,10 +252,12 @@ bool htex_server::step()
         if (!e) e = htex::launch_serve(meshes_dev, b.tiles_dev, ntiles, grid, cfg.dtype, cfg.filter,
                                        err_dev, b.stream);
         if (!e) e = hipEventRecord(b.ev_done, b.stream);
-        if (!e) e = hipStreamWaitEvent(s_down, b.ev_done, 0);
+        for (hipStream_t sd : s_down)
+            if (!e) e = hipStreamWaitEvent(sd, b.ev_done, 0);
         for (Request *r : b.reqs) {
-            if (!e) e = hipMemcpyAsync(r->out, r->dout, 16 * r->Q, hipMemcpyDeviceToHost, s_down);
-            if (!e) e = hipEventRecord(r->ev_down, s_down);
+            hipStream_t sd = s_down[down_rr++ % s_down.size()];
+            if (!e) e = hipMemcpyAsync(r->out, r->dout, 16 * r->Q, hipMemcpyDeviceToHost, sd);
+            if (!e) e = hipEventRecord(r->ev_down, sd);
             downloading.push_back(r);
         }
         if (e) throw std::runtime_error(std::string("launch: ") + hipGetErrorString(e));
@@ -341,6 +345,7 @@ htex_status htex_server_create(const htex_server_config *cfg, htex_server **out)
     if (cfg->filter != HTEX_BILINEAR && cfg->filter != HTEX_TRILINEAR)
         return fail(HTEX_E_ARG, "bad filter");
     if (cfg->max_inflight <= 0 || cfg->compute_streams < 1 || cfg->compute_streams > 4 ||
+        cfg->copy_streams < 1 || cfg->copy_streams > 4 ||
         cfg->arena_bytes <= 0 || cfg->max_batch_queries <= 0 || cfg->max_meshes <= 0 ||
         cfg->grid_blocks < 0)
         return fail(HTEX_E_ARG, "bad server configuration");
@@ -358,8 +363,13 @@ htex_status htex_server_create(const htex_server_config *cfg, htex_server **out)
     if (!e) e = hipMalloc(&S->meshes_dev, sizeof(htex::ServeMesh) * cfg->max_meshes);
     if (!e) e = hipMalloc(&S->err_dev, sizeof(int32_t));
     if (!e) e = hipMemset(S->err_dev, 0, sizeof(int32_t));
-    if (!e) e = hipStreamCreateWithFlags(&S->s_up, hipStreamNonBlocking);
-    if (!e) e = hipStreamCreateWithFlags(&S->s_down, hipStreamNonBlocking);
+    const int ncopy = cfg->copy_streams;
+    S->s_up.assign(ncopy, nullptr);
+    S->s_down.assign(ncopy, nullptr);
+    for (int i = 0; i < ncopy; ++i) {
+        if (!e) e = hipStreamCreateWithFlags(&S->s_up[i], hipStreamNonBlocking);
+        if (!e) e = hipStreamCreateWithFlags(&S->s_down[i], hipStreamNonBlocking);
+    }
     S->batches.resize(cfg->compute_streams);
     for (Batch &b : S->batches) {
         if (!e) e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking);
@@ -506,14 +516,16 @@ htex_status htex_server_destroy(htex_server *S)
         if (b.tiles_dev) (void)hipFree(b.tiles_dev);
         if (b.stream) (void)hipStreamDestroy(b.stream);
     }
-    if (S->s_up) {
-        (void)hipStreamSynchronize(S->s_up);
-        (void)hipStreamDestroy(S->s_up);
-    }
-    if (S->s_down) {
-        (void)hipStreamSynchronize(S->s_down);
-        (void)hipStreamDestroy(S->s_down);
-    }
+    for (hipStream_t st : S->s_up)
+        if (st) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
+    for (hipStream_t st : S->s_down)
+        if (st) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
     if (S->arena_dev) (void)hipFree(S->arena_dev);
     if (S->meshes_dev) (void)hipFree(S->meshes_dev);
     if (S->err_dev) (void)hipFree(S->err_dev);

@@ -18,10 +18,11 @@ from ._lib import check, load
 class Server:
     def __init__(self, dtype, filter, arena_bytes=1 << 30, max_inflight=64,
                  compute_streams=2, max_batch_queries=1 << 22, grid_blocks=0,
-                 max_meshes=64):
+                 max_meshes=64, copy_streams=2):
         cfg = _lib.htex_server_config(int(dtype), int(filter), int(max_inflight),
                                       int(compute_streams), int(arena_bytes),
-                                      int(max_batch_queries), int(grid_blocks), int(max_meshes))
+                                      int(max_batch_queries), int(grid_blocks), int(max_meshes),
+                                      int(copy_streams), 0)
         self._h = C.c_void_p()
         check(load().htex_server_create(C.byref(cfg), C.byref(self._h)))
         self.filter = filter

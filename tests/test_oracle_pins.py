@@ -666,3 +666,34 @@ def test_invalid_queries_give_nan_and_count():
     out, errs, _ = oracle.sample(M, P, h, u, v)
     assert errs == 4
     assert np.isfinite(out[0]).all() and np.isnan(out[1:]).all()
+
+
+def test_backward_fd_config4_shape():
+    """Config 4's shape: the tiny cube, 32x32 RGBA float32 textures, N(0,1)
+    upstream gradients; FP64 central differences on 512 sampled texel
+    channels (restricted to the queries that can touch each texel, which is
+    exact for a linear map) agree with the oracle gradient."""
+    m = cube_mesh()
+    lr = np.full(m.E, 5, np.uint8)
+    P, base = _pool(m, lr, kind=1, seed=401)
+    M = oracle.Mesh.of(m)
+    q = uniform_queries(m.H, 40000, 405, sort=True)
+    g = np.random.default_rng(403).standard_normal((q.Q, 4))
+    grad = oracle.backward(M, P, q.h, q.u, q.v, g)
+    rng = np.random.default_rng(404)
+    n = 32 * 32
+    for _ in range(512):
+        e = int(rng.integers(0, m.E))
+        t = int(base[e] + rng.integers(0, n))
+        c = int(rng.integers(0, 4))
+        near = np.isin(m.edge[q.h], [e]) | np.isin(m.edge[m.next[q.h]], [e]) | \
+            np.isin(m.edge[m.prev[q.h]], [e])
+        sel = np.nonzero(near)[0]
+        eps = 1e-3
+        Tp, Tm = P.texels.copy(), P.texels.copy()
+        Tp[t, c] += eps
+        Tm[t, c] -= eps
+        op, _, _ = oracle.sample(M, oracle.Pool(lr, base, Tp, False), q.h[sel], q.u[sel], q.v[sel])
+        om, _, _ = oracle.sample(M, oracle.Pool(lr, base, Tm, False), q.h[sel], q.u[sel], q.v[sel])
+        fd = ((op - om) * g[sel]).sum() / (2 * eps)
+        assert abs(fd - grad[t, c]) <= 1e-9 * max(1.0, abs(fd))
