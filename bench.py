@@ -445,7 +445,7 @@ def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9),
 def recorded_traffic():
     """HBM traffic per launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "htex_sample_frame4k_pmc.md")
+    path = os.path.join(ROOT, "profiles", "k_sample_prep_frame4k_pmc.md")
     src = os.path.join(ROOT, "paper_2207_05618_amd", "csrc", "htex_sample.hip")
     if not os.path.exists(path):
         return None
