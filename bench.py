@@ -227,8 +227,10 @@ def grad_benchmark(steps=200):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / n / 1e3
 
-    t_fwd = timed(lambda: htex.htex_sample(dm, pool, h, u, v, out=out))
-    t_bwd = timed(lambda: htex.htex_sample_backward(dm, pool, h, u, v, g, dtexels=dtex))
+    S = htex.HTEX_QUERIES_SORTED
+    t_fwd = timed(lambda: htex.htex_sample(dm, pool, h, u, v, flags=S, out=out))
+    t_bwd = timed(lambda: htex.htex_sample_backward(dm, pool, h, u, v, g, flags=S, dtexels=dtex))
+    t_bwd_plain = timed(lambda: htex.htex_sample_backward(dm, pool, h, u, v, g, dtexels=dtex))
     tex.requires_grad_(True)
     opt = torch.optim.Adam([tex], lr=0.02)
     losses = []
@@ -236,7 +238,7 @@ def grad_benchmark(steps=200):
     t0 = time.perf_counter()
     for it in range(steps):
         opt.zero_grad(set_to_none=False)
-        o = htex.HtexSample.apply(tex, dm, pool, h, u, v, None, htex.HTEX_BILINEAR)
+        o = htex.HtexSample.apply(tex, dm, pool, h, u, v, None, htex.HTEX_BILINEAR, S)
         loss = ((o - y) ** 2).mean()
         loss.backward()
         opt.step()
@@ -248,6 +250,7 @@ def grad_benchmark(steps=200):
     return {"queries": q.Q, "edges": int(m.E), "texels": int(total),
             "forward_samples_per_s": q.Q / t_fwd, "backward_samples_per_s": q.Q / t_bwd,
             "forward_us": t_fwd * 1e6, "backward_us": t_bwd * 1e6,
+            "backward_plain_atomics_us": t_bwd_plain * 1e6,
             "adam_steps": steps, "adam_seconds": fit_s, "loss_first": losses[0],
             "loss_last": losses[-1], "loss_reduction": losses[0] / max(losses[-1], 1e-30),
             "loss_curve_every_20": losses}
@@ -376,7 +379,7 @@ def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9),
     seq_rate = sum(payloads[j][1] for j in range(16)) / sum(seq_lat)
 
     srv = Server(htex.HTEX_BF16, htex.HTEX_TRILINEAR, arena_bytes=4 << 30, max_inflight=64,
-                 compute_streams=2, max_batch_queries=1 << 22, max_meshes=16)
+                 compute_streams=1, copy_streams=1, max_batch_queries=1 << 22, max_meshes=16)
     for dm, pool, prep, _ in resident:
         srv.add_mesh(prep, pool)
 

@@ -186,7 +186,10 @@ htex_status htex_sample(const htex_mesh *mesh, const htex_pool *pool,
  * (om: level weight, w: bilinear weight, W: the query's normalization).
  * dtexels is float32 with the pool's layout (16-byte aligned) and is added
  * to, with float32 atomics (summation order unspecified); the pool must be
- * HTEX_F32.  dout is float32 Q x 4 (16-byte aligned). */
+ * HTEX_F32.  dout is float32 Q x 4 (16-byte aligned).  With
+ * HTEX_QUERIES_SORTED, each workgroup first sums its consecutive queries'
+ * contributions to small textures (at most 32 x 32 texels per level) in
+ * on-chip memory and adds each texel once (fewer, uncontended atomics). */
 htex_status htex_sample_backward(const htex_mesh *mesh, const htex_pool *pool,
                                  const htex_queries *queries, int32_t filter,
                                  uint32_t flags, const float *dout, float *dtexels,
@@ -266,7 +269,9 @@ typedef struct htex_server_config {
     int32_t dtype;            /* texel storage of every mesh                   */
     int32_t filter;           /* HTEX_BILINEAR or HTEX_TRILINEAR              */
     int32_t max_inflight;     /* request slots (admitted, not yet complete)    */
-    int32_t compute_streams;  /* concurrent batch launches, 1..4               */
+    int32_t compute_streams;  /* concurrent batch launches, 1..4 (HIP maps a
+                                 process's streams onto few hardware queues;
+                                 1 compute + 1 + 1 copy streams measured best) */
     int64_t arena_bytes;      /* device bytes for request buffers (> 0)        */
     int64_t max_batch_queries;/* queries gathered into one launch (> 0)        */
     int32_t grid_blocks;      /* blocks per launch; 0 = 4 per compute unit     */

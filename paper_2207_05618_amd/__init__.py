@@ -258,21 +258,22 @@ def htex_sample_backward(mesh: Mesh, pool: Pool, h, u, v, dout, footprint=None,
 class HtexSample(torch.autograd.Function):
     """Differentiable sampling with respect to a float32 pool's texels.
 
-    forward(texels, mesh, pool, h, u, v, footprint, filter) -> [Q, 4]; the
-    gradient flows to `texels` (which must be pool.texels)."""
+    forward(texels, mesh, pool, h, u, v, footprint, filter, flags) -> [Q, 4];
+    the gradient flows to `texels` (which must be pool.texels)."""
 
     @staticmethod
-    def forward(ctx, texels, mesh, pool, h, u, v, footprint=None, filter=HTEX_BILINEAR):
+    def forward(ctx, texels, mesh, pool, h, u, v, footprint=None, filter=HTEX_BILINEAR,
+                flags=0):
         if texels.data_ptr() != pool.texels.data_ptr():
             raise ValueError("texels must be pool.texels")
-        out, _ = htex_sample(mesh, pool, h, u, v, footprint, filter)
+        out, _ = htex_sample(mesh, pool, h, u, v, footprint, filter, flags)
         ctx.save_for_backward(h, u, v, footprint)
-        ctx.mesh, ctx.pool, ctx.filter = mesh, pool, filter
+        ctx.mesh, ctx.pool, ctx.filter, ctx.flags = mesh, pool, filter, flags
         return out
 
     @staticmethod
     def backward(ctx, gout):
         h, u, v, footprint = ctx.saved_tensors
         d = htex_sample_backward(ctx.mesh, ctx.pool, h, u, v, gout.contiguous(), footprint,
-                                 ctx.filter)
-        return d, None, None, None, None, None, None, None
+                                 ctx.filter, ctx.flags)
+        return d, None, None, None, None, None, None, None, None

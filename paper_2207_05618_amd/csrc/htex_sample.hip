@@ -554,6 +554,119 @@ __global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
     }
 }
 
+// Backward with a per-workgroup cache of gradient tiles in LDS.  A block
+// takes kBwdChunk consecutive queries (sorted queries meet few textures
+// there) and accumulates each tap into an LDS slot holding one (edge, level)
+// of at most kSlotTexels texels; slots are claimed on first use by a
+// compare-and-swap on their tag and flushed to the gradient pool once, with
+// one float atomic per non-zero texel channel.  Taps of levels that are too
+// large, or that find every slot taken, go straight to global atomics.
+constexpr int kSlots = 4;
+constexpr int kSlotTexels = 1024;
+constexpr int kBwdPerThread = 16;
+constexpr int kBwdChunk = kBlock * kBwdPerThread;
+
+template <bool TRI>
+__global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
+{
+    __shared__ float4 acc[kSlots][kSlotTexels];
+    __shared__ int32_t tag[kSlots];   // edge * 16 + level, or -1
+    float *accf = reinterpret_cast<float *>(&acc[0][0]);
+    for (int i = threadIdx.x; i < kSlots * kSlotTexels * 4; i += kBlock) accf[i] = 0.0f;
+    if (threadIdx.x < kSlots) tag[threadIdx.x] = -1;
+    __syncthreads();
+    const int64_t q0 = (int64_t)blockIdx.x * kBwdChunk;
+    for (int r = 0; r < kBwdPerThread; ++r) {
+        const int64_t q = q0 + (int64_t)r * kBlock + threadIdx.x;
+        if (q >= a.Q) break;
+        const int32_t h = a.qh[q];
+        const float u = a.qu[q], v = a.qv[q];
+        if (!((uint32_t)h < (uint32_t)a.H) || !isfinite(u) || !isfinite(v)) continue;
+        const int32_t n1 = a.next[h], p1 = a.prev[h];
+        Lod L{0, 0, 0.0f, 1.0f};
+        if constexpr (TRI) L = lod_of(a.qf[q]);
+        FetchSpec fs[3];
+        fetch_specs(h, n1, p1, u, v, fs);
+        int32_t es[3], ks[3];
+        bool flips[3];
+        float W = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int32_t g = fs[s].g;
+            flips[s] = !(g > a.twin[g]);
+            es[s] = a.edge[g];
+            ks[s] = a.log2res[es[s]];
+            int lv[2];
+            float om[2];
+            const int nlev = fetch_levels(L, ks[s], lv, om);
+            for (int sl = 0; sl < nlev; ++sl) {
+                const LevelPlan p = plan_level(ks[s], lv[sl], om[sl], fs[s], flips[s]);
+                W += (p.wx0 + p.wx1) * (p.wy0 + p.wy1);
+            }
+        }
+        const float4 g4 = reinterpret_cast<const float4 *>(a.dout)[q];
+        const float rW = 1.0f / W;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            int lv[2];
+            float om[2];
+            const int nlev = fetch_levels(L, ks[s], lv, om);
+            const int64_t eb = a.base[es[s]];
+            for (int sl = 0; sl < nlev; ++sl) {
+                const LevelPlan p = plan_level(ks[s], lv[sl], om[sl], fs[s], flips[s]);
+                if (!p.act) continue;
+                const int m = ks[s] - lv[sl];
+                const uint32_t lo = level_offset32(ks[s], lv[sl]);
+                // slot of this (edge, level), if it fits
+                int slot = -1;
+                if ((1 << (2 * m)) <= kSlotTexels) {
+                    const int32_t key = es[s] * 16 + lv[sl];
+                    for (int t = 0; t < kSlots && slot < 0; ++t) {
+                        int32_t cur = tag[t];
+                        if (cur == -1) cur = atomicCAS(&tag[t], -1, key);
+                        if (cur == -1 || cur == key) slot = t;
+                    }
+                }
+                const float w[4] = {p.wx0 * p.wy0, p.wx1 * p.wy0, p.wx0 * p.wy1, p.wx1 * p.wy1};
+                const uint32_t off[4] = {p.o00, p.o01, p.o10, p.o11};
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (!((p.mask >> t) & 1)) continue;
+                    const float wt = w[t] * rW;
+                    if (slot >= 0) {
+                        float *c = reinterpret_cast<float *>(&acc[slot][off[t] - lo]);
+                        atomicAdd(c + 0, wt * g4.x);
+                        atomicAdd(c + 1, wt * g4.y);
+                        atomicAdd(c + 2, wt * g4.z);
+                        atomicAdd(c + 3, wt * g4.w);
+                    } else {
+                        float *pg = a.dtex + 4 * (eb + off[t]);
+                        unsafeAtomicAdd(pg + 0, wt * g4.x);
+                        unsafeAtomicAdd(pg + 1, wt * g4.y);
+                        unsafeAtomicAdd(pg + 2, wt * g4.z);
+                        unsafeAtomicAdd(pg + 3, wt * g4.w);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // flush the claimed slots
+    for (int t = 0; t < kSlots; ++t) {
+        const int32_t key = tag[t];
+        if (key < 0) continue;
+        const int32_t e = key >> 4, l = key & 15;
+        const int k = a.log2res[e];
+        const int cnt = 1 << (2 * (k - l));
+        float *dst = a.dtex + 4 * (a.base[e] + level_offset32(k, l));
+        const float *src = reinterpret_cast<const float *>(&acc[t][0]);
+        for (int i = threadIdx.x; i < 4 * cnt; i += kBlock) {
+            const float val = src[i];
+            if (val != 0.0f) unsafeAtomicAdd(dst + i, val);
+        }
+    }
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 template <int DT, bool TRI>
@@ -624,9 +737,18 @@ hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t
     }
 }
 
-hipError_t launch_backward(const SampleArgs &a, int filter, hipStream_t s)
+hipError_t launch_backward(const SampleArgs &a, int filter, uint32_t flags, hipStream_t s)
 {
     if (a.Q == 0) return hipSuccess;
+    if (flags & HTEX_QUERIES_SORTED) {
+        // sorted batches meet few textures per block: cache their gradients in LDS
+        const uint32_t G = (uint32_t)ceil_div(a.Q, kBwdChunk);
+        if (filter == HTEX_TRILINEAR)
+            hipLaunchKernelGGL((k_backward_lds<true>), dim3(G), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_backward_lds<false>), dim3(G), dim3(kBlock), 0, s, a);
+        return hipGetLastError();
+    }
     const uint32_t G = (uint32_t)ceil_div(a.Q, kBlock);
     if (filter == HTEX_TRILINEAR)
         hipLaunchKernelGGL((k_backward<true>), dim3(G), dim3(kBlock), 0, s, a);

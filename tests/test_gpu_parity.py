@@ -313,15 +313,23 @@ def test_quantized_trilinear_debug(dtype):
 
 # ------------------------------------------------------------ backward ---
 
+@pytest.mark.parametrize("flags", [0, htex.HTEX_QUERIES_SORTED])
 @pytest.mark.parametrize("filt", [htex.HTEX_BILINEAR, htex.HTEX_TRILINEAR])
-def test_backward_matches_oracle_gradient(filt):
+def test_backward_matches_oracle_gradient(filt, flags):
+    """Both scatter paths: plain float atomics, and (sorted batches) the
+    on-chip tile cache with one atomic per texel channel at the end; mixed
+    resolutions so that some levels fit the cache and some do not."""
     m = cube_mesh()
     mips = filt == htex.HTEX_TRILINEAR
-    s = Setup(m, np.full(m.E, 5 if mips else 4), has_mips=mips, kind=1)
+    lr = np.random.default_rng(5).integers(3, 7, m.E)
+    s = Setup(m, lr, has_mips=mips, kind=1)
     q = uniform_queries(m.H, 200000, 403, log2f=(-7, 0) if mips else None, sort=True)
+    q.h[:3] = [-1, m.H, 5]
+    q.u[2] = np.nan
     g = np.random.default_rng(404).standard_normal((q.Q, 4)).astype(np.float32)
     f = t(q.f) if q.f is not None else None
-    d = htex.htex_sample_backward(s.dmesh, s.pool, t(q.h), t(q.u), t(q.v), t(g), f, filter=filt)
+    d = htex.htex_sample_backward(s.dmesh, s.pool, t(q.h), t(q.u), t(q.v), t(g), f, filter=filt,
+                                  flags=flags)
     torch.cuda.synchronize()
     got = d.cpu().numpy().astype(np.float64)
     ref, dabs = oracle.backward(s.omesh, s.opool, q.h, q.u, q.v, g, q.f, filter=filt,
@@ -451,7 +459,8 @@ def test_backward_config4_full_size():
     s = Setup(m, np.full(m.E, 5), has_mips=False, kind=1, seed=401)
     q = uniform_queries(m.H, 3840 * 2160, 405, sort=True)
     g = np.random.default_rng(403).standard_normal((q.Q, 4)).astype(np.float32)
-    d = htex.htex_sample_backward(s.dmesh, s.pool, t(q.h), t(q.u), t(q.v), t(g))
+    d = htex.htex_sample_backward(s.dmesh, s.pool, t(q.h), t(q.u), t(q.v), t(g),
+                                  flags=htex.HTEX_QUERIES_SORTED)
     torch.cuda.synchronize()
     got = d.cpu().numpy().astype(np.float64)
     ref, dabs = oracle.backward(s.omesh, s.opool, q.h, q.u, q.v, g, with_abs=True)
