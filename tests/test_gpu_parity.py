@@ -466,3 +466,18 @@ def test_backward_config4_full_size():
     ref, dabs = oracle.backward(s.omesh, s.opool, q.h, q.u, q.v, g, with_abs=True)
     err = np.abs(got - ref)
     assert (err <= 1e-4 * dabs + 1e-12).all(), float((err / np.maximum(dabs, 1e-30)).max())
+
+
+def test_backward_sorted_flag_is_only_a_hint():
+    """The on-chip tile cache is correct for any order (unsorted batches just
+    overflow it more often)."""
+    m = cube_mesh()
+    s = Setup(m, np.full(m.E, 4), has_mips=False, kind=1)
+    q = uniform_queries(m.H, 100000, 7, shuffle_seed=8)
+    g = np.random.default_rng(9).standard_normal((q.Q, 4)).astype(np.float32)
+    d = htex.htex_sample_backward(s.dmesh, s.pool, t(q.h), t(q.u), t(q.v), t(g),
+                                  flags=htex.HTEX_QUERIES_SORTED)
+    torch.cuda.synchronize()
+    ref, dabs = oracle.backward(s.omesh, s.opool, q.h, q.u, q.v, g, with_abs=True)
+    err = np.abs(d.cpu().numpy().astype(np.float64) - ref)
+    assert (err <= 1e-4 * dabs + 1e-12).all()

@@ -100,3 +100,34 @@ def test_invalid_queries_in_requests(meshes):
     assert np.isnan(out[:3]).all() and np.isfinite(out[3:]).all()
     assert srv.stats()["invalid_queries"] == 3
     srv.close()
+
+
+@pytest.mark.parametrize("dtype", [htex.HTEX_F32, htex.HTEX_FP8_E4M3])
+def test_serving_other_storage_types(dtype):
+    m = cube_mesh(n=3, seed=4, n_split=3, n_merge=1)
+    s = Setup(m, np.full(m.E, 5), has_mips=True, kind=1, seed=77)
+    pool = s.pool if dtype == htex.HTEX_F32 else htex.htex_quantize(s.pool, dtype)
+    prep = htex.Prepared(s.dmesh, pool)
+    srv = Server(dtype, htex.HTEX_TRILINEAR, arena_bytes=1 << 24)
+    srv.add_mesh(prep, pool)
+    P = Server.pinned
+    rids, qs = [], []
+    for i in range(12):
+        q = uniform_queries(m.H, 1000 * (i + 1), 60 + i, log2f=(-6, 0))
+        qs.append(q)
+        rids.append(srv.submit(0, P(q.h, torch.int32), P(q.u, torch.float32),
+                               P(q.v, torch.float32), P(q.f, torch.float32)))
+    srv.drain(60)
+    for rid, q in zip(rids, qs):
+        o = htex.htex_sample_prepared(prep, pool, t(q.h), t(q.u), t(q.v), t(q.f),
+                                      filter=htex.HTEX_TRILINEAR)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(srv.result(rid).numpy(), o.cpu().numpy())
+    srv.close()
+
+
+def test_server_rejects_mismatched_pool(meshes):
+    srv = Server(htex.HTEX_F32, htex.HTEX_TRILINEAR)
+    with pytest.raises(htex.HtexError):
+        srv.add_mesh(meshes[0][2], meshes[0][1])     # a BF16 pool
+    srv.close()
