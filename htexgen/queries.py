@@ -1,4 +1,4 @@
-"""Seeded query batches: (halfedge h, barycentric (u, v), footprint f).
+"""Query batches: (halfedge h, barycentric (u, v), footprint f).
 
 h is uniform over [0, H); (u, v) is uniform over the triangle u, v >= 0,
 u + v <= 1 (two uniforms, folded when their sum exceeds 1), rounded to
@@ -47,3 +47,26 @@ def uniform_queries(H: int, Q: int, seed: int, log2f=None, sort: bool = False,
     elif shuffle_seed is not None:
         q = q.take(np.random.default_rng(shuffle_seed).permutation(Q))
     return q
+
+
+def tessellated_queries(H: int, T: int, footprint: float | None = None,
+                        halfedges=None) -> Queries:
+    """Vertex-stage queries of a uniformly tessellated intrinsic triangulation:
+    every halfedge's triangle (or those in `halfedges`) is cut into T^2
+    sub-triangles and each patch evaluates its (T+1)(T+2)/2 grid vertices
+    (u, v) = (i/T, j/T), i + j <= T, row by row (j outer), as a tessellator
+    emits them.  Vertices on patch borders are evaluated by every patch that
+    owns them.  `footprint` (quad units, e.g. 1/T for a filter as wide as a
+    sub-triangle) is stored for every query, or None for bilinear use.
+    For T a power of two every coordinate is exact in float32.
+    """
+    hs = np.arange(H, dtype=np.int32) if halfedges is None else np.asarray(halfedges, np.int32)
+    jj, ii = np.meshgrid(np.arange(T + 1), np.arange(T + 1), indexing="ij")
+    keep = (ii + jj) <= T
+    gi, gj = ii[keep], jj[keep]           # row-major over j, then i
+    P = len(gi)
+    h = np.repeat(hs, P)
+    u = np.tile((gi / T).astype(np.float32), len(hs))
+    v = np.tile((gj / T).astype(np.float32), len(hs))
+    f = None if footprint is None else np.full(len(h), footprint, np.float32)
+    return Queries(h, u, v, f)

@@ -37,6 +37,7 @@ class _Mesh(C.Structure):
 
 class _Pool(C.Structure):
     _fields_ = [("E", C.c_int32), ("has_mips", C.c_int32),
+                ("channels", C.c_int32), ("pad", C.c_int32),
                 ("log2res", C.c_void_p), ("base", C.c_void_p),
                 ("texels", C.c_void_p)]
 
@@ -73,6 +74,8 @@ def lib():
         L.ora_texture_fetch.restype = None
         L.ora_texture_fetch.argtypes = [p, C.c_int32, C.c_int, C.c_double, C.c_double,
                                         C.c_double, p, p]
+        L.ora_corner_average.restype = None
+        L.ora_corner_average.argtypes = [p, p, p, C.c_int32, C.c_int32, p, p]
         L.ora_validate.restype = C.c_int
         L.ora_validate.argtypes = [p, p, p]
         _lib = L
@@ -107,27 +110,31 @@ class Mesh:
 
 
 class Pool:
-    """Texel pool for the oracle: float64 [total, 4] plus per-edge layout."""
+    """Texel pool for the oracle: float64 [total, C] (C = 4 RGBA channels or
+    1, e.g. a displacement map) plus per-edge layout."""
 
     def __init__(self, log2res, base, texels, has_mips):
         self.log2res = _c(log2res, np.uint8)
         self.base = _c(base, np.int64)
         self.texels = _c(texels, np.float64)
+        if self.texels.ndim != 2 or self.texels.shape[1] not in (1, 4):
+            raise ValueError("texels must be [total, 4] or [total, 1]")
+        self.channels = int(self.texels.shape[1])
         self.has_mips = int(bool(has_mips))
         self.E = len(self.log2res)
-        self._s = _Pool(self.E, self.has_mips, _ptr(self.log2res), _ptr(self.base),
-                        _ptr(self.texels))
+        self._s = _Pool(self.E, self.has_mips, self.channels, 0, _ptr(self.log2res),
+                        _ptr(self.base), _ptr(self.texels))
 
 
 def sample(mesh: Mesh, pool: Pool, h, u, v, f=None, filter=BILINEAR,
            debug=False, nthreads=0):
-    """Alg. 3 for every query.  Returns (out float64 [Q,4], errors, debug)."""
+    """Alg. 3 for every query.  Returns (out float64 [Q, C], errors, debug)."""
     h = _c(h, np.int32)
     u = _c(u, np.float32)
     v = _c(v, np.float32)
     f = _c(f, np.float32)
     Q = len(h)
-    out = np.empty((Q, 4), dtype=np.float64)
+    out = np.empty((Q, pool.channels), dtype=np.float64)
     dbg = np.zeros(Q, dtype=DEBUG_DTYPE) if debug else None
     errs = lib().ora_sample(C.byref(mesh._s), C.byref(pool._s), Q, _ptr(h), _ptr(u),
                             _ptr(v), _ptr(f), int(filter), _ptr(out), _ptr(dbg),
@@ -181,7 +188,7 @@ def e4m3_pool_to_f64(log2res, base, has_mips, codes, scale):
     """float64 [total,4] texel values of an FP8 pool (decoded code x edge scale)."""
     c = np.ascontiguousarray(codes, dtype=np.uint8)
     s = np.ascontiguousarray(scale, dtype=np.float32)
-    p = Pool(log2res, base, np.zeros((1, 4)), has_mips)
+    p = Pool(log2res, base, np.zeros((1, c.shape[1])), has_mips)
     out = np.zeros(c.shape, dtype=np.float64)
     lib().ora_dequantize_e4m3(C.byref(p._s), _ptr(c), _ptr(s), _ptr(out))
     return out
@@ -200,13 +207,26 @@ def f64_to_e4m3(x) -> np.ndarray:
 
 
 def quantize_e4m3(log2res, base, has_mips, texels_f32):
-    """(codes uint8 [total,4], scale float32 [E]) for a float32 pool."""
+    """(codes uint8 [total, C], scale float32 [E]) for a float32 pool."""
     t = np.ascontiguousarray(texels_f32, dtype=np.float32)
-    p = Pool(log2res, base, np.zeros((1, 4)), has_mips)
+    p = Pool(log2res, base, np.zeros((1, t.shape[1])), has_mips)
     codes = np.zeros(t.shape, dtype=np.uint8)
     scale = np.zeros(p.E, dtype=np.float32)
     lib().ora_quantize_e4m3(C.byref(p._s), _ptr(t), t.shape[0], _ptr(codes), _ptr(scale))
     return codes, scale
+
+
+def corner_average(mesh: Mesh, pool: Pool, vert, face, V: int, F: int) -> np.ndarray:
+    """Section 4.4 corner pre-processing in FP64 (returns a copy of the
+    texels): corner texels on one mesh vertex or one face centroid take
+    their mean, per resolution n >= 2."""
+    tex = pool.texels.copy()
+    p2 = Pool(pool.log2res, pool.base, tex, pool.has_mips)
+    vt = _c(vert, np.int32)
+    fc = _c(face, np.int32)
+    lib().ora_corner_average(C.byref(mesh._s), _ptr(vt), _ptr(fc), int(V), int(F),
+                             C.byref(p2._s), _ptr(tex))
+    return tex
 
 
 def validate(mesh: Mesh):
@@ -218,9 +238,9 @@ def validate(mesh: Mesh):
 
 def texture_fetch(pool: Pool, e: int, x: float, y: float, f: float = 0.0,
                   filter=BILINEAR):
-    """One filtered fetch (Alg. 3's Texture): (colour float64[4], weight)."""
+    """One filtered fetch (Alg. 3's Texture): (colour float64[C], weight)."""
     out = np.zeros(4, dtype=np.float64)
     w = np.zeros(1, dtype=np.float64)
     lib().ora_texture_fetch(C.byref(pool._s), int(e), int(filter), float(f), float(x),
                             float(y), _ptr(out), _ptr(w))
-    return out, float(w[0])
+    return out[:pool.channels], float(w[0])

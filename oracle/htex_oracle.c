@@ -190,7 +190,8 @@ static void texture_fetch(const ora_pool *P, fetch_rec *F)
     for (int s = 0; s < F->nlev; ++s) {
         int l = F->lv[s];
         int64_t n = (int64_t)1 << (F->k - l);
-        const double *T = P->texels + 4 * (P->base[F->e] + level_offset(F->k, l));
+        const int C = P->channels;
+        const double *T = P->texels + C * (P->base[F->e] + level_offset(F->k, l));
         taps tp = level_taps(F->x, F->y, n);
         int mask = 0;
         for (int dj = 0; dj < 2; ++dj)
@@ -199,8 +200,8 @@ static void texture_fetch(const ora_pool *P, fetch_rec *F)
                 if (i < 0 || i >= n || j < 0 || j >= n)
                     continue;
                 double ow = F->om[s] * tap_weight(&tp, di, dj);
-                const double *t = T + 4 * (j * n + i);
-                for (int c = 0; c < 4; ++c)
+                const double *t = T + C * (j * n + i);
+                for (int c = 0; c < C; ++c)
                     F->C[c] += ow * t[c];
                 F->W += ow;
                 mask |= 1 << (dj * 2 + di);
@@ -231,11 +232,11 @@ static void htexture(const ora_mesh *M, const ora_pool *P, int filter, int32_t h
         R->k = P->log2res[R->e];
         R->nlev = lod_levels(filter, f, R->k, R->lv, R->om);
         texture_fetch(P, R);
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < P->channels; ++c)
             C[c] += R->C[c];
         W += R->W;
     }
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < P->channels; ++c)
         out[c] = C[c] / W;
     *Wtot = W;
 }
@@ -260,8 +261,8 @@ int64_t ora_sample(const ora_mesh *M, const ora_pool *P, int64_t Q, const int32_
     for (int64_t q = 0; q < Q; ++q) {
         ora_debug *d = dbg ? dbg + q : NULL;
         if (!query_valid(M, h[q], u[q], v[q])) {
-            for (int c = 0; c < 4; ++c)
-                out[4 * q + c] = NAN;
+            for (int c = 0; c < P->channels; ++c)
+                out[P->channels * q + c] = NAN;
             if (d) {
                 memset(d, 0, sizeof(*d));
                 d->next = d->prev = -1;
@@ -276,7 +277,7 @@ int64_t ora_sample(const ora_mesh *M, const ora_pool *P, int64_t Q, const int32_
         double f = fp ? (double)fp[q] : 0.0;
         fetch_rec F[3];
         double W = 0.0;
-        htexture(M, P, filter, h[q], (double)u[q], (double)v[q], f, F, out + 4 * q, &W);
+        htexture(M, P, filter, h[q], (double)u[q], (double)v[q], f, F, out + P->channels * q, &W);
         if (d) {
             d->next = F[1].g;
             d->prev = F[2].g;
@@ -303,7 +304,7 @@ int64_t ora_sample(const ora_mesh *M, const ora_pool *P, int64_t Q, const int32_
 /* The output of Alg. 3 is linear in the texels: out_c = sum over taps of
  * (om w / W) T_c.  The gradient of L with respect to a texel channel is the
  * sum, over every query and every in-bounds tap that reads it, of
- * (om w / W) dL/dout_c.  `dtex` (pool-shaped, 4 doubles per texel) is added
+ * (om w / W) dL/dout_c.  `dtex` (pool-shaped, one double per texel channel) is added
  * to; `dabs`, if given, receives the sum of the absolute values of the same
  * contributions (a scale for tolerances). */
 int64_t ora_backward(const ora_mesh *M, const ora_pool *P, int64_t Q, const int32_t *h,
@@ -335,11 +336,12 @@ int64_t ora_backward(const ora_mesh *M, const ora_pool *P, int64_t Q, const int3
                             continue;
                         double w = R->om[s] * tap_weight(&tp, di, dj) / W;
                         int64_t t = off + j * n + i;
-                        for (int c = 0; c < 4; ++c) {
-                            double gr = w * dout[4 * q + c];
-                            dtex[4 * t + c] += gr;
+                        const int C = P->channels;
+                        for (int c = 0; c < C; ++c) {
+                            double gr = w * dout[C * q + c];
+                            dtex[C * t + c] += gr;
                             if (dabs)
-                                dabs[4 * t + c] += fabs(gr);
+                                dabs[C * t + c] += fabs(gr);
                         }
                     }
             }
@@ -360,19 +362,92 @@ void ora_build_mips(const ora_pool *P, double *texels)
         int k = P->log2res[e];
         for (int l = 1; l <= k; ++l) {
             int64_t n = (int64_t)1 << (k - l);
-            double *src = texels + 4 * (P->base[e] + level_offset(k, l - 1));
-            double *dst = texels + 4 * (P->base[e] + level_offset(k, l));
+            const int C = P->channels;
+            double *src = texels + C * (P->base[e] + level_offset(k, l - 1));
+            double *dst = texels + C * (P->base[e] + level_offset(k, l));
             for (int64_t j = 0; j < n; ++j)
                 for (int64_t i = 0; i < n; ++i)
-                    for (int c = 0; c < 4; ++c) {
-                        double s = src[4 * ((2 * j) * (2 * n) + 2 * i) + c] +
-                                   src[4 * ((2 * j) * (2 * n) + 2 * i + 1) + c] +
-                                   src[4 * ((2 * j + 1) * (2 * n) + 2 * i) + c] +
-                                   src[4 * ((2 * j + 1) * (2 * n) + 2 * i + 1) + c];
-                        dst[4 * (j * n + i) + c] = 0.25 * s;
+                    for (int c = 0; c < C; ++c) {
+                        double s = src[C * ((2 * j) * (2 * n) + 2 * i) + c] +
+                                   src[C * ((2 * j) * (2 * n) + 2 * i + 1) + c] +
+                                   src[C * ((2 * j + 1) * (2 * n) + 2 * i) + c] +
+                                   src[C * ((2 * j + 1) * (2 * n) + 2 * i + 1) + c];
+                        dst[C * (j * n + i) + c] = 0.25 * s;
                     }
         }
     }
+}
+
+/* ------------------------------------------ corner pre-processing (Sec. 4.4) */
+
+/* Quad corners on the mesh.  The halfedge g of an edge with the larger id
+ * keeps its barycentric (u, v) as quad coordinates (Alg. 2), and Section 4.2
+ * puts Vert(g) at (u, v) = (1, 0) and Vert(Next(g)) at (0, 1); the third
+ * corner of its intrinsic triangle, the centroid of g's face (Alg. 1), is at
+ * (0, 0), and the twin's face centroid at (1, 1).  On a level of n texels
+ * per side these four points lie in the corner texels (i, j) = (n-1, 0),
+ * (0, n-1), (0, 0) and (n-1, n-1).
+ *
+ * The pre-processing of Section 4.4 makes every corner texel that lies on
+ * one mesh vertex, or on one face centroid, hold the same value: here the
+ * mean of those texels, taken separately for each resolution n >= 2 (levels
+ * of different edges with equal n are averaged together).  A 1x1 level is
+ * left alone: its one texel is all four corners at once.  A boundary quad
+ * mirrors its lower-left half, so its (n-1, n-1) corner is the image of its
+ * (0, 0) corner and takes the same value without being counted twice.
+ *
+ * vert[h] and face[h] give the vertex and face ids of each halfedge (V and F
+ * of them); the texels are updated in place. */
+void ora_corner_average(const ora_mesh *M, const int32_t *vert, const int32_t *face, int32_t V,
+                        int32_t F, const ora_pool *P, double *texels)
+{
+    int kmax = 0;
+    for (int32_t e = 0; e < P->E; ++e)
+        if (P->log2res[e] > kmax)
+            kmax = P->log2res[e];
+    const int64_t G = (int64_t)V + F;
+    const int C = P->channels;
+    double *sum = (double *)malloc(sizeof(double) * 4 * (size_t)(G > 0 ? G : 1));
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(G > 0 ? G : 1));
+    for (int r = 1; r <= kmax; ++r) {
+        const int64_t n = (int64_t)1 << r;
+        memset(sum, 0, sizeof(double) * 4 * (size_t)G);
+        memset(cnt, 0, sizeof(int64_t) * (size_t)G);
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int32_t g = 0; g < M->H; ++g) {
+                const int32_t t = M->twin[g];
+                if (!(g > t))
+                    continue; /* visit each edge once, through its larger halfedge */
+                const int32_t e = M->edge[g];
+                const int k = P->log2res[e];
+                const int l = k - r;
+                if (l < 0 || (l > 0 && !P->has_mips))
+                    continue;
+                const int64_t lv = P->base[e] + level_offset(k, l);
+                const int64_t at[4] = {lv + (n - 1), lv + (n - 1) * n, lv, lv + (n - 1) * n + n - 1};
+                const int64_t grp[4] = {vert[g], vert[M->next[g]], (int64_t)V + face[g],
+                                        t >= 0 ? (int64_t)V + face[t] : -1};
+                for (int c = 0; c < 4; ++c) {
+                    if (grp[c] < 0) {
+                        if (pass == 1) /* boundary mirror of the (0, 0) corner */
+                            for (int ch = 0; ch < C; ++ch)
+                                texels[C * at[3] + ch] = texels[C * at[2] + ch];
+                        continue;
+                    }
+                    if (pass == 0) {
+                        for (int ch = 0; ch < C; ++ch)
+                            sum[4 * grp[c] + ch] += texels[C * at[c] + ch];
+                        cnt[grp[c]] += 1;
+                    } else {
+                        for (int ch = 0; ch < C; ++ch)
+                            texels[C * at[c] + ch] = sum[4 * grp[c] + ch] / (double)cnt[grp[c]];
+                    }
+                }
+            }
+        }
+    }
+    free(sum);
+    free(cnt);
 }
 
 /* -------------------------------------------------------- quantization */
@@ -452,17 +527,18 @@ void ora_quantize_e4m3(const ora_pool *P, const float *src, int64_t total_texels
         int64_t cnt = 0;
         for (int l = 0; l <= (P->has_mips ? k : 0); ++l)
             cnt += (int64_t)1 << (2 * (k - l));
-        const float *t = src + 4 * P->base[e];
+        const int C = P->channels;
+        const float *t = src + C * P->base[e];
         float mx = 0.0f;
-        for (int64_t i = 0; i < 4 * cnt; ++i) {
+        for (int64_t i = 0; i < C * cnt; ++i) {
             float a = fabsf(t[i]);
             if (a > mx)
                 mx = a;
         }
         float s = mx / 448.0f;
         scale[e] = s;
-        uint8_t *o = codes + 4 * P->base[e];
-        for (int64_t i = 0; i < 4 * cnt; ++i) {
+        uint8_t *o = codes + C * P->base[e];
+        for (int64_t i = 0; i < C * cnt; ++i) {
             if (s == 0.0f) {
                 o[i] = 0;
                 continue;
@@ -548,7 +624,7 @@ void ora_dequantize_e4m3(const ora_pool *P, const uint8_t *codes, const float *s
         int64_t cnt = 0;
         for (int l = 0; l <= (P->has_mips ? k : 0); ++l)
             cnt += (int64_t)1 << (2 * (k - l));
-        for (int64_t i = 4 * P->base[e]; i < 4 * (P->base[e] + cnt); ++i)
+        for (int64_t i = P->channels * P->base[e]; i < P->channels * (P->base[e] + cnt); ++i)
             out[i] = ora_e4m3_to_f64(codes[i]) * (double)scale[e];
     }
 }
@@ -568,6 +644,6 @@ void ora_texture_fetch(const ora_pool *P, int32_t e, int filter, double f, doubl
     R.nlev = lod_levels(filter, f, R.k, R.lv, R.om);
     texture_fetch(P, &R);
     for (int c = 0; c < 4; ++c)
-        C[c] = R.C[c];
+        C[c] = c < P->channels ? R.C[c] : 0.0;
     *W = R.W;
 }

@@ -15,9 +15,11 @@ typedef struct {
 
 typedef struct {
     int32_t E, has_mips;
+    int32_t channels;        /* values per texel: 4 (RGBA) or 1          */
+    int32_t pad;
     const uint8_t *log2res;  /* [E] level-0 resolution 2^k             */
     const int64_t *base;     /* [E] texel offset of level 0 of edge e   */
-    const double *texels;    /* [total][4] RGBA, levels fine to coarse   */
+    const double *texels;    /* [total][channels], levels fine to coarse */
 } ora_pool;
 
 /* Per-query trace of the three fetches (s = own, Next, Prev; l = level slot). */
@@ -53,5 +55,7 @@ void ora_dequantize_e4m3(const ora_pool *P, const uint8_t *codes, const float *s
                          double *out);
 void ora_texture_fetch(const ora_pool *P, int32_t e, int filter, double f, double x,
                        double y, double C[4], double *W);
+void ora_corner_average(const ora_mesh *M, const int32_t *vert, const int32_t *face, int32_t V,
+                        int32_t F, const ora_pool *P, double *texels);
 int ora_validate(const ora_mesh *M, const int32_t *vert, int32_t *first_bad);
 #endif
