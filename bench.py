@@ -256,6 +256,71 @@ def grad_benchmark(steps=200):
             "loss_curve_every_20": losses}
 
 
+# ---------------------------------------------------------- displacement --
+
+def displacement_benchmark(mesh, dmesh, rgb_step, Q_rgb, T=4, n_iter=10):
+    """The paper's "RGB + disp" configuration on the frame mesh: besides the
+    4K fragment batch (RGBA, trilinear), a vertex stage tessellates every
+    intrinsic triangle into T^2 sub-triangles and reads a one-channel 64x64
+    float32 displacement map per edge at each patch vertex (bilinear, level
+    0), with corners pre-processed so the displaced surface has no cracks.
+    Reports the one-off corner pass, the vertex stage alone, and the frame
+    with and without it."""
+    import numpy as np
+    import torch
+
+    import paper_2207_05618_amd as htex
+    from htexgen import device as gdev
+    from htexgen.queries import tessellated_queries
+
+    lr = np.full(mesh.E, 6, np.uint8)
+    disp = htex.Pool(lr, False, htex.HTEX_F32, channels=1)
+    gdev.fill_level0(disp.texels, 1, 501, disp.log2res, disp.base, mesh.boundary_edges())
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    htex.htex_corner_average(dmesh, disp)
+    e1.record()
+    torch.cuda.synchronize()
+    corner_ms = e0.elapsed_time(e1)
+    prep = htex.Prepared(dmesh, disp)
+    q = tessellated_queries(mesh.H, T)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    h, u, v = dev(q.h), dev(q.u), dev(q.v)
+    out = torch.empty((q.Q, 1), dtype=torch.float32, device="cuda")
+
+    def disp_step():
+        htex.htex_sample_prepared(prep, disp, h, u, v, None, filter=htex.HTEX_BILINEAR,
+                                  flags=htex.HTEX_QUERIES_SORTED, out=out)
+
+    def timed(fn):
+        for i in range(3):
+            fn(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n_iter):
+            fn(i)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n_iter
+
+    t_disp = timed(lambda i: disp_step())
+    t_rgb = timed(rgb_step)
+
+    def both(i):
+        disp_step()
+        rgb_step(i)
+
+    t_both = timed(both)
+    res = {"tessellation": T, "vertex_queries": int(q.Q), "fragment_queries": int(Q_rgb),
+           "displacement_pool_bytes": disp.nbytes(), "corner_preprocess_ms": corner_ms,
+           "vertex_stage_ms": t_disp * 1e3,
+           "vertex_samples_per_s": q.Q / t_disp, "rgb_only_ms": t_rgb * 1e3,
+           "rgb_plus_disp_ms": t_both * 1e3, "rgb_plus_disp_over_rgb": t_both / t_rgb}
+    del disp, prep, h, u, v, out
+    torch.cuda.empty_cache()
+    return res
+
+
 # -------------------------------------------------------------- serving --
 
 def _gen_sphere(args):
@@ -571,6 +636,9 @@ def main():
         for kk in list(extra):
             extra[kk.replace("samples_per_s", "speedup_vs_f32")] = extra[kk] / value
         log(f"extra {json.dumps({k: round(v, 3) for k, v in extra.items()})}")
+        if args.workload == "frame4k":
+            extra["rgb_plus_displacement"] = displacement_benchmark(mesh, dmesh, step, Q)
+            log(f"rgb+disp {json.dumps(extra['rgb_plus_displacement'])}")
 
     roofline = None
     alg = None

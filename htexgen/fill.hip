@@ -30,7 +30,7 @@ __device__ __forceinline__ uint64_t hash5(uint64_t seed, uint64_t a, uint64_t b,
 __constant__ int32_t kRamp[8] = {1, 6, 14, 25, 39, 50, 58, 63};
 
 __global__ void k_fill(int kind, uint64_t seed, int32_t E, const uint8_t *log2res,
-                       const int64_t *base, const uint8_t *boundary, float4 *tex)
+                       const int64_t *base, const uint8_t *boundary, float *tex, int channels)
 {
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         const int k = log2res[e];
@@ -44,7 +44,7 @@ __global__ void k_fill(int kind, uint64_t seed, int32_t E, const uint8_t *log2re
                 sj = n - 1 - i;
             }
             float vals[4];
-            for (int c = 0; c < 4; ++c) {
+            for (int c = 0; c < channels; ++c) {
                 if (kind == 0) {
                     const uint64_t hv = hash5(seed, (uint64_t)e, (uint64_t)(sj * n + si), (uint64_t)c, 0);
                     vals[c] = (float)(int32_t)(hv >> 40) * 0x1p-24f;
@@ -60,21 +60,24 @@ __global__ void k_fill(int kind, uint64_t seed, int32_t E, const uint8_t *log2re
                     vals[c] = (float)num * 0x1p-18f;
                 }
             }
-            tex[base[e] + t] = make_float4(vals[0], vals[1], vals[2], vals[3]);
+            for (int c = 0; c < channels; ++c) tex[channels * (base[e] + t) + c] = vals[c];
         }
     }
 }
 
 }  // namespace
 
+// texels: float32 [total][channels]; a one-channel pool receives channel 0
+// of the four-channel values.
 extern "C" int htexgen_fill_level0(int kind, uint64_t seed, int32_t E, const uint8_t *log2res,
                                    const int64_t *base, const uint8_t *boundary, float *texels,
-                                   void *stream)
+                                   int channels, void *stream)
 {
     if (E <= 0) return 0;
     if (kind != 0 && kind != 1) return -1;
+    if (channels != 1 && channels != 4) return -1;
     const uint32_t grid = (uint32_t)(E < (1 << 20) ? E : (1 << 20));
     hipLaunchKernelGGL(k_fill, dim3(grid), dim3(256), 0, static_cast<hipStream_t>(stream), kind,
-                       seed, E, log2res, base, boundary, reinterpret_cast<float4 *>(texels));
+                       seed, E, log2res, base, boundary, texels, channels);
     return hipGetLastError() == hipSuccess ? 0 : -4;
 }

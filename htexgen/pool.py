@@ -34,10 +34,11 @@ def layout(log2res, has_mips: bool, align: int = ALIGN):
 
 
 def fill_level0_host(kind: int, seed: int, log2res, base, total: int,
-                     boundary, has_mips: bool, edges=None) -> np.ndarray:
-    """float32 [total, 4] pool with level 0 of every edge (or of `edges`) filled;
-    mip levels and padding are left at zero."""
-    pool = np.zeros((total, 4), dtype=np.float32)
+                     boundary, has_mips: bool, edges=None, channels: int = 4) -> np.ndarray:
+    """float32 [total, channels] pool with level 0 of every edge (or of
+    `edges`) filled; mip levels and padding are left at zero.  A one-channel
+    pool holds channel 0 of the four-channel values."""
+    pool = np.zeros((total, channels), dtype=np.float32)
     log2res = np.asarray(log2res)
     es = np.arange(len(log2res)) if edges is None else np.asarray(edges)
     for k in np.unique(log2res[es]):
@@ -52,7 +53,7 @@ def fill_level0_host(kind: int, seed: int, log2res, base, total: int,
             E_ = chunk[:, None, None]
             vals = texel_values(kind, seed, E_, n, boundary[chunk][:, None, None],
                                 ii[None, :, None], jj[None, :, None],
-                                np.arange(4)[None, None, :])
+                                np.arange(channels)[None, None, :])
             rows = base[chunk][:, None] + (jj * n + ii)[None, :]
-            pool[rows.reshape(-1)] = vals.reshape(-1, 4)
+            pool[rows.reshape(-1)] = vals.reshape(-1, channels)
     return pool

@@ -64,11 +64,13 @@ typedef int32_t htex_status;
 #define HTEX_E_BUSY (-6)         /* resource in use (serving)                 */
 #define HTEX_E_NOMEM (-7)        /* memory budget exhausted (serving)         */
 
-/* texel storage */
-#define HTEX_F32 0        /* float32 RGBA, 16 bytes per texel                  */
-#define HTEX_BF16 1       /* bfloat16 RGBA, 8 bytes per texel                  */
-#define HTEX_FP8_E4M3 2   /* OCP E4M3 (no infinities, max 448) RGBA, 4 bytes  */
-                          /* per texel, times a float32 scale per edge         */
+/* texel storage, per channel (a texel holds 4 channels, RGBA, or 1, e.g. a
+ * displacement map) */
+#define HTEX_F32 0        /* float32: 16 bytes per RGBA texel, 4 per scalar     */
+#define HTEX_BF16 1       /* bfloat16: 8 bytes per RGBA texel, 2 per scalar     */
+#define HTEX_FP8_E4M3 2   /* OCP E4M3 (no infinities, max 448): 4 bytes per    */
+                          /* RGBA texel, 1 per scalar, times a float32 scale   */
+                          /* per edge                                          */
 /* filters */
 #define HTEX_BILINEAR 0
 #define HTEX_TRILINEAR 1
@@ -86,16 +88,21 @@ typedef struct htex_mesh {
 /* Per-edge texel pool.  Edge e's texels start at texel index base[e] (a
  * multiple of 16); its levels follow each other from level 0 (n x n) down to
  * level k (1 x 1) when has_mips, level 0 only otherwise; each level is
- * row-major (texel (i, j) at j * n + i), 4 channels per texel.  Level l of an
- * edge of log2 resolution k starts (4^(k+1) - 4^(k+1-l)) / 3 texels after
- * base[e].  htex_pool_layout computes a valid base[] (host).
- * texels: 16-byte aligned for HTEX_F32, 8 for HTEX_BF16, 4 for HTEX_FP8_E4M3.
- * scale: FP8 only, float32 [E], texel value = decoded code * scale[e]. */
+ * row-major (texel (i, j) at j * n + i), `channels` values per texel.  Level
+ * l of an edge of log2 resolution k starts (4^(k+1) - 4^(k+1-l)) / 3 texels
+ * after base[e].  htex_pool_layout computes a valid base[] (host).
+ * texels: aligned to one texel's bytes (16 / 8 / 4 for RGBA float32 / BF16 /
+ * FP8; 4 / 2 / 1 for one channel).
+ * scale: FP8 only, float32 [E], texel value = decoded code * scale[e].
+ * Results (and gradients of results) have `channels` floats per query:
+ * Alg. 3 filters every channel with the same weights and normalization. */
 typedef struct htex_pool {
     int32_t E;
     int32_t dtype;         /* HTEX_F32 / HTEX_BF16 / HTEX_FP8_E4M3 */
     int32_t has_mips;      /* 0 or 1 */
     int32_t max_log2res;   /* max over log2res[] (host-known bound, <= 15) */
+    int32_t channels;      /* 4 (RGBA) or 1 */
+    int32_t reserved;      /* 0 */
     int64_t total_texels;  /* size of the pool in texels */
     const uint8_t *log2res;   /* [E] */
     const int64_t *base;      /* [E] */
@@ -156,12 +163,35 @@ htex_status htex_mesh_validate(const htex_mesh *mesh, int32_t *first_bad_host,
 
 /* Box-filtered mip chain, in place: for every edge and l = 1..k, texel (i, j)
  * of level l becomes the mean of texels (2i..2i+1, 2j..2j+1) of level l-1,
- * in float32.  The pool must be HTEX_F32 with has_mips = 1; `texels_rw` is
+ * in float32, channel by channel.  The pool must be HTEX_F32 with has_mips = 1; `texels_rw` is
  * the same memory as pool->texels, writable. */
 htex_status htex_build_mips(const htex_pool *pool, void *texels_rw, void *stream);
 
+/* Corner pre-processing (Section 4.4, "Corner Pre-processing"), in place on
+ * a float32 pool: on every level of n >= 2 texels per side, the corner
+ * texels that lie on one mesh vertex, or on one face centroid, all receive
+ * the mean of their values (computed in float64, rounded once to float32);
+ * levels of different edges are grouped by equal n.  With one resolution
+ * everywhere, filtering is then continuous at vertices and face centroids
+ * too (the seams are continuous already), which displacement needs to stay
+ * crack-free; 1x1 levels (one texel = four corners) are left unchanged.
+ * Corner texels of the quad of edge e, whose larger halfedge g keeps its
+ * barycentric (u, v) as quad coordinates (Alg. 2): (n-1, 0) at Vert(g),
+ * (0, n-1) at Vert(Next g), (0, 0) at the centroid of g's face, (n-1, n-1)
+ * at the centroid of the twin's face -- or, for a boundary edge, the mirror
+ * image of (0, 0), written with the same value.  Vertices and faces are
+ * found from the halfedge operators alone (rings of Twin(Prev g) and of
+ * Next), so the mesh must be valid; a ring longer than 65536 halfedges or
+ * one that leaves [0, H) increments *err_count (device, nullable) and is
+ * left unchanged.  Run it after htex_build_mips (rebuilding the mips would
+ * undo it on the coarser levels) and before quantizing (BF16 keeps equal
+ * values equal; FP8's per-edge scales do not).  `texels_rw` is the same
+ * memory as pool->texels, writable. */
+htex_status htex_corner_average(const htex_mesh *mesh, const htex_pool *pool, void *texels_rw,
+                                int32_t *err_count, void *stream);
+
 /* Converts a float32 pool to `dtype` into `dst` (same layout, same base[],
- * total_texels texels).  HTEX_BF16: round to nearest even.  HTEX_FP8_E4M3:
+ * same channels, total_texels texels).  HTEX_BF16: round to nearest even.  HTEX_FP8_E4M3:
  * per-edge scale s = (max |T| over every level and channel of the edge) / 448
  * computed in float32 and written to scale_out[e]; code = E4M3 of the
  * float32 quotient T / s, rounded to nearest even and saturated to +-448; an
@@ -170,8 +200,8 @@ htex_status htex_build_mips(const htex_pool *pool, void *texels_rw, void *stream
 htex_status htex_quantize(const htex_pool *src_f32, int32_t dtype, void *dst,
                           float *scale_out, void *stream);
 
-/* Alg. 3 for every query (Section 4.4) -> out[q][0..3] (float32, 16-byte
- * aligned, Q x 4).  filter: HTEX_BILINEAR (level 0, footprint ignored) or
+/* Alg. 3 for every query (Section 4.4) -> out[q][0..C) (float32, Q x C for
+ * a pool of C channels, aligned to 4 C bytes).  filter: HTEX_BILINEAR (level 0, footprint ignored) or
  * HTEX_TRILINEAR (needs has_mips and a footprint array).  Colour is blended
  * and normalized in float32 whatever the storage type.  debug (nullable):
  * Q records.  err_count (nullable, device int32): incremented once per
@@ -184,12 +214,13 @@ htex_status htex_sample(const htex_mesh *mesh, const htex_pool *pool,
 /* Transpose of htex_sample with respect to the texels: for every valid query
  * and every in-bounds tap it reads, dtexels[tap][c] += (om w / W) * dout[q][c]
  * (om: level weight, w: bilinear weight, W: the query's normalization).
- * dtexels is float32 with the pool's layout (16-byte aligned) and is added
- * to, with float32 atomics (summation order unspecified); the pool must be
- * HTEX_F32.  dout is float32 Q x 4 (16-byte aligned).  With
- * HTEX_QUERIES_SORTED, each workgroup first sums its consecutive queries'
- * contributions to small textures (at most 32 x 32 texels per level) in
- * on-chip memory and adds each texel once (fewer, uncontended atomics). */
+ * dtexels is float32 with the pool's layout and channels (aligned to 4 C
+ * bytes) and is added to, with float32 atomics (summation order
+ * unspecified); the pool must be HTEX_F32.  dout is float32 Q x C (aligned
+ * to 4 C bytes).  With HTEX_QUERIES_SORTED, each workgroup first sums its
+ * consecutive queries' contributions to small textures (at most 32 x 32
+ * RGBA or 64 x 64 one-channel texels per level) in on-chip memory and adds
+ * each texel once (fewer, uncontended atomics). */
 htex_status htex_sample_backward(const htex_mesh *mesh, const htex_pool *pool,
                                  const htex_queries *queries, int32_t filter,
                                  uint32_t flags, const float *dout, float *dtexels,
@@ -293,7 +324,8 @@ typedef struct htex_server_stats {
 htex_status htex_server_create(const htex_server_config *cfg, htex_server **out);
 
 /* Registers a resident mesh: its prepared records (htex_prepare, H records)
- * and its pool (dtype must match the server's; trilinear needs mips).  The
+ * and its pool (dtype must match the server's; trilinear needs mips; RGBA
+ * pools only).  The
  * device memory stays owned by the caller and must outlive the server.  Up
  * to max_meshes calls; *mesh_id receives 0, 1, ... */
 htex_status htex_server_add_mesh(htex_server *srv, int32_t H, const void *prep,

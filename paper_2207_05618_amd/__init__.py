@@ -18,7 +18,7 @@ from ._lib import (DEBUG_FIELDS, HTEX_BF16, HTEX_BILINEAR, HTEX_F32, HTEX_FP8_E4
                    HTEX_QUERIES_SORTED, HTEX_TRILINEAR, HtexError, check, load)
 
 __all__ = ["Mesh", "Pool", "htex_pool_layout", "htex_mesh_validate", "htex_build_mips",
-           "htex_quantize", "htex_sample", "htex_sample_backward", "HtexSample",
+           "htex_corner_average", "htex_quantize", "htex_sample", "htex_sample_backward", "HtexSample",
            "htex_prepare", "htex_sample_prepared", "Prepared",
            "htex_sort_queries", "htex_permute_queries", "htex_unpermute_results",
            "debug_records", "HtexError"]
@@ -73,16 +73,19 @@ def htex_pool_layout(log2res, has_mips: bool):
 class Pool:
     """Per-edge texel pool on the device (layout of htex.h).
 
-    texels: float32 [total, 4] (HTEX_F32), int16 [total, 4] holding bfloat16
-    bits (HTEX_BF16) or uint8 [total, 4] holding E4M3 codes (HTEX_FP8_E4M3,
-    with float32 scale [E])."""
+    texels: float32 [total, C] (HTEX_F32), int16 [total, C] holding bfloat16
+    bits (HTEX_BF16) or uint8 [total, C] holding E4M3 codes (HTEX_FP8_E4M3,
+    with float32 scale [E]); C = 4 (RGBA) or 1 (e.g. displacement)."""
 
     def __init__(self, log2res, has_mips: bool, dtype: int = HTEX_F32, texels=None,
-                 scale=None, device="cuda"):
+                 scale=None, device="cuda", channels: int = 4):
         lr = np.ascontiguousarray(log2res, dtype=np.uint8)
         self.E = len(lr)
         self.has_mips = bool(has_mips)
         self.dtype = int(dtype)
+        if channels not in (1, 4):
+            raise ValueError("channels must be 1 or 4")
+        self.channels = int(channels)
         self.max_log2res = int(lr.max()) if self.E else 0
         base, total = htex_pool_layout(lr, has_mips)
         self.base_host = base
@@ -91,10 +94,11 @@ class Pool:
         self.log2res = torch.as_tensor(lr).to(device)
         self.base = torch.as_tensor(base).to(device)
         if texels is None:
-            texels = torch.zeros((total, 4), dtype=_TEXEL_TORCH[self.dtype], device=device)
+            texels = torch.zeros((total, self.channels), dtype=_TEXEL_TORCH[self.dtype],
+                                 device=device)
         self.texels = _dev(texels, _TEXEL_TORCH[self.dtype], "texels")
-        if self.texels.shape != (total, 4):
-            raise ValueError(f"texels must have shape ({total}, 4)")
+        if self.texels.shape != (total, self.channels):
+            raise ValueError(f"texels must have shape ({total}, {self.channels})")
         self.scale = scale
         if self.dtype == HTEX_FP8_E4M3:
             self.scale = _dev(scale, torch.float32, "scale") if scale is not None else \
@@ -103,7 +107,8 @@ class Pool:
 
     def _sync_c(self):
         self.c = _lib.htex_pool(self.E, self.dtype, int(self.has_mips), self.max_log2res,
-                                self.total, self.log2res.data_ptr(), self.base.data_ptr(),
+                                self.channels, 0, self.total, self.log2res.data_ptr(),
+                                self.base.data_ptr(),
                                 self.texels.data_ptr(),
                                 self.scale.data_ptr() if self.scale is not None else None)
 
@@ -125,9 +130,20 @@ def htex_build_mips(pool: Pool, stream=None):
     check(load().htex_build_mips(C.byref(pool.c), pool.texels.data_ptr(), _stream(stream)))
 
 
+def htex_corner_average(mesh: Mesh, pool: Pool, err_count: torch.Tensor | None = None,
+                        stream=None):
+    """Corner pre-processing (Section 4.4) of a float32 pool, in place: corner
+    texels on one mesh vertex or one face centroid take their mean, on every
+    level of at least 2x2 texels.  Run after htex_build_mips."""
+    err = None if err_count is None else _dev(err_count, torch.int32, "err_count").data_ptr()
+    check(load().htex_corner_average(C.byref(mesh.c), C.byref(pool.c), pool.texels.data_ptr(),
+                                     err, _stream(stream)))
+
+
 def htex_quantize(pool: Pool, dtype: int, stream=None) -> Pool:
     """New pool holding `pool` (float32) converted to HTEX_BF16 or HTEX_FP8_E4M3."""
-    q = Pool(pool.log2res_host, pool.has_mips, dtype, device=pool.texels.device)
+    q = Pool(pool.log2res_host, pool.has_mips, dtype, device=pool.texels.device,
+             channels=pool.channels)
     scale_ptr = q.scale.data_ptr() if q.scale is not None else None
     check(load().htex_quantize(C.byref(pool.c), int(dtype), q.texels.data_ptr(), scale_ptr,
                                _stream(stream)))
@@ -150,10 +166,10 @@ def _queries(h, u, v, footprint):
 
 def htex_sample(mesh: Mesh, pool: Pool, h, u, v, footprint=None, filter=HTEX_BILINEAR,
                 flags=0, out=None, debug=False, err_count=None, stream=None):
-    """Alg. 3 for every query -> (out float32 [Q, 4], debug int32 [Q, 40] or None)."""
+    """Alg. 3 for every query -> (out float32 [Q, C], debug int32 [Q, 40] or None)."""
     q, Q = _queries(h, u, v, footprint)
     if out is None:
-        out = torch.empty((Q, 4), dtype=torch.float32, device=h.device)
+        out = torch.empty((Q, pool.channels), dtype=torch.float32, device=h.device)
     _dev(out, torch.float32, "out")
     dbg = torch.zeros((Q, 40), dtype=torch.int32, device=h.device) if debug else None
     if err_count is not None:
@@ -184,10 +200,10 @@ def htex_prepare(mesh: Mesh, pool: Pool, prep: "Prepared", stream=None):
 def htex_sample_prepared(prep: "Prepared", pool: Pool, h, u, v, footprint=None,
                          filter=HTEX_BILINEAR, flags=0, out=None, err_count=None,
                          stream=None):
-    """htex_sample from prepared records (bit-identical results) -> out [Q, 4]."""
+    """htex_sample from prepared records (bit-identical results) -> out [Q, C]."""
     q, Q = _queries(h, u, v, footprint)
     if out is None:
-        out = torch.empty((Q, 4), dtype=torch.float32, device=h.device)
+        out = torch.empty((Q, pool.channels), dtype=torch.float32, device=h.device)
     _dev(out, torch.float32, "out")
     if err_count is not None:
         _dev(err_count, torch.int32, "err_count")
@@ -258,7 +274,7 @@ def htex_sample_backward(mesh: Mesh, pool: Pool, h, u, v, dout, footprint=None,
 class HtexSample(torch.autograd.Function):
     """Differentiable sampling with respect to a float32 pool's texels.
 
-    forward(texels, mesh, pool, h, u, v, footprint, filter, flags) -> [Q, 4];
+    forward(texels, mesh, pool, h, u, v, footprint, filter, flags) -> [Q, C];
     the gradient flows to `texels` (which must be pool.texels)."""
 
     @staticmethod

@@ -32,7 +32,8 @@ class htex_mesh(C.Structure):
 
 class htex_pool(C.Structure):
     _fields_ = [("E", C.c_int32), ("dtype", C.c_int32), ("has_mips", C.c_int32),
-                ("max_log2res", C.c_int32), ("total_texels", C.c_int64),
+                ("max_log2res", C.c_int32), ("channels", C.c_int32), ("reserved", C.c_int32),
+                ("total_texels", C.c_int64),
                 ("log2res", C.c_void_p), ("base", C.c_void_p),
                 ("texels", C.c_void_p), ("scale", C.c_void_p)]
 
@@ -56,6 +57,7 @@ SIGNATURES = {
     "htex_pool_layout": (C.c_int32, [C.c_int32, _P, C.c_int32, _P, _P]),
     "htex_mesh_validate": (C.c_int32, [_P, _P, _P]),
     "htex_build_mips": (C.c_int32, [_P, _P, _P]),
+    "htex_corner_average": (C.c_int32, [_P, _P, _P, _P, _P]),
     "htex_quantize": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
     "htex_sample": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_uint32, _P, _P, _P, _P]),
     "htex_sample_backward": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_uint32, _P, _P, _P]),

@@ -50,12 +50,13 @@ htex_status from_hip(hipError_t e, const char *what)
 
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
-size_t texel_bytes(int32_t dtype)
+// Bytes of one stored texel (all channels), 0 for an unknown dtype.
+size_t texel_bytes(int32_t dtype, int32_t channels)
 {
     switch (dtype) {
-    case HTEX_F32: return 16;
-    case HTEX_BF16: return 8;
-    case HTEX_FP8_E4M3: return 4;
+    case HTEX_F32: return 4 * (size_t)channels;
+    case HTEX_BF16: return 2 * (size_t)channels;
+    case HTEX_FP8_E4M3: return (size_t)channels;
     default: return 0;
     }
 }
@@ -75,7 +76,10 @@ htex_status check_pool(const htex_pool *p, const htex_mesh *m)
     if (!p) return fail(HTEX_E_ARG, "pool is NULL");
     if (m && p->E != m->E) return fail(HTEX_E_ARG, "pool has %d edges, mesh has %d", p->E, m->E);
     if (p->E < 0 || p->total_texels < 0) return fail(HTEX_E_ARG, "negative pool size");
-    const size_t tb = texel_bytes(p->dtype);
+    if (p->channels != 1 && p->channels != 4)
+        return fail(HTEX_E_ARG, "channels must be 1 or 4, got %d", p->channels);
+    if (p->reserved != 0) return fail(HTEX_E_ARG, "pool->reserved must be 0");
+    const size_t tb = texel_bytes(p->dtype, p->channels);
     if (!tb) return fail(HTEX_E_ARG, "unknown texel dtype %d", p->dtype);
     if (p->has_mips != 0 && p->has_mips != 1) return fail(HTEX_E_ARG, "has_mips must be 0 or 1");
     if (p->max_log2res < 0 || p->max_log2res > 15)
@@ -119,6 +123,7 @@ htex::SampleArgs make_args(const htex_mesh *m, const htex_pool *p, const htex_qu
     a.qu = q->u;
     a.qv = q->v;
     a.qf = q->footprint;
+    a.channels = p->channels;
     return a;
 }
 
@@ -201,8 +206,25 @@ htex_status htex_build_mips(const htex_pool *pool, void *texels_rw, void *stream
     if (texels_rw != pool->texels) return fail(HTEX_E_ARG, "texels_rw must be pool->texels");
     return from_hip(htex::launch_build_mips(static_cast<float *>(texels_rw), pool->log2res,
                                             pool->base, pool->E, pool->max_log2res,
-                                            static_cast<hipStream_t>(stream)),
+                                            pool->channels, static_cast<hipStream_t>(stream)),
                     "mip build");
+}
+
+htex_status htex_corner_average(const htex_mesh *mesh, const htex_pool *pool, void *texels_rw,
+                                int32_t *err_count, void *stream)
+{
+    htex_status st = check_mesh(mesh);
+    if (!st) st = check_pool(pool, mesh);
+    if (st) return st;
+    if (pool->dtype != HTEX_F32)
+        return fail(HTEX_E_UNSUPPORTED, "corners are averaged on float32 pools");
+    if (texels_rw != pool->texels) return fail(HTEX_E_ARG, "texels_rw must be pool->texels");
+    return from_hip(htex::launch_corner_average(*mesh, static_cast<float *>(texels_rw),
+                                                pool->log2res, pool->base, pool->channels,
+                                                pool->has_mips,
+                                                pool->max_log2res, err_count,
+                                                static_cast<hipStream_t>(stream)),
+                    "corner average");
 }
 
 htex_status htex_quantize(const htex_pool *src, int32_t dtype, void *dst, float *scale_out,
@@ -213,20 +235,23 @@ htex_status htex_quantize(const htex_pool *src, int32_t dtype, void *dst, float 
     if (src->dtype != HTEX_F32) return fail(HTEX_E_ARG, "quantize reads a float32 pool");
     if (!dst && src->total_texels > 0) return fail(HTEX_E_ARG, "dst is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const int C = src->channels;
     if (dtype == HTEX_BF16) {
-        if (!aligned(dst, 8)) return fail(HTEX_E_ARG, "dst must be 8-byte aligned");
+        if (!aligned(dst, texel_bytes(HTEX_BF16, C)))
+            return fail(HTEX_E_ARG, "dst must be %zu-byte aligned", texel_bytes(HTEX_BF16, C));
         return from_hip(htex::launch_quantize_bf16(static_cast<const float *>(src->texels),
                                                    static_cast<uint16_t *>(dst),
-                                                   src->total_texels * 4, s),
+                                                   src->total_texels * C, s),
                         "bf16 quantize");
     }
     if (dtype == HTEX_FP8_E4M3) {
-        if (!aligned(dst, 4)) return fail(HTEX_E_ARG, "dst must be 4-byte aligned");
+        if (!aligned(dst, texel_bytes(HTEX_FP8_E4M3, C)))
+            return fail(HTEX_E_ARG, "dst must be %zu-byte aligned", texel_bytes(HTEX_FP8_E4M3, C));
         if (!scale_out && src->E > 0) return fail(HTEX_E_ARG, "scale_out is NULL");
         return from_hip(htex::launch_quantize_fp8(static_cast<const float *>(src->texels),
                                                   static_cast<uint8_t *>(dst), scale_out,
                                                   src->log2res, src->base, src->E,
-                                                  src->has_mips, src->total_texels, s),
+                                                  src->has_mips, C, src->total_texels, s),
                         "fp8 quantize");
     }
     return fail(HTEX_E_ARG, "quantize target must be HTEX_BF16 or HTEX_FP8_E4M3");
@@ -243,8 +268,9 @@ htex_status htex_sample(const htex_mesh *mesh, const htex_pool *pool, const htex
     if (flags & ~HTEX_QUERIES_SORTED) return fail(HTEX_E_ARG, "unknown flags 0x%x", flags);
     if (filter == HTEX_TRILINEAR && !pool->has_mips)
         return fail(HTEX_E_ARG, "trilinear filtering needs a pool with mips");
-    if (queries->Q > 0 && (!out || !aligned(out, 16)))
-        return fail(HTEX_E_ARG, "out must be non-NULL and 16-byte aligned");
+    const size_t row = 4 * (size_t)pool->channels;   // bytes of one result row
+    if (queries->Q > 0 && (!out || !aligned(out, row)))
+        return fail(HTEX_E_ARG, "out must be non-NULL and %zu-byte aligned", row);
     if (debug && !aligned(debug, 4)) return fail(HTEX_E_ARG, "debug must be 4-byte aligned");
     if (queries->Q > 0 && mesh->H == 0) return fail(HTEX_E_ARG, "queries on an empty mesh");
     htex::SampleArgs a = make_args(mesh, pool, queries);
@@ -267,10 +293,12 @@ htex_status htex_sample_backward(const htex_mesh *mesh, const htex_pool *pool,
     if (pool->dtype != HTEX_F32) return fail(HTEX_E_UNSUPPORTED, "gradients need a float32 pool");
     if (filter == HTEX_TRILINEAR && !pool->has_mips)
         return fail(HTEX_E_ARG, "trilinear filtering needs a pool with mips");
+    const size_t row = 4 * (size_t)pool->channels;
     if (queries->Q > 0) {
-        if (!dout || !aligned(dout, 16)) return fail(HTEX_E_ARG, "dout must be 16-byte aligned");
-        if (!dtexels || !aligned(dtexels, 16))
-            return fail(HTEX_E_ARG, "dtexels must be 16-byte aligned");
+        if (!dout || !aligned(dout, row))
+            return fail(HTEX_E_ARG, "dout must be %zu-byte aligned", row);
+        if (!dtexels || !aligned(dtexels, row))
+            return fail(HTEX_E_ARG, "dtexels must be %zu-byte aligned", row);
         if (mesh->H == 0) return fail(HTEX_E_ARG, "queries on an empty mesh");
     }
     htex::SampleArgs a = make_args(mesh, pool, queries);
@@ -354,10 +382,12 @@ htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *p
     if (queries->Q > 0) {
         if (H == 0) return fail(HTEX_E_ARG, "queries on an empty mesh");
         if (!prep || !aligned(prep, 16)) return fail(HTEX_E_ARG, "prep must be 16-byte aligned");
-        if (!out || !aligned(out, 16)) return fail(HTEX_E_ARG, "out must be 16-byte aligned");
+        if (!out || !aligned(out, 4 * (size_t)pool->channels))
+            return fail(HTEX_E_ARG, "out must be %d-byte aligned", 4 * pool->channels);
     }
     htex::SampleArgs a{};
     a.H = H;
+    a.channels = pool->channels;
     a.texels = pool->texels;
     a.scale = pool->scale;
     a.Q = queries->Q;

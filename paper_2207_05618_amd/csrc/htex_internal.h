@@ -24,12 +24,13 @@ struct SampleArgs {
     int64_t Q;
     const int32_t *qh;
     const float *qu, *qv, *qf;
-    float *out;                 // forward: [Q][4]
+    float *out;                 // forward: [Q][channels]
     htex_debug_rec *dbg;        // forward, nullable
     int32_t *err;               // forward, nullable
-    const float *dout;          // backward: [Q][4]
+    const float *dout;          // backward: [Q][channels]
     float *dtex;                // backward: pool-shaped float32
     const void *prep;           // prepared descriptors (fast path), nullable
+    int32_t channels;           // values per texel and per output row: 4 or 1
 };
 
 // Offset of mip level l inside an edge of log2 resolution k, in texels:
@@ -75,12 +76,15 @@ hipError_t launch_backward(const SampleArgs &a, int filter, uint32_t flags, hipS
 hipError_t launch_prepare(const SampleArgs &a, void *prep, hipStream_t s);
 hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, hipStream_t s);
 hipError_t launch_build_mips(float *texels, const uint8_t *log2res, const int64_t *base,
-                             int32_t E, int max_k, hipStream_t s);
+                             int32_t E, int max_k, int channels, hipStream_t s);
 hipError_t launch_quantize_bf16(const float *src, uint16_t *dst, int64_t count,
                                 hipStream_t s);
 hipError_t launch_quantize_fp8(const float *src, uint8_t *dst, float *scale,
                                const uint8_t *log2res, const int64_t *base, int32_t E,
-                               int has_mips, int64_t total_texels, hipStream_t s);
+                               int has_mips, int channels, int64_t total_texels, hipStream_t s);
+hipError_t launch_corner_average(const htex_mesh &m, float *texels, const uint8_t *log2res,
+                                 const int64_t *base, int channels, int has_mips, int kmax,
+                                 int32_t *err, hipStream_t s);
 hipError_t launch_validate(const htex_mesh &m, int32_t *ws_use, int32_t *ws_bad,
                            hipStream_t s);
 

@@ -1,5 +1,6 @@
 // htex_prep.hip -- per-pool and per-mesh preparation kernels: box-filtered
-// mip chains, BF16 / FP8-E4M3 quantization, halfedge validation.
+// mip chains, BF16 / FP8-E4M3 quantization, halfedge validation.  Pools hold
+// 4 channels per texel (RGBA) or 1 (a scalar map such as displacement).
 #include <hip/hip_runtime.h>
 
 #include "htex_internal.h"
@@ -9,9 +10,21 @@ namespace {
 
 // Level l of every edge with k >= l, from level l-1: the mean of each 2x2
 // block.  One workgroup per edge (grid-stride), threads over the level's
-// texels.
-__global__ void k_mip_level(float4 *tex, const uint8_t *log2res, const int64_t *base,
-                            int32_t E, int l)
+// texels.  T is float4 (RGBA texels) or float (one channel).
+__device__ __forceinline__ float4 box4(const float4 &p, const float4 &q, const float4 &r,
+                                       const float4 &s)
+{
+    return make_float4(0.25f * ((p.x + q.x) + (r.x + s.x)), 0.25f * ((p.y + q.y) + (r.y + s.y)),
+                       0.25f * ((p.z + q.z) + (r.z + s.z)), 0.25f * ((p.w + q.w) + (r.w + s.w)));
+}
+
+__device__ __forceinline__ float box4(float p, float q, float r, float s)
+{
+    return 0.25f * ((p + q) + (r + s));
+}
+
+template <typename T>
+__global__ void k_mip_level(T *tex, const uint8_t *log2res, const int64_t *base, int32_t E, int l)
 {
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         const int k = log2res[e];
@@ -24,10 +37,7 @@ __global__ void k_mip_level(float4 *tex, const uint8_t *log2res, const int64_t *
             const int32_t i = t & (n - 1), j = t >> m;
             const int64_t r0 = src + (int64_t)(2 * j) * (2 * n) + 2 * i;
             const int64_t r1 = r0 + 2 * n;
-            const float4 p = tex[r0], q = tex[r0 + 1], r = tex[r1], s = tex[r1 + 1];
-            tex[dst + (int64_t)j * n + i] =
-                make_float4(0.25f * ((p.x + q.x) + (r.x + s.x)), 0.25f * ((p.y + q.y) + (r.y + s.y)),
-                            0.25f * ((p.z + q.z) + (r.z + s.z)), 0.25f * ((p.w + q.w) + (r.w + s.w)));
+            tex[dst + (int64_t)j * n + i] = box4(tex[r0], tex[r0 + 1], tex[r1], tex[r1 + 1]);
         }
     }
 }
@@ -76,17 +86,18 @@ __device__ __forceinline__ uint8_t to_e4m3(float x)
     return (uint8_t)(sgn | code);
 }
 
-// One workgroup per edge: max |T| over all of the edge's texels, scale =
-// max / 448 (float32), then the codes of T / scale.
+// One workgroup per edge: max |T| over all of the edge's texel channels,
+// scale = max / 448 (float32), then the codes of T / scale.
 __global__ void __launch_bounds__(256) k_quant_fp8(const float *src, uint8_t *dst, float *scale,
                                                    const uint8_t *log2res, const int64_t *base,
-                                                   int32_t E, int has_mips)
+                                                   int32_t E, int has_mips, int channels)
 {
     __shared__ float red[256];
     for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
         const int k = log2res[e];
-        const int64_t cnt = 4 * (has_mips ? ((int64_t(4) << (2 * k)) - 1) / 3 : (int64_t(1) << (2 * k)));
-        const float *t = src + 4 * base[e];
+        const int64_t cnt =
+            channels * (has_mips ? ((int64_t(4) << (2 * k)) - 1) / 3 : (int64_t(1) << (2 * k)));
+        const float *t = src + channels * base[e];
         float mx = 0.0f;
         for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) mx = fmaxf(mx, fabsf(t[i]));
         red[threadIdx.x] = mx;
@@ -98,7 +109,7 @@ __global__ void __launch_bounds__(256) k_quant_fp8(const float *src, uint8_t *ds
         const float s = red[0] / 448.0f;
         __syncthreads();
         if (threadIdx.x == 0) scale[e] = s;
-        uint8_t *o = dst + 4 * base[e];
+        uint8_t *o = dst + channels * base[e];
         for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x)
             o[i] = (s == 0.0f) ? (uint8_t)0 : to_e4m3(t[i] / s);
     }
@@ -138,14 +149,18 @@ __global__ void k_validate2(htex_mesh m, const int32_t *use, int32_t *bad, int32
 }  // namespace
 
 hipError_t launch_build_mips(float *texels, const uint8_t *log2res, const int64_t *base,
-                             int32_t E, int max_k, hipStream_t s)
+                             int32_t E, int max_k, int channels, hipStream_t s)
 {
     if (E == 0) return hipSuccess;
     for (int l = 1; l <= max_k; ++l) {
         const int threads = (max_k - l) >= 4 ? 256 : 64;
         const uint32_t grid = (uint32_t)(E < (1 << 20) ? E : (1 << 20));
-        hipLaunchKernelGGL(k_mip_level, dim3(grid), dim3(threads), 0, s,
-                           reinterpret_cast<float4 *>(texels), log2res, base, E, l);
+        if (channels == 4)
+            hipLaunchKernelGGL(k_mip_level<float4>, dim3(grid), dim3(threads), 0, s,
+                               reinterpret_cast<float4 *>(texels), log2res, base, E, l);
+        else
+            hipLaunchKernelGGL(k_mip_level<float>, dim3(grid), dim3(threads), 0, s, texels,
+                               log2res, base, E, l);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
@@ -162,14 +177,14 @@ hipError_t launch_quantize_bf16(const float *src, uint16_t *dst, int64_t count, 
 }
 
 hipError_t launch_quantize_fp8(const float *src, uint8_t *dst, float *scale, const uint8_t *log2res,
-                               const int64_t *base, int32_t E, int has_mips, int64_t total_texels,
-                               hipStream_t s)
+                               const int64_t *base, int32_t E, int has_mips, int channels,
+                               int64_t total_texels, hipStream_t s)
 {
-    hipError_t err = hipMemsetAsync(dst, 0, (size_t)total_texels * 4, s);
+    hipError_t err = hipMemsetAsync(dst, 0, (size_t)total_texels * channels, s);
     if (err != hipSuccess || E == 0) return err;
     const uint32_t grid = (uint32_t)(E < (1 << 20) ? E : (1 << 20));
     hipLaunchKernelGGL(k_quant_fp8, dim3(grid), dim3(256), 0, s, src, dst, scale, log2res, base, E,
-                       has_mips);
+                       has_mips, channels);
     return hipGetLastError();
 }
 

@@ -54,23 +54,36 @@ __device__ __forceinline__ AxisTaps axis_taps(float c, bool neg, int rho, int m)
     return o;
 }
 
-template <int DT>
-__device__ __forceinline__ float4 load_texel(const void *tex, int64_t idx)
+// One texel widened to float32: CH = 4 channels (RGBA) or 1 (a scalar map,
+// returned in .x with the other lanes zero).
+template <int DT, int CH>
+__device__ __forceinline__ float4 load_texel(const char *p)
 {
-    // idx counts texels from `tex`
-    if constexpr (DT == HTEX_F32) {
-        return reinterpret_cast<const float4 *>(tex)[idx];
-    } else if constexpr (DT == HTEX_BF16) {
-        const uint2 p = reinterpret_cast<const uint2 *>(tex)[idx];
-        return make_float4(__uint_as_float(p.x << 16), __uint_as_float(p.x & 0xffff0000u),
-                           __uint_as_float(p.y << 16), __uint_as_float(p.y & 0xffff0000u));
+    if constexpr (CH == 4) {
+        if constexpr (DT == HTEX_F32) {
+            return *reinterpret_cast<const float4 *>(p);
+        } else if constexpr (DT == HTEX_BF16) {
+            const uint2 b = *reinterpret_cast<const uint2 *>(p);
+            return make_float4(__uint_as_float(b.x << 16), __uint_as_float(b.x & 0xffff0000u),
+                               __uint_as_float(b.y << 16), __uint_as_float(b.y & 0xffff0000u));
+        } else {
+            // OCP E4M3 -> float32 with gfx950's packed converter (exact for
+            // all 256 codes, subnormals and NaN included)
+            const int b = *reinterpret_cast<const int *>(p);
+            const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(b, false);
+            const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(b, true);
+            return make_float4(lo[0], lo[1], hi[0], hi[1]);
+        }
     } else {
-        // OCP E4M3 -> float32 with gfx950's packed converter (exact for all
-        // 256 codes, subnormals and NaN included)
-        const int p = reinterpret_cast<const int *>(tex)[idx];
-        const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8(p, false);
-        const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8(p, true);
-        return make_float4(lo[0], lo[1], hi[0], hi[1]);
+        float x;
+        if constexpr (DT == HTEX_F32) {
+            x = *reinterpret_cast<const float *>(p);
+        } else if constexpr (DT == HTEX_BF16) {
+            x = __uint_as_float((uint32_t)*reinterpret_cast<const uint16_t *>(p) << 16);
+        } else {
+            x = __builtin_amdgcn_cvt_f32_fp8((int)*reinterpret_cast<const uint8_t *>(p), 0);
+        }
+        return make_float4(x, 0.0f, 0.0f, 0.0f);
     }
 }
 
@@ -159,10 +172,9 @@ __device__ __forceinline__ uint32_t level_offset32(int k, int l)
     return ones << (2 * (k - l) + 2);
 }
 
-template <int DT> struct TexelBytes;
-template <> struct TexelBytes<HTEX_F32> { static constexpr int v = 16; };
-template <> struct TexelBytes<HTEX_BF16> { static constexpr int v = 8; };
-template <> struct TexelBytes<HTEX_FP8_E4M3> { static constexpr int v = 4; };
+template <int DT, int CH> struct TexelBytes {
+    static constexpr int v = (DT == HTEX_F32 ? 4 : DT == HTEX_BF16 ? 2 : 1) * CH;
+};
 
 // One mip level of one fetch, planned before any texel is read: the
 // bilinear taps (i0 + di, j0 + dj), their weights with the level weight `om`
@@ -207,15 +219,23 @@ __device__ __forceinline__ LevelPlan plan_level(int k, int l, float om, const Fe
     return p;
 }
 
+template <int CH>
 __device__ __forceinline__ void accumulate(const LevelPlan &p, const float4 &t00, const float4 &t01,
                                            const float4 &t10, const float4 &t11, float4 &Cf,
                                            float &Wf)
 {
     const float w00 = p.wx0 * p.wy0, w01 = p.wx1 * p.wy0, w10 = p.wx0 * p.wy1, w11 = p.wx1 * p.wy1;
-    Cf.x += w00 * t00.x; Cf.y += w00 * t00.y; Cf.z += w00 * t00.z; Cf.w += w00 * t00.w;
-    Cf.x += w01 * t01.x; Cf.y += w01 * t01.y; Cf.z += w01 * t01.z; Cf.w += w01 * t01.w;
-    Cf.x += w10 * t10.x; Cf.y += w10 * t10.y; Cf.z += w10 * t10.z; Cf.w += w10 * t10.w;
-    Cf.x += w11 * t11.x; Cf.y += w11 * t11.y; Cf.z += w11 * t11.z; Cf.w += w11 * t11.w;
+    if constexpr (CH == 4) {
+        Cf.x += w00 * t00.x; Cf.y += w00 * t00.y; Cf.z += w00 * t00.z; Cf.w += w00 * t00.w;
+        Cf.x += w01 * t01.x; Cf.y += w01 * t01.y; Cf.z += w01 * t01.z; Cf.w += w01 * t01.w;
+        Cf.x += w10 * t10.x; Cf.y += w10 * t10.y; Cf.z += w10 * t10.z; Cf.w += w10 * t10.w;
+        Cf.x += w11 * t11.x; Cf.y += w11 * t11.y; Cf.z += w11 * t11.z; Cf.w += w11 * t11.w;
+    } else {
+        Cf.x += w00 * t00.x;
+        Cf.x += w01 * t01.x;
+        Cf.x += w10 * t10.x;
+        Cf.x += w11 * t11.x;
+    }
     Wf += (p.wx0 + p.wx1) * (p.wy0 + p.wy1);
 }
 
@@ -228,26 +248,26 @@ struct Resolved {
     const char *ep;
 };
 
-template <int DT>
+template <int DT, int CH>
 __device__ __forceinline__ Resolved resolve_plain(const SampleArgs &a, int32_t g)
 {
     Resolved r;
     r.flip = !(g > a.twin[g]);
     r.e = a.edge[g];
     r.k = a.log2res[r.e];
-    r.ep = static_cast<const char *>(a.texels) + a.base[r.e] * TexelBytes<DT>::v;
+    r.ep = static_cast<const char *>(a.texels) + a.base[r.e] * TexelBytes<DT, CH>::v;
     return r;
 }
 
 // One of Alg. 3's fetches: Texture(Edge(g), TriangleToQuadUV(g, <x, y>)),
 // colour and normalization channel.  Both mip levels are planned first and
 // read under a single branch, so their eight loads are in flight together.
-template <int DT, bool TRI, bool DBG>
+template <int DT, int CH, bool TRI, bool DBG>
 __device__ __forceinline__ void fetch(const SampleArgs &a, const Lod &L, const FetchSpec &f,
                                       const Resolved &R, float4 &Cf, float &Wf,
                                       htex_debug_rec *d, int s)
 {
-    constexpr int TB = TexelBytes<DT>::v;
+    constexpr int TB = TexelBytes<DT, CH>::v;
     const int k = R.k;
     const bool flip = R.flip;
     const char *ep = R.ep;
@@ -261,26 +281,28 @@ __device__ __forceinline__ void fetch(const SampleArgs &a, const Lod &L, const F
         p1.act = p1.act & (nlev == 2);
     }
     if (p0.act | (TRI && p1.act)) {
-        const float4 t00 = load_texel<DT>(ep + (uint64_t)p0.o00 * TB, 0);
-        const float4 t01 = load_texel<DT>(ep + (uint64_t)p0.o01 * TB, 0);
-        const float4 t10 = load_texel<DT>(ep + (uint64_t)p0.o10 * TB, 0);
-        const float4 t11 = load_texel<DT>(ep + (uint64_t)p0.o11 * TB, 0);
+        const float4 t00 = load_texel<DT, CH>(ep + (uint64_t)p0.o00 * TB);
+        const float4 t01 = load_texel<DT, CH>(ep + (uint64_t)p0.o01 * TB);
+        const float4 t10 = load_texel<DT, CH>(ep + (uint64_t)p0.o10 * TB);
+        const float4 t11 = load_texel<DT, CH>(ep + (uint64_t)p0.o11 * TB);
         if constexpr (TRI) {
-            const float4 u00 = load_texel<DT>(ep + (uint64_t)p1.o00 * TB, 0);
-            const float4 u01 = load_texel<DT>(ep + (uint64_t)p1.o01 * TB, 0);
-            const float4 u10 = load_texel<DT>(ep + (uint64_t)p1.o10 * TB, 0);
-            const float4 u11 = load_texel<DT>(ep + (uint64_t)p1.o11 * TB, 0);
-            if (p0.act) accumulate(p0, t00, t01, t10, t11, Cf, Wf);
-            if (p1.act) accumulate(p1, u00, u01, u10, u11, Cf, Wf);
+            const float4 u00 = load_texel<DT, CH>(ep + (uint64_t)p1.o00 * TB);
+            const float4 u01 = load_texel<DT, CH>(ep + (uint64_t)p1.o01 * TB);
+            const float4 u10 = load_texel<DT, CH>(ep + (uint64_t)p1.o10 * TB);
+            const float4 u11 = load_texel<DT, CH>(ep + (uint64_t)p1.o11 * TB);
+            if (p0.act) accumulate<CH>(p0, t00, t01, t10, t11, Cf, Wf);
+            if (p1.act) accumulate<CH>(p1, u00, u01, u10, u11, Cf, Wf);
         } else {
-            accumulate(p0, t00, t01, t10, t11, Cf, Wf);
+            accumulate<CH>(p0, t00, t01, t10, t11, Cf, Wf);
         }
         if constexpr (DT == HTEX_FP8_E4M3) {
             const float sc = a.scale[R.e];
             Cf.x *= sc;
-            Cf.y *= sc;
-            Cf.z *= sc;
-            Cf.w *= sc;
+            if constexpr (CH == 4) {
+                Cf.y *= sc;
+                Cf.z *= sc;
+                Cf.w *= sc;
+            }
         }
     }
     if constexpr (DBG) {
@@ -309,20 +331,40 @@ struct alignas(16) PrepRec {
 };
 static_assert(sizeof(PrepRec) == HTEX_PREP_BYTES, "record size");
 
-template <int DT>
+template <int DT, int CH>
 __device__ __forceinline__ Resolved resolve_prepared(const SampleArgs &a, uint64_t w, int32_t e)
 {
     Resolved r;
     r.e = e;
     r.k = (int)((w >> 40) & 31u);
     r.flip = ((w >> 45) & 1u) != 0;
-    r.ep = static_cast<const char *>(a.texels) + (int64_t)(w & 0xffffffffffull) * TexelBytes<DT>::v;
+    r.ep = static_cast<const char *>(a.texels) +
+           (int64_t)(w & 0xffffffffffull) * TexelBytes<DT, CH>::v;
     return r;
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <int DT, bool TRI, bool DBG>
+// Result row q (CH floats), streamed past the caches.
+template <int CH>
+__device__ __forceinline__ void store_row(float *out, int64_t q, float x, float y, float z, float w)
+{
+    if constexpr (CH == 4) {
+        const f32x4 v = {x, y, z, w};
+        __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(out) + q);
+    } else {
+        __builtin_nontemporal_store(x, out + q);
+    }
+}
+
+template <int CH>
+__device__ __forceinline__ float4 load_row(const float *in, int64_t q)
+{
+    if constexpr (CH == 4) return reinterpret_cast<const float4 *>(in)[q];
+    else return make_float4(in[q], 0.0f, 0.0f, 0.0f);
+}
+
+template <int DT, int CH, bool TRI, bool DBG>
 __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a)
 {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -331,11 +373,9 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a)
     const int32_t h = __builtin_nontemporal_load(a.qh + q);
     const float u = __builtin_nontemporal_load(a.qu + q);
     const float v = __builtin_nontemporal_load(a.qv + q);
-    f32x4 *out4 = reinterpret_cast<f32x4 *>(a.out);
     if (!((uint32_t)h < (uint32_t)a.H) || !isfinite(u) || !isfinite(v)) {
         const float nan = __uint_as_float(0x7fc00000u);
-        const f32x4 nv = {nan, nan, nan, nan};
-        __builtin_nontemporal_store(nv, out4 + q);
+        store_row<CH>(a.out, q, nan, nan, nan, nan);
         if (a.err) atomicAdd(a.err, 1);
         if constexpr (DBG) {
             htex_debug_rec d = {};
@@ -367,7 +407,7 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a)
     for (int s = 0; s < 3; ++s) {
         float4 Cf = make_float4(0.f, 0.f, 0.f, 0.f);
         float Wf = 0.0f;
-        fetch<DT, TRI, DBG>(a, L, fs[s], resolve_plain<DT>(a, fs[s].g), Cf, Wf, &d, s);
+        fetch<DT, CH, TRI, DBG>(a, L, fs[s], resolve_plain<DT, CH>(a, fs[s].g), Cf, Wf, &d, s);
         C.x += Cf.x;
         C.y += Cf.y;
         C.z += Cf.z;
@@ -375,8 +415,7 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a)
         W += Wf;
     }
     const float r = __builtin_amdgcn_rcpf(W);
-    const f32x4 ov = {C.x * r, C.y * r, C.z * r, C.w * r};
-    __builtin_nontemporal_store(ov, out4 + q);
+    store_row<CH>(a.out, q, C.x * r, C.y * r, C.z * r, C.w * r);
     if constexpr (DBG) {
         d.W = W;
         a.dbg[q] = d;
@@ -387,17 +426,15 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a)
 // one prepared record per query (bit-identical results).  Shared by the
 // batch kernel and the serving kernel, so a query's result does not depend
 // on which launch, batch or tile computes it.
-template <int DT, bool TRI>
+template <int DT, int CH, bool TRI>
 __device__ __forceinline__ void sample_one_prepared(const SampleArgs &a, int64_t q)
 {
     const int32_t h = __builtin_nontemporal_load(a.qh + q);
     const float u = __builtin_nontemporal_load(a.qu + q);
     const float v = __builtin_nontemporal_load(a.qv + q);
-    f32x4 *out4 = reinterpret_cast<f32x4 *>(a.out);
     if (!((uint32_t)h < (uint32_t)a.H) || !isfinite(u) || !isfinite(v)) {
         const float nan = __uint_as_float(0x7fc00000u);
-        const f32x4 nv = {nan, nan, nan, nan};
-        __builtin_nontemporal_store(nv, out4 + q);
+        store_row<CH>(a.out, q, nan, nan, nan, nan);
         if (a.err) atomicAdd(a.err, 1);
         return;
     }
@@ -412,8 +449,8 @@ __device__ __forceinline__ void sample_one_prepared(const SampleArgs &a, int64_t
     for (int s = 0; s < 3; ++s) {
         float4 Cf = make_float4(0.f, 0.f, 0.f, 0.f);
         float Wf = 0.0f;
-        fetch<DT, TRI, false>(a, L, fs[s], resolve_prepared<DT>(a, rec.w[s], rec.e[s]), Cf, Wf,
-                              nullptr, s);
+        fetch<DT, CH, TRI, false>(a, L, fs[s], resolve_prepared<DT, CH>(a, rec.w[s], rec.e[s]),
+                                  Cf, Wf, nullptr, s);
         C.x += Cf.x;
         C.y += Cf.y;
         C.z += Cf.z;
@@ -421,16 +458,15 @@ __device__ __forceinline__ void sample_one_prepared(const SampleArgs &a, int64_t
         W += Wf;
     }
     const float r = __builtin_amdgcn_rcpf(W);
-    const f32x4 ov = {C.x * r, C.y * r, C.z * r, C.w * r};
-    __builtin_nontemporal_store(ov, out4 + q);
+    store_row<CH>(a.out, q, C.x * r, C.y * r, C.z * r, C.w * r);
 }
 
-template <int DT, bool TRI>
+template <int DT, int CH, bool TRI>
 __global__ void __launch_bounds__(kBlock) k_sample_prep(SampleArgs a)
 {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q >= a.Q) return;
-    sample_one_prepared<DT, TRI>(a, q);
+    sample_one_prepared<DT, CH, TRI>(a, q);
 }
 
 // Serving: one launch covers a list of tiles, each up to kBlock queries of
@@ -456,7 +492,7 @@ __global__ void __launch_bounds__(kBlock) k_serve(const ServeMesh *meshes, const
             a.qf = T.f;
             a.out = T.out;
             a.err = err;
-            sample_one_prepared<DT, TRI>(a, T.q0 + threadIdx.x);
+            sample_one_prepared<DT, 4, TRI>(a, T.q0 + threadIdx.x);
         }
     }
 }
@@ -485,7 +521,7 @@ __global__ void __launch_bounds__(kBlock) k_prepare(SampleArgs a, PrepRec *out)
 // Backward: out_c = sum over taps (om w / W) T_c, so dL/dT_c at each tap
 // receives (om w / W) dL/dout_c.  First the normalization W (weights only,
 // no texel reads), then the scatter with float32 atomics.
-template <bool TRI>
+template <int CH, bool TRI>
 __global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
 {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -523,7 +559,7 @@ __global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
                 }
         }
     }
-    const float4 g4 = reinterpret_cast<const float4 *>(a.dout)[q];
+    const float4 g4 = load_row<CH>(a.dout, q);
     const float r = 1.0f / W;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
@@ -543,11 +579,13 @@ __global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
                     if ((uint32_t)i < (uint32_t)n && (uint32_t)j < (uint32_t)n) {
                         const float w =
                             om[sl] * ((di ? X.w1 : X.w0) * (dj ? Y.w1 : Y.w0)) * r;
-                        float *p = a.dtex + 4 * (lvb + (int64_t)j * n + i);
+                        float *p = a.dtex + CH * (lvb + (int64_t)j * n + i);
                         unsafeAtomicAdd(p + 0, w * g4.x);
-                        unsafeAtomicAdd(p + 1, w * g4.y);
-                        unsafeAtomicAdd(p + 2, w * g4.z);
-                        unsafeAtomicAdd(p + 3, w * g4.w);
+                        if constexpr (CH == 4) {
+                            unsafeAtomicAdd(p + 1, w * g4.y);
+                            unsafeAtomicAdd(p + 2, w * g4.z);
+                            unsafeAtomicAdd(p + 3, w * g4.w);
+                        }
                     }
                 }
         }
@@ -557,22 +595,23 @@ __global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
 // Backward with a per-workgroup cache of gradient tiles in LDS.  A block
 // takes kBwdChunk consecutive queries (sorted queries meet few textures
 // there) and accumulates each tap into an LDS slot holding one (edge, level)
-// of at most kSlotTexels texels; slots are claimed on first use by a
+// of at most kSlotFloats / CH texels; slots are claimed on first use by a
 // compare-and-swap on their tag and flushed to the gradient pool once, with
 // one float atomic per non-zero texel channel.  Taps of levels that are too
 // large, or that find every slot taken, go straight to global atomics.
 constexpr int kSlots = 4;
-constexpr int kSlotTexels = 1024;
+constexpr int kSlotFloats = 4096;
 constexpr int kBwdPerThread = 16;
 constexpr int kBwdChunk = kBlock * kBwdPerThread;
 
-template <bool TRI>
+template <int CH, bool TRI>
 __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
 {
-    __shared__ float4 acc[kSlots][kSlotTexels];
+    constexpr int kSlotTexels = kSlotFloats / CH;
+    __shared__ float acc[kSlots][kSlotFloats];
     __shared__ int32_t tag[kSlots];   // edge * 16 + level, or -1
-    float *accf = reinterpret_cast<float *>(&acc[0][0]);
-    for (int i = threadIdx.x; i < kSlots * kSlotTexels * 4; i += kBlock) accf[i] = 0.0f;
+    float *accf = &acc[0][0];
+    for (int i = threadIdx.x; i < kSlots * kSlotFloats; i += kBlock) accf[i] = 0.0f;
     if (threadIdx.x < kSlots) tag[threadIdx.x] = -1;
     __syncthreads();
     const int64_t q0 = (int64_t)blockIdx.x * kBwdChunk;
@@ -604,7 +643,7 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
                 W += (p.wx0 + p.wx1) * (p.wy0 + p.wy1);
             }
         }
-        const float4 g4 = reinterpret_cast<const float4 *>(a.dout)[q];
+        const float4 g4 = load_row<CH>(a.dout, q);
         const float rW = 1.0f / W;
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
@@ -634,17 +673,21 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
                     if (!((p.mask >> t) & 1)) continue;
                     const float wt = w[t] * rW;
                     if (slot >= 0) {
-                        float *c = reinterpret_cast<float *>(&acc[slot][off[t] - lo]);
+                        float *c = &acc[slot][CH * (off[t] - lo)];
                         atomicAdd(c + 0, wt * g4.x);
-                        atomicAdd(c + 1, wt * g4.y);
-                        atomicAdd(c + 2, wt * g4.z);
-                        atomicAdd(c + 3, wt * g4.w);
+                        if constexpr (CH == 4) {
+                            atomicAdd(c + 1, wt * g4.y);
+                            atomicAdd(c + 2, wt * g4.z);
+                            atomicAdd(c + 3, wt * g4.w);
+                        }
                     } else {
-                        float *pg = a.dtex + 4 * (eb + off[t]);
+                        float *pg = a.dtex + CH * (eb + off[t]);
                         unsafeAtomicAdd(pg + 0, wt * g4.x);
-                        unsafeAtomicAdd(pg + 1, wt * g4.y);
-                        unsafeAtomicAdd(pg + 2, wt * g4.z);
-                        unsafeAtomicAdd(pg + 3, wt * g4.w);
+                        if constexpr (CH == 4) {
+                            unsafeAtomicAdd(pg + 1, wt * g4.y);
+                            unsafeAtomicAdd(pg + 2, wt * g4.z);
+                            unsafeAtomicAdd(pg + 3, wt * g4.w);
+                        }
                     }
                 }
             }
@@ -658,9 +701,9 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
         const int32_t e = key >> 4, l = key & 15;
         const int k = a.log2res[e];
         const int cnt = 1 << (2 * (k - l));
-        float *dst = a.dtex + 4 * (a.base[e] + level_offset32(k, l));
-        const float *src = reinterpret_cast<const float *>(&acc[t][0]);
-        for (int i = threadIdx.x; i < 4 * cnt; i += kBlock) {
+        float *dst = a.dtex + CH * (a.base[e] + level_offset32(k, l));
+        const float *src = &acc[t][0];
+        for (int i = threadIdx.x; i < CH * cnt; i += kBlock) {
             const float val = src[i];
             if (val != 0.0f) unsafeAtomicAdd(dst + i, val);
         }
@@ -669,24 +712,52 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-template <int DT, bool TRI>
+template <int DT, int CH, bool TRI>
 hipError_t launch_fwd(const SampleArgs &a, hipStream_t s)
 {
     const uint32_t G = (uint32_t)ceil_div(a.Q, kBlock);
     if (a.dbg)
-        hipLaunchKernelGGL((k_sample<DT, TRI, true>), dim3(G), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((k_sample<DT, CH, TRI, true>), dim3(G), dim3(kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL((k_sample<DT, TRI, false>), dim3(G), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((k_sample<DT, CH, TRI, false>), dim3(G), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
-template <int DT, bool TRI>
+template <int DT, int CH, bool TRI>
 hipError_t launch_fwd_prep(const SampleArgs &a, hipStream_t s)
 {
     const uint32_t G = (uint32_t)ceil_div(a.Q, kBlock);
-    hipLaunchKernelGGL((k_sample_prep<DT, TRI>), dim3(G), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_sample_prep<DT, CH, TRI>), dim3(G), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
+
+// Calls L<DT, CH, TRI>::run(a, s) for the runtime storage type, channel
+// count and filter.
+template <template <int, int, bool> class L>
+hipError_t dispatch(const SampleArgs &a, int dtype, int filter, hipStream_t s)
+{
+    const bool tri = filter == HTEX_TRILINEAR;
+    const bool one = a.channels == 1;
+#define HTEX_DISPATCH_DT(DTV)                                                              \
+    return one ? (tri ? L<DTV, 1, true>::run(a, s) : L<DTV, 1, false>::run(a, s))          \
+               : (tri ? L<DTV, 4, true>::run(a, s) : L<DTV, 4, false>::run(a, s))
+    switch (dtype) {
+    case HTEX_F32: HTEX_DISPATCH_DT(HTEX_F32);
+    case HTEX_BF16: HTEX_DISPATCH_DT(HTEX_BF16);
+    default: HTEX_DISPATCH_DT(HTEX_FP8_E4M3);
+    }
+#undef HTEX_DISPATCH_DT
+}
+
+template <int DT, int CH, bool TRI> struct Fwd {
+    static hipError_t run(const SampleArgs &a, hipStream_t s) { return launch_fwd<DT, CH, TRI>(a, s); }
+};
+template <int DT, int CH, bool TRI> struct FwdPrep {
+    static hipError_t run(const SampleArgs &a, hipStream_t s)
+    {
+        return launch_fwd_prep<DT, CH, TRI>(a, s);
+    }
+};
 
 }  // namespace
 
@@ -718,43 +789,36 @@ hipError_t launch_prepare(const SampleArgs &a, void *prep, hipStream_t s)
 hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, hipStream_t s)
 {
     if (a.Q == 0) return hipSuccess;
-    const bool tri = filter == HTEX_TRILINEAR;
-    switch (dtype) {
-    case HTEX_F32: return tri ? launch_fwd_prep<HTEX_F32, true>(a, s) : launch_fwd_prep<HTEX_F32, false>(a, s);
-    case HTEX_BF16: return tri ? launch_fwd_prep<HTEX_BF16, true>(a, s) : launch_fwd_prep<HTEX_BF16, false>(a, s);
-    default: return tri ? launch_fwd_prep<HTEX_FP8_E4M3, true>(a, s) : launch_fwd_prep<HTEX_FP8_E4M3, false>(a, s);
-    }
+    return dispatch<FwdPrep>(a, dtype, filter, s);
 }
 
 hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t s)
 {
     if (a.Q == 0) return hipSuccess;
-    const bool tri = filter == HTEX_TRILINEAR;
-    switch (dtype) {
-    case HTEX_F32: return tri ? launch_fwd<HTEX_F32, true>(a, s) : launch_fwd<HTEX_F32, false>(a, s);
-    case HTEX_BF16: return tri ? launch_fwd<HTEX_BF16, true>(a, s) : launch_fwd<HTEX_BF16, false>(a, s);
-    default: return tri ? launch_fwd<HTEX_FP8_E4M3, true>(a, s) : launch_fwd<HTEX_FP8_E4M3, false>(a, s);
+    return dispatch<Fwd>(a, dtype, filter, s);
+}
+
+template <int CH, bool TRI>
+hipError_t launch_bwd(const SampleArgs &a, uint32_t flags, hipStream_t s)
+{
+    if (flags & HTEX_QUERIES_SORTED) {
+        // sorted batches meet few textures per block: cache their gradients in LDS
+        const uint32_t G = (uint32_t)ceil_div(a.Q, kBwdChunk);
+        hipLaunchKernelGGL((k_backward_lds<CH, TRI>), dim3(G), dim3(kBlock), 0, s, a);
+    } else {
+        const uint32_t G = (uint32_t)ceil_div(a.Q, kBlock);
+        hipLaunchKernelGGL((k_backward<CH, TRI>), dim3(G), dim3(kBlock), 0, s, a);
     }
+    return hipGetLastError();
 }
 
 hipError_t launch_backward(const SampleArgs &a, int filter, uint32_t flags, hipStream_t s)
 {
     if (a.Q == 0) return hipSuccess;
-    if (flags & HTEX_QUERIES_SORTED) {
-        // sorted batches meet few textures per block: cache their gradients in LDS
-        const uint32_t G = (uint32_t)ceil_div(a.Q, kBwdChunk);
-        if (filter == HTEX_TRILINEAR)
-            hipLaunchKernelGGL((k_backward_lds<true>), dim3(G), dim3(kBlock), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_backward_lds<false>), dim3(G), dim3(kBlock), 0, s, a);
-        return hipGetLastError();
-    }
-    const uint32_t G = (uint32_t)ceil_div(a.Q, kBlock);
-    if (filter == HTEX_TRILINEAR)
-        hipLaunchKernelGGL((k_backward<true>), dim3(G), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_backward<false>), dim3(G), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+    const bool tri = filter == HTEX_TRILINEAR;
+    if (a.channels == 1)
+        return tri ? launch_bwd<1, true>(a, flags, s) : launch_bwd<1, false>(a, flags, s);
+    return tri ? launch_bwd<4, true>(a, flags, s) : launch_bwd<4, false>(a, flags, s);
 }
 
 }  // namespace htex

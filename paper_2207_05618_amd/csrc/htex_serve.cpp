@@ -393,6 +393,8 @@ htex_status htex_server_add_mesh(htex_server *S, int32_t H, const void *prep, co
 {
     if (!S || !prep || !pool || !mesh_id || H <= 0) return fail(HTEX_E_ARG, "bad argument");
     if (pool->dtype != S->cfg.dtype) return fail(HTEX_E_ARG, "pool dtype differs from the server's");
+    if (pool->channels != 4)
+        return fail(HTEX_E_UNSUPPORTED, "the server serves RGBA (4-channel) pools");
     if (S->cfg.filter == HTEX_TRILINEAR && !pool->has_mips)
         return fail(HTEX_E_ARG, "trilinear serving needs pools with mips");
     if (!pool->texels || (pool->dtype == HTEX_FP8_E4M3 && !pool->scale))

@@ -19,15 +19,16 @@ def t(a, dtype=None):
 class Setup:
     """A mesh with a seeded float32 pool, on the device and in the oracle."""
 
-    def __init__(self, mesh, log2res, has_mips, kind=0, seed=102):
+    def __init__(self, mesh, log2res, has_mips, kind=0, seed=102, channels=4):
         self.m = mesh
         self.log2res = np.asarray(log2res, np.uint8)
         self.has_mips = has_mips
         base, total = gpool.layout(self.log2res, has_mips)
         lvl0 = gpool.fill_level0_host(kind, seed, self.log2res, base, total,
-                                      mesh.boundary_edges(), has_mips)
+                                      mesh.boundary_edges(), has_mips, channels=channels)
         self.dmesh = htex.Mesh.of(mesh)
-        self.pool = htex.Pool(self.log2res, has_mips, htex.HTEX_F32, texels=t(lvl0))
+        self.pool = htex.Pool(self.log2res, has_mips, htex.HTEX_F32, texels=t(lvl0),
+                              channels=channels)
         if has_mips:
             htex.htex_build_mips(self.pool)
         op = oracle.Pool(self.log2res, base, lvl0.astype(np.float64), has_mips)

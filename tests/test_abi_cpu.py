@@ -67,8 +67,8 @@ def _mesh(H=4, E=2, null=False):
     return _lib.htex_mesh(H, E, None if null else 8, 8, 8, 8)
 
 
-def _pool(E=2, dtype=0, tex=16, mips=1, maxk=2, scale=None):
-    return _lib.htex_pool(E, dtype, mips, maxk, 64, 8, 8, tex, scale)
+def _pool(E=2, dtype=0, tex=16, mips=1, maxk=2, scale=None, channels=4, reserved=0):
+    return _lib.htex_pool(E, dtype, mips, maxk, channels, reserved, 64, 8, 8, tex, scale)
 
 
 def _q(Q=1, f=None):
@@ -79,6 +79,8 @@ def _q(Q=1, f=None):
     ("null_mesh_array", -1), ("E_mismatch", -1), ("bad_dtype", -1), ("misaligned_texels", -1),
     ("fp8_no_scale", -1), ("bad_filter", -1), ("tri_no_footprint", -1), ("tri_no_mips", -1),
     ("neg_Q", -1), ("misaligned_out", -1), ("bad_flags", -1), ("big_k", -3),
+    ("bad_channels", -1), ("reserved_set", -1), ("one_channel_misaligned_out", -1),
+    ("one_channel_misaligned_texels", -1),
 ])
 def test_sample_rejects_bad_arguments_without_launching(case, status):
     L = _lib.load()
@@ -108,6 +110,14 @@ def test_sample_rejects_bad_arguments_without_launching(case, status):
         flags = 1 << 7
     elif case == "big_k":
         pool = _pool(maxk=16)
+    elif case == "bad_channels":
+        pool = _pool(channels=2)
+    elif case == "reserved_set":
+        pool = _pool(reserved=1)
+    elif case == "one_channel_misaligned_out":
+        pool, out = _pool(channels=1), 18
+    elif case == "one_channel_misaligned_texels":
+        pool = _pool(channels=1, tex=18)
     st = L.htex_sample(C.byref(mesh), C.byref(pool), C.byref(q), filt, flags, out, None, None,
                        None)
     assert st == status
@@ -128,6 +138,13 @@ def test_quantize_and_mips_argument_checks():
     assert L.htex_build_mips(C.byref(_pool(mips=0)), 16, None) == -1
     assert L.htex_build_mips(C.byref(_pool()), 32, None) == -1
     assert L.htex_build_mips(C.byref(_pool(dtype=1, tex=8)), 8, None) == -5
+    # corner pre-processing: float32 only, in place, pool and mesh must agree
+    m = _mesh()
+    assert L.htex_corner_average(C.byref(m), C.byref(_pool(dtype=1, tex=8)), 8, None, None) == -5
+    assert L.htex_corner_average(C.byref(m), C.byref(_pool()), 32, None, None) == -1
+    assert L.htex_corner_average(C.byref(m), C.byref(_pool(E=3)), 16, None, None) == -1
+    assert L.htex_corner_average(C.byref(_mesh(null=True)), C.byref(_pool()), 16, None,
+                                 None) == -1
 
 
 def test_product_path_refuses_cpu_tensors():

@@ -126,3 +126,97 @@ def test_frame_quantized_error_bounds(frame):
         assert_rel(g.cpu().numpy(), ref, tol)
         del qp
         torch.cuda.empty_cache()
+
+
+# ------------------------------------------------ vertex-stage displacement --
+
+@pytest.fixture(scope="module")
+def disp_frame(frame):
+    """The displacement map of the frame mesh as the benchmark builds it:
+    one 64x64 float32 channel per edge, level 0 only, corners pre-processed,
+    sampled at the vertices of every patch tessellated with T = 4."""
+    mesh, lr, pool, dm, q, out = frame
+    from htexgen.queries import tessellated_queries
+    disp = htex.Pool(lr, False, htex.HTEX_F32, channels=1)
+    gdev.fill_level0(disp.texels, 1, 501, disp.log2res, disp.base, mesh.boundary_edges())
+    torch.cuda.synchronize()
+    before = disp.texels.cpu().numpy()
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    htex.htex_corner_average(dm, disp, err_count=err)
+    prep = htex.Prepared(dm, disp)
+    tq = tessellated_queries(mesh.H, 4)
+    o = htex.htex_sample_prepared(prep, disp, t(tq.h), t(tq.u), t(tq.v), None,
+                                  filter=htex.HTEX_BILINEAR, flags=htex.HTEX_QUERIES_SORTED)
+    torch.cuda.synchronize()
+    yield mesh, disp, before, disp.texels.cpu().numpy(), int(err.item()), tq, o.cpu().numpy()
+    del disp, prep
+    torch.cuda.empty_cache()
+
+
+def test_frame_corner_groups_hold_their_means(disp_frame):
+    """Sampled vertices and faces of the full mesh: their corner texels all
+    equal the float64 mean of the values before, rounded once."""
+    mesh, disp, before, after, err, _, _ = disp_frame
+    assert err == 0
+    base = disp.base_host
+    n = 64
+    rng = np.random.default_rng(11)
+    gi = np.nonzero(mesh.twin < np.arange(mesh.H))[0]          # larger halfedge of each edge
+    gi = np.concatenate([gi, np.nonzero(mesh.twin < 0)[0]])
+    gi = np.unique(gi)
+    e = mesh.edge[gi]
+    t = mesh.twin[gi]
+    rows = np.concatenate([base[e] + n - 1, base[e] + (n - 1) * n, base[e],
+                           np.where(t >= 0, base[e] + n * n - 1, -1)])
+    keys = np.concatenate([mesh.vert[gi], mesh.vert[mesh.next[gi]], mesh.V + mesh.face[gi],
+                           np.where(t >= 0, mesh.V + mesh.face[np.maximum(t, 0)], -1)])
+    ok = rows >= 0
+    rows, keys = rows[ok], keys[ok]
+    pick = rng.choice(np.unique(keys), 3000, replace=False)
+    sel = np.isin(keys, pick)
+    rows, keys = rows[sel], keys[sel]
+    order = np.argsort(keys, kind="stable")
+    rows, keys = rows[order], keys[order]
+    starts = np.r_[0, np.nonzero(np.diff(keys))[0] + 1, len(keys)]
+    for a, b in zip(starts[:-1], starts[1:]):
+        r = rows[a:b]
+        want = np.float32(before[r, 0].astype(np.float64).mean())
+        assert (after[r, 0] == want).all(), (keys[a], after[r, 0], want)
+
+
+def test_frame_displacement_sampled_parity_and_crack_free(disp_frame):
+    """Patches of a run of faces: GPU values against the oracle on the
+    processed texels of the touched edges, and equal displacement wherever
+    two of those patches share a surface point."""
+    from scipy.spatial import cKDTree
+    mesh, disp, _, after, _, tq, o = disp_frame
+    f0 = mesh.F // 2
+    hs = np.nonzero((mesh.face >= f0) & (mesh.face < f0 + 300))[0]
+    hs = np.unique(np.concatenate([hs, mesh.twin[hs][mesh.twin[hs] >= 0]]))
+    idx = np.nonzero(np.isin(tq.h, hs))[0]
+    qs = tq.take(idx)
+    touched = np.unique(np.concatenate([qs.h, mesh.next[qs.h], mesh.prev[qs.h]]))
+    edges = np.unique(mesh.edge[touched])
+    remap = np.full(mesh.E, -1, np.int32)
+    remap[edges] = np.arange(len(edges), dtype=np.int32)
+    sub = np.full(len(edges), 6, np.uint8)
+    base, total = gpool.layout(sub, False)
+    T = np.zeros((total, 1), np.float64)
+    for i, e in enumerate(edges):
+        T[base[i]:base[i] + 4096] = after[disp.base_host[e]:disp.base_host[e] + 4096]
+    op = oracle.Pool(sub, base, T, False)
+    om = oracle.Mesh(mesh.twin, mesh.next, mesh.prev, remap[mesh.edge], len(edges))
+    ref, errs, _ = oracle.sample(om, op, qs.h, qs.u, qs.v)
+    assert errs == 0
+    assert_rel(o[idx], ref, 1e-5)
+    pos = np.asarray(mesh.positions)
+    cen = np.zeros((mesh.F, 3))
+    np.add.at(cen, mesh.face, pos[mesh.vert])
+    cen /= np.bincount(mesh.face, minlength=mesh.F)[:, None]
+    w = 1.0 - qs.u.astype(np.float64) - qs.v
+    pts = (qs.u[:, None] * pos[mesh.vert[qs.h]] + qs.v[:, None] * pos[mesh.vert[mesh.next[qs.h]]]
+           + w[:, None] * cen[mesh.face[qs.h]])
+    pairs = np.array(sorted(cKDTree(pts).query_pairs(1e-9)))
+    assert len(pairs) > len(hs)
+    got = o[idx]
+    assert np.abs(got[pairs[:, 0]] - got[pairs[:, 1]]).max() < 4e-7
