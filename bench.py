@@ -86,11 +86,12 @@ def to_dev(q):
 
 # ------------------------------------------------------ algorithmic bytes --
 
-def algorithmic_bytes(dbg, h, log2res, base, total, Q):
-    """Exact bytes one launch must move: queries in (h, u, v, f: 16 B), result
-    out (16 B), each distinct halfedge/edge record it reads, and each distinct
-    texel (16 B) under an in-bounds filter tap.  Also the distinct 64-byte
-    segments those texels occupy."""
+def algorithmic_bytes(dbg, h, log2res, base, total, Q, qbytes=16, obytes=16, tbytes=16):
+    """Exact bytes one launch must move: queries in (h, u, v and f when
+    filtering trilinearly: qbytes), result out (obytes), each distinct
+    halfedge/edge record it reads, and each distinct texel (tbytes) under an
+    in-bounds filter tap.  Also the distinct 64-byte segments and 128-byte
+    lines those texels occupy."""
     import numpy as np
     rec = dbg.view(np.dtype([("next", "<i4"), ("prev", "<i4"), ("edge", "<i4", (3,)),
                              ("flip", "<i4", (3,)), ("level", "<i4", (3, 2)),
@@ -118,21 +119,22 @@ def algorithmic_bytes(dbg, h, log2res, base, total, Q):
                     idx = eb + lofs + (j0 + dj) * n + (i0 + di)
                     mark[idx[ok]] = True
     texels = int(np.count_nonzero(mark))
-    nz = np.nonzero(mark)[0]
-    segments = int(len(np.unique(nz >> 2)))      # 64-byte segments
-    lines128 = int(len(np.unique(nz >> 3)))      # 128-byte lines
+    nz = np.nonzero(mark)[0] * tbytes
+    segments = int(len(np.unique(nz >> 6)))      # 64-byte segments
+    lines128 = int(len(np.unique(nz >> 7)))      # 128-byte lines
     # Next/Prev of each distinct h; Twin/Edge of each distinct h, Next h, Prev h;
     # log2res/base of each distinct edge
     n_h = len(np.unique(h))
     n_g = len(np.unique(np.concatenate([h, rec["next"], rec["prev"]])))
     n_e = len(np.unique(rec["edge"].reshape(-1)))
     topo = 8 * n_h + 8 * n_g + 9 * n_e
-    total_bytes = 16 * Q + 16 * Q + topo + 16 * texels
+    io = (qbytes + obytes) * Q
+    total_bytes = io + topo + tbytes * texels
     return {"bytes": int(total_bytes), "bytes_per_query": total_bytes / Q,
-            "texel_bytes_per_query": 16 * texels / Q, "unique_texels": texels,
+            "texel_bytes_per_query": tbytes * texels / Q, "unique_texels": texels,
             "unique_64B_segments": segments, "unique_128B_lines": lines128,
-            "segment_bytes_per_query": (32 * Q + topo + 64 * segments) / Q,
-            "line128_bytes_per_query": (32 * Q + topo + 128 * lines128) / Q}
+            "segment_bytes_per_query": (io + topo + 64 * segments) / Q,
+            "line128_bytes_per_query": (io + topo + 128 * lines128) / Q}
 
 
 # ----------------------------------------------------------- CPU oracle --
@@ -258,7 +260,7 @@ def grad_benchmark(steps=200):
 
 # ---------------------------------------------------------- displacement --
 
-def displacement_benchmark(mesh, dmesh, rgb_step, Q_rgb, T=4, n_iter=10):
+def displacement_benchmark(mesh, dmesh, rgb_step, Q_rgb, T=4, n_iter=10, with_bytes=True):
     """The paper's "RGB + disp" configuration on the frame mesh: besides the
     4K fragment batch (RGBA, trilinear), a vertex stage tessellates every
     intrinsic triangle into T^2 sub-triangles and reads a one-channel 64x64
@@ -311,11 +313,33 @@ def displacement_benchmark(mesh, dmesh, rgb_step, Q_rgb, T=4, n_iter=10):
         rgb_step(i)
 
     t_both = timed(both)
+    # kernel time of the vertex stage alone (HIP events on the launch stream)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    for _ in range(n_iter):
+        disp_step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    k_disp = e0.elapsed_time(e1) / n_iter / 1e3
     res = {"tessellation": T, "vertex_queries": int(q.Q), "fragment_queries": int(Q_rgb),
            "displacement_pool_bytes": disp.nbytes(), "corner_preprocess_ms": corner_ms,
-           "vertex_stage_ms": t_disp * 1e3,
+           "vertex_stage_ms": t_disp * 1e3, "vertex_stage_kernel_us": k_disp * 1e6,
            "vertex_samples_per_s": q.Q / t_disp, "rgb_only_ms": t_rgb * 1e3,
            "rgb_plus_disp_ms": t_both * 1e3, "rgb_plus_disp_over_rgb": t_both / t_rgb}
+    if with_bytes:
+        _, dbg = htex.htex_sample(dmesh, disp, h, u, v, None, filter=htex.HTEX_BILINEAR,
+                                  debug=True)
+        dbg_host = dbg.cpu().numpy()
+        del dbg
+        alg = algorithmic_bytes(dbg_host, q.h, lr, disp.base_host, disp.total, q.Q,
+                                qbytes=12, obytes=4, tbytes=4)
+        achieved = alg["bytes"] / k_disp / 1e9
+        res["roofline"] = {"bound": "hbm", "kernel": "htex::k_sample_prep<f32,1ch,bilinear>",
+                           "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS,
+                           "alg_bytes_per_query": alg["bytes_per_query"],
+                           "alg_texel_bytes_per_query": alg["texel_bytes_per_query"],
+                           "line128_bytes_per_query": alg["line128_bytes_per_query"]}
     del disp, prep, h, u, v, out
     torch.cuda.empty_cache()
     return res
@@ -637,7 +661,8 @@ def main():
             extra[kk.replace("samples_per_s", "speedup_vs_f32")] = extra[kk] / value
         log(f"extra {json.dumps({k: round(v, 3) for k, v in extra.items()})}")
         if args.workload == "frame4k":
-            extra["rgb_plus_displacement"] = displacement_benchmark(mesh, dmesh, step, Q)
+            extra["rgb_plus_displacement"] = displacement_benchmark(
+                mesh, dmesh, step, Q, with_bytes=not args.no_bytes)
             log(f"rgb+disp {json.dumps(extra['rgb_plus_displacement'])}")
 
     roofline = None
