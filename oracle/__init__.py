@@ -51,6 +51,8 @@ def lib():
         p = C.c_void_p
         L.ora_sample.restype = C.c_int64
         L.ora_sample.argtypes = [p, p, C.c_int64, p, p, p, p, C.c_int, p, p, C.c_int]
+        L.ora_sample_aniso.restype = C.c_int64
+        L.ora_sample_aniso.argtypes = [p, p, C.c_int64, p, p, p, p, C.c_int, p, p, C.c_int]
         L.ora_backward.restype = C.c_int64
         L.ora_backward.argtypes = [p, p, C.c_int64, p, p, p, p, C.c_int, p, p, p]
         L.ora_build_mips.restype = None
@@ -142,6 +144,25 @@ def sample(mesh: Mesh, pool: Pool, h, u, v, f=None, filter=BILINEAR,
     if errs < 0:
         raise ValueError("oracle rejected the call (trilinear on a pool without mips)")
     return out, int(errs), dbg
+
+
+def sample_aniso(mesh: Mesh, pool: Pool, h, u, v, jac, max_aniso=16, nthreads=0):
+    """Anisotropic Alg. 3 (Section 5.1 reading): jac is float32 [Q, 4] =
+    (du/dx, dv/dx, du/dy, dv/dy).  Returns (out float64 [Q, C], errors,
+    probes int32 [Q])."""
+    h = _c(h, np.int32)
+    u = _c(u, np.float32)
+    v = _c(v, np.float32)
+    jac = _c(jac, np.float32).reshape(-1, 4)
+    Q = len(h)
+    out = np.empty((Q, pool.channels), dtype=np.float64)
+    n = np.zeros(Q, dtype=np.int32)
+    errs = lib().ora_sample_aniso(C.byref(mesh._s), C.byref(pool._s), Q, _ptr(h), _ptr(u),
+                                  _ptr(v), _ptr(jac), int(max_aniso), _ptr(out), _ptr(n),
+                                  int(nthreads))
+    if errs < 0:
+        raise ValueError("oracle rejected the call (needs mips and max_aniso >= 1)")
+    return out, int(errs), n
 
 
 def backward(mesh: Mesh, pool: Pool, h, u, v, dout, f=None, filter=BILINEAR,

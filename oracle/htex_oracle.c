@@ -215,15 +215,18 @@ static void texture_fetch(const ora_pool *P, fetch_rec *F)
 /* Alg. 3 for one query, in the algorithm's order: the own quad at (u, v),
  * the Next halfedge's quad at (v, -u), the Prev halfedge's quad at (-v, u),
  * each mapped by Alg. 2; each fetch is formed on its own and added to the
- * running sum (c <- c + Texture(...)); the result is c_i / c_n. */
-static void htexture(const ora_mesh *M, const ora_pool *P, int filter, int32_t h,
-                     double u, double v, double f, fetch_rec F[3], double out[4],
-                     double *Wtot)
+ * running sum (c <- c + Texture(...)).  htexture_sums leaves the colour
+ * channels C and the normalization channel W unnormalized; htexture
+ * returns c_i / c_n. */
+static void htexture_sums(const ora_mesh *M, const ora_pool *P, int filter, int32_t h,
+                          double u, double v, double f, fetch_rec F[3], double C[4], double *Wtot)
 {
     const int32_t g[3] = {h, M->next[h], M->prev[h]};
     const double a[3] = {u, v, -v};
     const double b[3] = {v, -u, u};
-    double C[4] = {0, 0, 0, 0}, W = 0.0;
+    double W = 0.0;
+    for (int c = 0; c < 4; ++c)
+        C[c] = 0.0;
     for (int q = 0; q < 3; ++q) {
         fetch_rec *R = &F[q];
         R->g = g[q];
@@ -236,9 +239,17 @@ static void htexture(const ora_mesh *M, const ora_pool *P, int filter, int32_t h
             C[c] += R->C[c];
         W += R->W;
     }
-    for (int c = 0; c < P->channels; ++c)
-        out[c] = C[c] / W;
     *Wtot = W;
+}
+
+static void htexture(const ora_mesh *M, const ora_pool *P, int filter, int32_t h,
+                     double u, double v, double f, fetch_rec F[3], double out[4],
+                     double *Wtot)
+{
+    double C[4];
+    htexture_sums(M, P, filter, h, u, v, f, F, C, Wtot);
+    for (int c = 0; c < P->channels; ++c)
+        out[c] = C[c] / *Wtot;
 }
 
 static int query_valid(const ora_mesh *M, int32_t h, float u, float v)
@@ -295,6 +306,113 @@ int64_t ora_sample(const ora_mesh *M, const ora_pool *P, int64_t Q, const int32_
             d->phi = trilinear_fraction(filter, f);
             d->W = W;
         }
+    }
+    return errs;
+}
+
+/* ------------------------------------------- anisotropic filtering (Sec. 5.1) */
+
+/* The paper samples with the GPU's anisotropic texture filter (Fig. 7).  Read
+ * here as the filter of the OpenGL anisotropic-filtering extension: from the
+ * screen-space derivatives of the query's barycentric coordinates, the
+ * footprint's two axis lengths px = |d(u,v)/dx| and py = |d(u,v)/dy|; N =
+ * ceil(pmax / pmin) probes, at most max_aniso, spread evenly along the major
+ * axis, each a trilinear fetch whose level comes from pmax / N.  The maps of
+ * Alg. 2 and Alg. 3 are rotations and reflections of the quad, so lengths
+ * and the probe points agree in the three quads: every fetch of Alg. 3
+ * becomes the sum of its N probes, colour and normalization channel alike,
+ * and the result is sum C / sum W over all probes of all three fetches.
+ *
+ * The decisions that pick integers -- N, and the probe coordinates from
+ * which tap bases follow -- are taken in float32, one rounding per
+ * operation (squares, sums, square roots, quotients, the probe offset and
+ * its product and sum), so the oracle and the device take them alike. */
+typedef struct {
+    int n;        /* probes                                  */
+    float f;      /* footprint of each probe (quad units)    */
+    float au, av; /* major axis in barycentric coordinates   */
+} aniso_plan;
+
+static aniso_plan aniso_setup(float dudx, float dvdx, float dudy, float dvdy, int max_aniso)
+{
+    volatile float t0, t1;
+    t0 = dudx * dudx;
+    t1 = dvdx * dvdx;
+    const float px = sqrtf(t0 + t1);
+    t0 = dudy * dudy;
+    t1 = dvdy * dvdy;
+    const float py = sqrtf(t0 + t1);
+    aniso_plan A;
+    const int xmajor = px >= py;
+    const float pmax = xmajor ? px : py, pmin = xmajor ? py : px;
+    A.au = xmajor ? dudx : dudy;
+    A.av = xmajor ? dvdx : dvdy;
+    if (pmax == 0.0f) {
+        A.n = 1;
+        A.f = 0.0f;
+        return A;
+    }
+    const float ratio = pmax / pmin;   /* +inf when pmin is 0 */
+    A.n = ratio > (float)max_aniso ? max_aniso : (int)ceilf(ratio);
+    if (A.n < 1)
+        A.n = 1;
+    A.f = pmax / (float)A.n;
+    return A;
+}
+
+/* Probe i (1..n) of a plan: (u, v) + (i / (n + 1) - 1/2) * axis. */
+static void aniso_probe(const aniso_plan *A, int i, float u, float v, float *ui, float *vi)
+{
+    volatile float t = (float)i / (float)(A->n + 1);
+    t = t - 0.5f;
+    volatile float du = t * A->au, dv = t * A->av;
+    *ui = u + du;
+    *vi = v + dv;
+}
+
+int64_t ora_sample_aniso(const ora_mesh *M, const ora_pool *P, int64_t Q, const int32_t *h,
+                         const float *u, const float *v, const float *jac, int max_aniso,
+                         double *out, int32_t *nprobe, int nthreads)
+{
+    if (!P->has_mips || max_aniso < 1)
+        return -1;
+    int64_t errs = 0;
+    const int C = P->channels;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static) reduction(+ : errs)
+#endif
+    for (int64_t q = 0; q < Q; ++q) {
+        const float *J = jac + 4 * q;
+        int ok = query_valid(M, h[q], u[q], v[q]);
+        for (int c = 0; c < 4; ++c)
+            ok = ok && isfinite(J[c]);
+        if (!ok) {
+            for (int c = 0; c < C; ++c)
+                out[C * q + c] = NAN;
+            if (nprobe)
+                nprobe[q] = 0;
+            errs += 1;
+            continue;
+        }
+        aniso_plan A = aniso_setup(J[0], J[1], J[2], J[3], max_aniso);
+        double Cs[4] = {0, 0, 0, 0}, Ws = 0.0;
+        for (int i = 1; i <= A.n; ++i) {
+            float ui, vi;
+            aniso_probe(&A, i, u[q], v[q], &ui, &vi);
+            fetch_rec F[3];
+            double Ci[4], Wi;
+            htexture_sums(M, P, ORA_TRILINEAR, h[q], (double)ui, (double)vi, (double)A.f, F, Ci,
+                          &Wi);
+            for (int c = 0; c < C; ++c)
+                Cs[c] += Ci[c];
+            Ws += Wi;
+        }
+        for (int c = 0; c < C; ++c)
+            out[C * q + c] = Cs[c] / Ws;
+        if (nprobe)
+            nprobe[q] = A.n;
     }
     return errs;
 }

@@ -39,6 +39,9 @@ typedef struct {
 int64_t ora_sample(const ora_mesh *M, const ora_pool *P, int64_t Q, const int32_t *h,
                    const float *u, const float *v, const float *f, int filter,
                    double *out, ora_debug *dbg, int nthreads);
+int64_t ora_sample_aniso(const ora_mesh *M, const ora_pool *P, int64_t Q, const int32_t *h,
+                         const float *u, const float *v, const float *jac, int max_aniso,
+                         double *out, int32_t *nprobe, int nthreads);
 int64_t ora_backward(const ora_mesh *M, const ora_pool *P, int64_t Q, const int32_t *h,
                      const float *u, const float *v, const float *f, int filter,
                      const double *dout, double *dtex, double *dabs);
