@@ -345,6 +345,53 @@ def displacement_benchmark(mesh, dmesh, rgb_step, Q_rgb, T=4, n_iter=10, with_by
     return res
 
 
+# ------------------------------------------------------------ anisotropy --
+
+def aniso_benchmark(prep, pool, batches, dev_batches, Q, max_aniso=16, n_iter=10):
+    """Anisotropic filtering on the frame (Section 5.1, Fig. 7): the frame's
+    queries with elliptic footprints whose minor axis is the query's
+    isotropic footprint and whose major axis is longer by a log-uniform
+    factor in [1, 16] (grazing views), up to 16 probes per query."""
+    import numpy as np
+    import torch
+
+    import paper_2207_05618_amd as htex
+    from htexgen.queries import aniso_jacobians
+
+    jacs = [torch.from_numpy(aniso_jacobians(b.Q, 601 + i, b.f)).cuda()
+            for i, b in enumerate(batches)]
+    out = torch.empty((Q, 4), dtype=torch.float32, device="cuda")
+
+    def step(i):
+        h, u, v, _ = dev_batches[i % len(dev_batches)]
+        htex.htex_sample_aniso_prepared(prep, pool, h, u, v, jacs[i % len(jacs)],
+                                        max_aniso=max_aniso, flags=htex.HTEX_QUERIES_SORTED,
+                                        out=out)
+
+    for i in range(3):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(n_iter):
+        step(i)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / n_iter
+    # mean probe count of the batches (the filter's rule: ceil of the axis
+    # ratio, at most max_aniso)
+    n_sum = 0.0
+    for jb in jacs:
+        px = torch.sqrt(jb[:, 0] * jb[:, 0] + jb[:, 1] * jb[:, 1])
+        py = torch.sqrt(jb[:, 2] * jb[:, 2] + jb[:, 3] * jb[:, 3])
+        r = torch.maximum(px, py) / torch.minimum(px, py)
+        n_sum += float(torch.clamp(torch.ceil(r), max=max_aniso).mean())
+    n_mean = n_sum / len(jacs)
+    res = {"max_aniso": max_aniso, "ratio_range": [1, 16], "queries": Q,
+           "ms_per_frame": t * 1e3, "samples_per_s": Q / t, "mean_probes": n_mean,
+           "probe_samples_per_s": Q * n_mean / t}
+    del jacs, out
+    return res
+
+
 # -------------------------------------------------------------- serving --
 
 def _gen_sphere(args):
@@ -663,6 +710,10 @@ def main():
         if args.workload == "frame4k":
             extra["rgb_plus_displacement"] = displacement_benchmark(
                 mesh, dmesh, step, Q, with_bytes=not args.no_bytes)
+            extra["anisotropic"] = aniso_benchmark(prep, pool, batches, dev_batches, Q)
+            a = extra["anisotropic"]
+            a["cost_vs_trilinear"] = value / a["samples_per_s"]
+            log(f"aniso {json.dumps(a)}")
             log(f"rgb+disp {json.dumps(extra['rgb_plus_displacement'])}")
 
     roofline = None

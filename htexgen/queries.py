@@ -70,3 +70,25 @@ def tessellated_queries(H: int, T: int, footprint: float | None = None,
     v = np.tile((gj / T).astype(np.float32), len(hs))
     f = None if footprint is None else np.full(len(h), footprint, np.float32)
     return Queries(h, u, v, f)
+
+
+def aniso_jacobians(Q: int, seed: int, minor, ratio=(1.0, 16.0)) -> np.ndarray:
+    """Screen-space derivatives (du/dx, dv/dx, du/dy, dv/dy) of an elliptic
+    pixel footprint per query: the minor axis has length `minor` (array or
+    scalar, quad units), the major axis is longer by a log-uniform factor in
+    `ratio`; the major axis points in a uniform random direction and the
+    minor axis at a uniform random angle to it (screen axes need not be
+    orthogonal in texture space); which screen axis is the major one is a
+    coin flip.  float32 [Q, 4]."""
+    rng = np.random.default_rng(seed)
+    lo, hi = ratio
+    r = np.exp(rng.uniform(np.log(lo), np.log(hi), Q))
+    mn = np.broadcast_to(np.asarray(minor, np.float64), (Q,))
+    a = rng.uniform(0.0, 2.0 * np.pi, Q)
+    b = a + rng.uniform(0.25 * np.pi, 0.75 * np.pi, Q) * rng.choice([-1.0, 1.0], Q)
+    major = np.stack([r * mn * np.cos(a), r * mn * np.sin(a)], 1)
+    minor_v = np.stack([mn * np.cos(b), mn * np.sin(b)], 1)
+    swap = rng.random(Q) < 0.5
+    J = np.where(swap[:, None], np.concatenate([minor_v, major], 1),
+                 np.concatenate([major, minor_v], 1))
+    return np.ascontiguousarray(J, dtype=np.float32)

@@ -278,6 +278,41 @@ htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *p
                                  uint32_t flags, float *out, int32_t *err_count,
                                  void *stream);
 
+/* ----------------------------------------------- anisotropic filtering --
+ * The paper samples with the GPU's anisotropic filter (Section 5.1, Fig. 7).
+ * Here that is the OpenGL anisotropic-filtering extension's filter applied
+ * to each of Alg. 3's fetches.  Per query, jac[q] = (du/dx, dv/dx, du/dy,
+ * dv/dy): the screen-space derivatives of the query's barycentric (u, v).
+ * With px = |(du/dx, dv/dx)|, py = |(du/dy, dv/dy)|, pmax, pmin their
+ * maximum and minimum and a the derivative vector of the longer axis:
+ *   N = 1 if pmax = 0, else min(ceil(pmax / pmin), max_aniso) probes;
+ *   probe i = 1..N at (u, v) + (i / (N + 1) - 1/2) a;
+ *   each probe is Alg. 3 with trilinear fetches at footprint f = pmax / N
+ *   (LOD as for htex_sample; the quad maps preserve lengths, so the same
+ *   footprint holds in all three quads);
+ *   out = (sum over probes and fetches of colour) / (same sum of the
+ *   normalization channel).
+ * N and the probe coordinates are computed in float32 with one rounding
+ * per operation (squares, sums, square roots, quotients, offset, product
+ * and sum; no fused multiply-add), so they are reproducible.  N = 1 is
+ * exactly htex_sample's trilinear result at footprint f = pmax.
+ * Requires a pool with mips; footprint arrays in `queries` are ignored.
+ * jac: device float32 [Q][4], 16-byte aligned.  A query with a non-finite
+ * derivative is invalid (NaN row, *err_count incremented). */
+#define HTEX_MAX_ANISO 16
+
+/* nprobe (nullable, device int32 [Q]) receives N per query (0 if invalid). */
+htex_status htex_sample_aniso(const htex_mesh *mesh, const htex_pool *pool,
+                              const htex_queries *queries, const float *jac, int32_t max_aniso,
+                              uint32_t flags, float *out, int32_t *nprobe, int32_t *err_count,
+                              void *stream);
+
+/* The same from prepared records (htex_prepare), bit for bit. */
+htex_status htex_sample_aniso_prepared(int32_t H, const void *prep, const htex_pool *pool,
+                                       const htex_queries *queries, const float *jac,
+                                       int32_t max_aniso, uint32_t flags, float *out,
+                                       int32_t *err_count, void *stream);
+
 /* ------------------------------------------------------------- serving --
  * A continuous-batching server over resident meshes.  Requests (a mesh id
  * and a batch of queries in host memory) are admitted in arrival order as

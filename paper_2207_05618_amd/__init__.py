@@ -20,6 +20,7 @@ from ._lib import (DEBUG_FIELDS, HTEX_BF16, HTEX_BILINEAR, HTEX_F32, HTEX_FP8_E4
 __all__ = ["Mesh", "Pool", "htex_pool_layout", "htex_mesh_validate", "htex_build_mips",
            "htex_corner_average", "htex_quantize", "htex_sample", "htex_sample_backward", "HtexSample",
            "htex_prepare", "htex_sample_prepared", "Prepared",
+           "htex_sample_aniso", "htex_sample_aniso_prepared",
            "htex_sort_queries", "htex_permute_queries", "htex_unpermute_results",
            "debug_records", "HtexError"]
 
@@ -211,6 +212,49 @@ def htex_sample_prepared(prep: "Prepared", pool: Pool, h, u, v, footprint=None,
                                       int(filter), int(flags), out.data_ptr(),
                                       err_count.data_ptr() if err_count is not None else None,
                                       _stream(stream)))
+    return out
+
+
+def htex_sample_aniso(mesh: Mesh, pool: Pool, h, u, v, jac, max_aniso: int = 16, flags=0,
+                      out=None, nprobe=False, err_count=None, stream=None):
+    """Anisotropic Alg. 3 (the OpenGL anisotropic filter on every fetch);
+    jac: float32 [Q, 4] = (du/dx, dv/dx, du/dy, dv/dy).
+    -> (out float32 [Q, C], probes int32 [Q] or None)."""
+    q, Q = _queries(h, u, v, None)
+    _dev(jac, torch.float32, "jac")
+    if jac.numel() != 4 * Q:
+        raise ValueError("jac must hold 4 floats per query")
+    if out is None:
+        out = torch.empty((Q, pool.channels), dtype=torch.float32, device=h.device)
+    _dev(out, torch.float32, "out")
+    n = torch.zeros(Q, dtype=torch.int32, device=h.device) if nprobe else None
+    if err_count is not None:
+        _dev(err_count, torch.int32, "err_count")
+    check(load().htex_sample_aniso(C.byref(mesh.c), C.byref(pool.c), C.byref(q), jac.data_ptr(),
+                                   int(max_aniso), int(flags), out.data_ptr(),
+                                   n.data_ptr() if n is not None else None,
+                                   err_count.data_ptr() if err_count is not None else None,
+                                   _stream(stream)))
+    return out, n
+
+
+def htex_sample_aniso_prepared(prep: "Prepared", pool: Pool, h, u, v, jac, max_aniso: int = 16,
+                               flags=0, out=None, err_count=None, stream=None):
+    """htex_sample_aniso from prepared records (bit-identical) -> out [Q, C]."""
+    q, Q = _queries(h, u, v, None)
+    _dev(jac, torch.float32, "jac")
+    if jac.numel() != 4 * Q:
+        raise ValueError("jac must hold 4 floats per query")
+    if out is None:
+        out = torch.empty((Q, pool.channels), dtype=torch.float32, device=h.device)
+    _dev(out, torch.float32, "out")
+    if err_count is not None:
+        _dev(err_count, torch.int32, "err_count")
+    check(load().htex_sample_aniso_prepared(prep.H, prep.buf.data_ptr(), C.byref(pool.c),
+                                            C.byref(q), jac.data_ptr(), int(max_aniso),
+                                            int(flags), out.data_ptr(),
+                                            err_count.data_ptr() if err_count is not None
+                                            else None, _stream(stream)))
     return out
 
 

@@ -68,8 +68,12 @@ SIGNATURES = {
     "htex_unpermute_results": (C.c_int32, [C.c_int64, _P, _P, _P, _P]),
     "htex_sample_prepared": (C.c_int32, [C.c_int32, _P, _P, _P, C.c_int32, C.c_uint32, _P, _P,
                                          _P]),
+    "htex_sample_aniso": (C.c_int32, [_P, _P, _P, _P, C.c_int32, C.c_uint32, _P, _P, _P, _P]),
+    "htex_sample_aniso_prepared": (C.c_int32, [C.c_int32, _P, _P, _P, _P, C.c_int32, C.c_uint32,
+                                               _P, _P, _P]),
 }
 HTEX_PREP_BYTES = 48
+HTEX_MAX_ANISO = 16
 
 
 class htex_server_config(C.Structure):

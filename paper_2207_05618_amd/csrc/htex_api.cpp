@@ -403,4 +403,79 @@ htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *p
                     "prepared sample launch");
 }
 
+namespace {
+
+htex_status check_aniso(const htex_pool *pool, const htex_queries *q, const float *jac,
+                        int32_t max_aniso, uint32_t flags, const float *out)
+{
+    htex_status st = check_queries(q, HTEX_BILINEAR);
+    if (st) return st;
+    if (flags & ~HTEX_QUERIES_SORTED) return fail(HTEX_E_ARG, "unknown flags 0x%x", flags);
+    if (!pool->has_mips) return fail(HTEX_E_ARG, "anisotropic filtering needs a pool with mips");
+    if (max_aniso < 1 || max_aniso > HTEX_MAX_ANISO)
+        return fail(HTEX_E_ARG, "max_aniso %d outside [1, %d]", max_aniso, HTEX_MAX_ANISO);
+    if (q->Q > 0) {
+        if (!jac || !aligned(jac, 16)) return fail(HTEX_E_ARG, "jac must be 16-byte aligned");
+        if (!out || !aligned(out, 4 * (size_t)pool->channels))
+            return fail(HTEX_E_ARG, "out must be %d-byte aligned", 4 * pool->channels);
+    }
+    return HTEX_OK;
+}
+
+}  // namespace
+
+htex_status htex_sample_aniso(const htex_mesh *mesh, const htex_pool *pool,
+                              const htex_queries *queries, const float *jac, int32_t max_aniso,
+                              uint32_t flags, float *out, int32_t *nprobe, int32_t *err_count,
+                              void *stream)
+{
+    htex_status st = check_mesh(mesh);
+    if (!st) st = check_pool(pool, mesh);
+    if (st) return st;
+    if (!queries) return fail(HTEX_E_ARG, "queries is NULL");
+    st = check_aniso(pool, queries, jac, max_aniso, flags, out);
+    if (st) return st;
+    if (nprobe && !aligned(nprobe, 4)) return fail(HTEX_E_ARG, "nprobe must be 4-byte aligned");
+    if (queries->Q > 0 && mesh->H == 0) return fail(HTEX_E_ARG, "queries on an empty mesh");
+    htex::SampleArgs a = make_args(mesh, pool, queries);
+    a.qf = nullptr;
+    a.out = out;
+    a.err = err_count;
+    return from_hip(htex::launch_sample_aniso(a, pool->dtype, jac, max_aniso, nprobe,
+                                              static_cast<hipStream_t>(stream)),
+                    "anisotropic sample launch");
+}
+
+htex_status htex_sample_aniso_prepared(int32_t H, const void *prep, const htex_pool *pool,
+                                       const htex_queries *queries, const float *jac,
+                                       int32_t max_aniso, uint32_t flags, float *out,
+                                       int32_t *err_count, void *stream)
+{
+    htex_status st = check_pool(pool, nullptr);
+    if (st) return st;
+    if (!queries) return fail(HTEX_E_ARG, "queries is NULL");
+    st = check_aniso(pool, queries, jac, max_aniso, flags, out);
+    if (st) return st;
+    if (H < 0) return fail(HTEX_E_ARG, "negative H");
+    if (queries->Q > 0) {
+        if (H == 0) return fail(HTEX_E_ARG, "queries on an empty mesh");
+        if (!prep || !aligned(prep, 16)) return fail(HTEX_E_ARG, "prep must be 16-byte aligned");
+    }
+    htex::SampleArgs a{};
+    a.H = H;
+    a.channels = pool->channels;
+    a.texels = pool->texels;
+    a.scale = pool->scale;
+    a.Q = queries->Q;
+    a.qh = queries->h;
+    a.qu = queries->u;
+    a.qv = queries->v;
+    a.out = out;
+    a.err = err_count;
+    a.prep = prep;
+    return from_hip(htex::launch_sample_aniso(a, pool->dtype, jac, max_aniso, nullptr,
+                                              static_cast<hipStream_t>(stream)),
+                    "prepared anisotropic sample launch");
+}
+
 }  // extern "C"

@@ -75,6 +75,8 @@ hipError_t launch_serve(const ServeMesh *meshes, const ServeTile *tiles, int32_t
 hipError_t launch_backward(const SampleArgs &a, int filter, uint32_t flags, hipStream_t s);
 hipError_t launch_prepare(const SampleArgs &a, void *prep, hipStream_t s);
 hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, hipStream_t s);
+hipError_t launch_sample_aniso(const SampleArgs &a, int dtype, const float *jac, int max_aniso,
+                               int32_t *nprobe, hipStream_t s);
 hipError_t launch_build_mips(float *texels, const uint8_t *log2res, const int64_t *base,
                              int32_t E, int max_k, int channels, hipStream_t s);
 hipError_t launch_quantize_bf16(const float *src, uint16_t *dst, int64_t count,
