@@ -152,3 +152,24 @@ def test_product_path_refuses_cpu_tensors():
     m = htex
     with pytest.raises(TypeError):
         m._dev(torch.zeros(3, dtype=torch.int32), torch.int32, "h")
+
+
+def test_aniso_argument_checks():
+    L = _lib.load()
+    m, q = _mesh(), _q()
+    ok_pool = _pool()
+    # max_aniso outside [1, 16], no mips, misaligned derivatives, bad flags
+    assert L.htex_sample_aniso(C.byref(m), C.byref(ok_pool), C.byref(q), 16, 0, 0, 16, None, None,
+                               None) == -1
+    assert L.htex_sample_aniso(C.byref(m), C.byref(ok_pool), C.byref(q), 16, 17, 0, 16, None, None,
+                               None) == -1
+    assert L.htex_sample_aniso(C.byref(m), C.byref(_pool(mips=0)), C.byref(q), 16, 4, 0, 16, None,
+                               None, None) == -1
+    assert L.htex_sample_aniso(C.byref(m), C.byref(ok_pool), C.byref(q), 24, 4, 0, 16, None, None,
+                               None) == -1
+    assert L.htex_sample_aniso(C.byref(m), C.byref(ok_pool), C.byref(q), 16, 4, 1 << 5, 16, None,
+                               None, None) == -1
+    assert L.htex_sample_aniso_prepared(4, 16, C.byref(ok_pool), C.byref(q), 16, 0, 0, 16, None,
+                                        None) == -1
+    assert L.htex_sample_aniso_prepared(4, 24, C.byref(ok_pool), C.byref(q), 16, 4, 0, 16, None,
+                                        None) == -1
