@@ -57,6 +57,8 @@ def lib():
         L.ora_backward.argtypes = [p, p, C.c_int64, p, p, p, p, C.c_int, p, p, p]
         L.ora_build_mips.restype = None
         L.ora_build_mips.argtypes = [p, p]
+        L.ora_mip_backward.restype = None
+        L.ora_mip_backward.argtypes = [p, p]
         L.ora_f32_to_bf16.restype = C.c_uint16
         L.ora_f32_to_bf16.argtypes = [C.c_float]
         L.ora_bf16_to_f64.restype = C.c_double
@@ -189,6 +191,15 @@ def build_mips(pool: Pool) -> np.ndarray:
     p2 = Pool(pool.log2res, pool.base, tex, pool.has_mips)
     lib().ora_build_mips(C.byref(p2._s), _ptr(tex))
     return tex
+
+
+def mip_backward(pool: Pool, dtex) -> np.ndarray:
+    """Transpose of build_mips: gradients of every level folded into level 0
+    (returns a copy; see ora_mip_backward)."""
+    d = np.array(dtex, dtype=np.float64, copy=True, order="C")
+    p2 = Pool(pool.log2res, pool.base, np.zeros((1, d.shape[1])), pool.has_mips)
+    lib().ora_mip_backward(C.byref(p2._s), _ptr(d))
+    return d
 
 
 def f32_to_bf16(x):

@@ -568,6 +568,35 @@ void ora_corner_average(const ora_mesh *M, const int32_t *vert, const int32_t *f
     free(cnt);
 }
 
+/* Transpose of the mip chain (ora_build_mips) for gradients: when the
+ * coarser levels are box means of level 0, a gradient with respect to
+ * every stored level folds into one with respect to level 0.  Level l-1
+ * receives a quarter of the gradient of each level-l texel in each of the
+ * four texels it averages, from the coarsest level down, so level 0 ends
+ * with the total; each coarser level ends with its own gradient plus what
+ * came through the levels above it.  In place on `dtex` (pool-shaped). */
+void ora_mip_backward(const ora_pool *P, double *dtex)
+{
+    const int C = P->channels;
+    for (int32_t e = 0; e < P->E; ++e) {
+        int k = P->log2res[e];
+        for (int l = k; l >= 1; --l) {
+            int64_t n = (int64_t)1 << (k - l);
+            const double *src = dtex + C * (P->base[e] + level_offset(k, l));
+            double *dst = dtex + C * (P->base[e] + level_offset(k, l - 1));
+            for (int64_t j = 0; j < n; ++j)
+                for (int64_t i = 0; i < n; ++i)
+                    for (int c = 0; c < C; ++c) {
+                        double g = 0.25 * src[C * (j * n + i) + c];
+                        dst[C * ((2 * j) * (2 * n) + 2 * i) + c] += g;
+                        dst[C * ((2 * j) * (2 * n) + 2 * i + 1) + c] += g;
+                        dst[C * ((2 * j + 1) * (2 * n) + 2 * i) + c] += g;
+                        dst[C * ((2 * j + 1) * (2 * n) + 2 * i + 1) + c] += g;
+                    }
+        }
+    }
+}
+
 /* -------------------------------------------------------- quantization */
 
 /* bfloat16: the upper 16 bits of a binary32 after rounding its significand

@@ -46,6 +46,7 @@ int64_t ora_backward(const ora_mesh *M, const ora_pool *P, int64_t Q, const int3
                      const float *u, const float *v, const float *f, int filter,
                      const double *dout, double *dtex, double *dabs);
 void ora_build_mips(const ora_pool *P, double *texels);
+void ora_mip_backward(const ora_pool *P, double *dtex);
 uint16_t ora_f32_to_bf16(float x);
 double ora_bf16_to_f64(uint16_t c);
 double ora_e4m3_to_f64(uint8_t c);
