@@ -167,6 +167,18 @@ htex_status htex_mesh_validate(const htex_mesh *mesh, int32_t *first_bad_host,
  * the same memory as pool->texels, writable. */
 htex_status htex_build_mips(const htex_pool *pool, void *texels_rw, void *stream);
 
+/* Transpose of htex_build_mips, for training a pool whose coarser levels
+ * are box means of level 0: in place on `dtexels` (float32, the pool's
+ * layout and channels, aligned to 4 C bytes), from the coarsest level
+ * down, each texel of level l adds a quarter of its gradient to each of the
+ * four level-(l-1) texels it averages.  Level 0 then holds the gradient
+ * with respect to level 0 through every level (what an optimizer of level
+ * 0 needs); with clear_coarse = 1 the coarser levels are zeroed as they
+ * are folded, otherwise each keeps its own gradient plus what came from
+ * the levels above it.  Needs has_mips; the pool's texels are not read. */
+htex_status htex_mip_backward(const htex_pool *pool, float *dtexels, int32_t clear_coarse,
+                              void *stream);
+
 /* Corner pre-processing (Section 4.4, "Corner Pre-processing"), in place on
  * a float32 pool: on every level of n >= 2 texels per side, the corner
  * texels that lie on one mesh vertex, or on one face centroid, all receive

@@ -18,7 +18,7 @@ from ._lib import (DEBUG_FIELDS, HTEX_BF16, HTEX_BILINEAR, HTEX_F32, HTEX_FP8_E4
                    HTEX_QUERIES_SORTED, HTEX_TRILINEAR, HtexError, check, load)
 
 __all__ = ["Mesh", "Pool", "htex_pool_layout", "htex_mesh_validate", "htex_build_mips",
-           "htex_corner_average", "htex_quantize", "htex_sample", "htex_sample_backward", "HtexSample",
+           "htex_corner_average", "htex_mip_backward", "htex_quantize", "htex_sample", "htex_sample_backward", "HtexSample",
            "htex_prepare", "htex_sample_prepared", "Prepared",
            "htex_sample_aniso", "htex_sample_aniso_prepared",
            "htex_sort_queries", "htex_permute_queries", "htex_unpermute_results",
@@ -129,6 +129,18 @@ def htex_mesh_validate(mesh: Mesh, stream=None):
 
 def htex_build_mips(pool: Pool, stream=None):
     check(load().htex_build_mips(C.byref(pool.c), pool.texels.data_ptr(), _stream(stream)))
+
+
+def htex_mip_backward(pool: Pool, dtexels: torch.Tensor, clear_coarse: bool = False,
+                      stream=None) -> torch.Tensor:
+    """Transpose of htex_build_mips on a pool-shaped float32 gradient, in
+    place: level 0 receives the gradient through every coarser level."""
+    _dev(dtexels, torch.float32, "dtexels")
+    if dtexels.shape != (pool.total, pool.channels):
+        raise ValueError("dtexels must have the pool's shape")
+    check(load().htex_mip_backward(C.byref(pool.c), dtexels.data_ptr(), int(bool(clear_coarse)),
+                                   _stream(stream)))
+    return dtexels
 
 
 def htex_corner_average(mesh: Mesh, pool: Pool, err_count: torch.Tensor | None = None,
@@ -318,17 +330,22 @@ def htex_sample_backward(mesh: Mesh, pool: Pool, h, u, v, dout, footprint=None,
 class HtexSample(torch.autograd.Function):
     """Differentiable sampling with respect to a float32 pool's texels.
 
-    forward(texels, mesh, pool, h, u, v, footprint, filter, flags) -> [Q, C];
-    the gradient flows to `texels` (which must be pool.texels)."""
+    forward(texels, mesh, pool, h, u, v, footprint, filter, flags,
+    mips_from_level0) -> [Q, C]; the gradient flows to `texels` (which must
+    be pool.texels).  With mips_from_level0 the pool's coarser levels are
+    taken to be box means of level 0 (rebuild them with htex_build_mips
+    after each update): the gradient is folded into level 0 through the
+    transposed mip chain and is zero on the coarser levels."""
 
     @staticmethod
     def forward(ctx, texels, mesh, pool, h, u, v, footprint=None, filter=HTEX_BILINEAR,
-                flags=0):
+                flags=0, mips_from_level0=False):
         if texels.data_ptr() != pool.texels.data_ptr():
             raise ValueError("texels must be pool.texels")
         out, _ = htex_sample(mesh, pool, h, u, v, footprint, filter, flags)
         ctx.save_for_backward(h, u, v, footprint)
         ctx.mesh, ctx.pool, ctx.filter, ctx.flags = mesh, pool, filter, flags
+        ctx.mips = bool(mips_from_level0)
         return out
 
     @staticmethod
@@ -336,4 +353,6 @@ class HtexSample(torch.autograd.Function):
         h, u, v, footprint = ctx.saved_tensors
         d = htex_sample_backward(ctx.mesh, ctx.pool, h, u, v, gout.contiguous(), footprint,
                                  ctx.filter, ctx.flags)
-        return d, None, None, None, None, None, None, None, None
+        if ctx.mips:
+            htex_mip_backward(ctx.pool, d, clear_coarse=True)
+        return d, None, None, None, None, None, None, None, None, None

@@ -58,6 +58,7 @@ SIGNATURES = {
     "htex_mesh_validate": (C.c_int32, [_P, _P, _P]),
     "htex_build_mips": (C.c_int32, [_P, _P, _P]),
     "htex_corner_average": (C.c_int32, [_P, _P, _P, _P, _P]),
+    "htex_mip_backward": (C.c_int32, [_P, _P, C.c_int32, _P]),
     "htex_quantize": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
     "htex_sample": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_uint32, _P, _P, _P, _P]),
     "htex_sample_backward": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_uint32, _P, _P, _P]),

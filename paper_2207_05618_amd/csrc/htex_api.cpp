@@ -210,6 +210,22 @@ htex_status htex_build_mips(const htex_pool *pool, void *texels_rw, void *stream
                     "mip build");
 }
 
+htex_status htex_mip_backward(const htex_pool *pool, float *dtexels, int32_t clear_coarse,
+                              void *stream)
+{
+    htex_status st = check_pool(pool, nullptr);
+    if (st) return st;
+    if (!pool->has_mips) return fail(HTEX_E_ARG, "pool has no mip levels");
+    if (clear_coarse != 0 && clear_coarse != 1) return fail(HTEX_E_ARG, "clear_coarse must be 0 or 1");
+    if (pool->total_texels > 0 && (!dtexels || !aligned(dtexels, 4 * (size_t)pool->channels)))
+        return fail(HTEX_E_ARG, "dtexels must be non-NULL and %d-byte aligned",
+                    4 * pool->channels);
+    return from_hip(htex::launch_mip_backward(dtexels, pool->log2res, pool->base, pool->E,
+                                              pool->max_log2res, pool->channels, clear_coarse,
+                                              static_cast<hipStream_t>(stream)),
+                    "mip backward");
+}
+
 htex_status htex_corner_average(const htex_mesh *mesh, const htex_pool *pool, void *texels_rw,
                                 int32_t *err_count, void *stream)
 {

@@ -79,6 +79,8 @@ hipError_t launch_sample_aniso(const SampleArgs &a, int dtype, const float *jac,
                                int32_t *nprobe, hipStream_t s);
 hipError_t launch_build_mips(float *texels, const uint8_t *log2res, const int64_t *base,
                              int32_t E, int max_k, int channels, hipStream_t s);
+hipError_t launch_mip_backward(float *dtex, const uint8_t *log2res, const int64_t *base, int32_t E,
+                               int max_k, int channels, int clear, hipStream_t s);
 hipError_t launch_quantize_bf16(const float *src, uint16_t *dst, int64_t count,
                                 hipStream_t s);
 hipError_t launch_quantize_fp8(const float *src, uint8_t *dst, float *scale,

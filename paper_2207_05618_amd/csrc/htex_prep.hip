@@ -42,6 +42,52 @@ __global__ void k_mip_level(T *tex, const uint8_t *log2res, const int64_t *base,
     }
 }
 
+// Transpose of one mip step for gradients: every texel of level l hands a
+// quarter of its gradient to each of the four level-(l-1) texels it is the
+// mean of (one lane per level-l texel, so no two lanes write one texel),
+// and is cleared afterwards when `clear` is set.
+__device__ __forceinline__ void quarter_add(float4 &d, const float4 &g)
+{
+    d.x += g.x;
+    d.y += g.y;
+    d.z += g.z;
+    d.w += g.w;
+}
+
+__device__ __forceinline__ void quarter_add(float &d, float g) { d += g; }
+
+__device__ __forceinline__ float4 quarter(const float4 &g)
+{
+    return make_float4(0.25f * g.x, 0.25f * g.y, 0.25f * g.z, 0.25f * g.w);
+}
+
+__device__ __forceinline__ float quarter(float g) { return 0.25f * g; }
+
+template <typename T>
+__global__ void k_mip_backward_level(T *d, const uint8_t *log2res, const int64_t *base, int32_t E,
+                                     int l, int clear)
+{
+    for (int64_t e = blockIdx.x; e < E; e += gridDim.x) {
+        const int k = log2res[e];
+        if (k < l) continue;
+        const int m = k - l;
+        const int32_t n = 1 << m;
+        const int64_t src = base[e] + level_offset(k, l);
+        const int64_t dst = base[e] + level_offset(k, l - 1);
+        for (int32_t t = threadIdx.x; t < n * n; t += blockDim.x) {
+            const int32_t i = t & (n - 1), j = t >> m;
+            const T g = quarter(d[src + t]);
+            const int64_t r0 = dst + (int64_t)(2 * j) * (2 * n) + 2 * i;
+            const int64_t r1 = r0 + 2 * n;
+            quarter_add(d[r0], g);
+            quarter_add(d[r0 + 1], g);
+            quarter_add(d[r1], g);
+            quarter_add(d[r1 + 1], g);
+            if (clear) d[src + t] = T{};
+        }
+    }
+}
+
 // float32 -> bfloat16, round to nearest even; NaN stays a quiet NaN.
 __device__ __forceinline__ uint16_t to_bf16(float x)
 {
@@ -161,6 +207,25 @@ hipError_t launch_build_mips(float *texels, const uint8_t *log2res, const int64_
         else
             hipLaunchKernelGGL(k_mip_level<float>, dim3(grid), dim3(threads), 0, s, texels,
                                log2res, base, E, l);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_mip_backward(float *dtex, const uint8_t *log2res, const int64_t *base, int32_t E,
+                               int max_k, int channels, int clear, hipStream_t s)
+{
+    if (E == 0) return hipSuccess;
+    for (int l = max_k; l >= 1; --l) {
+        const int threads = (max_k - l) >= 4 ? 256 : 64;
+        const uint32_t grid = (uint32_t)(E < (1 << 20) ? E : (1 << 20));
+        if (channels == 4)
+            hipLaunchKernelGGL(k_mip_backward_level<float4>, dim3(grid), dim3(threads), 0, s,
+                               reinterpret_cast<float4 *>(dtex), log2res, base, E, l, clear);
+        else
+            hipLaunchKernelGGL(k_mip_backward_level<float>, dim3(grid), dim3(threads), 0, s, dtex,
+                               log2res, base, E, l, clear);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
