@@ -249,10 +249,69 @@ def grad_benchmark(steps=200):
     torch.cuda.synchronize()
     fit_s = time.perf_counter() - t0
     tex.requires_grad_(False)
+    tri = grad_trilinear(m, dm, q, timed, steps)
     return {"queries": q.Q, "edges": int(m.E), "texels": int(total),
             "forward_samples_per_s": q.Q / t_fwd, "backward_samples_per_s": q.Q / t_bwd,
             "forward_us": t_fwd * 1e6, "backward_us": t_bwd * 1e6,
             "backward_plain_atomics_us": t_bwd_plain * 1e6,
+            "adam_steps": steps, "adam_seconds": fit_s, "loss_first": losses[0],
+            "loss_last": losses[-1], "loss_reduction": losses[0] / max(losses[-1], 1e-30),
+            "loss_curve_every_20": losses, "trilinear_level0": tri}
+
+
+def grad_trilinear(m, dm, q, timed, steps):
+    """Trilinear training of level 0: the same cube and queries with 32x32
+    textures and their mips, log2 footprints ~ U[-8, 0]; forward, backward,
+    the mip-chain transpose, and Adam on level 0 with the mips rebuilt from
+    it before every step."""
+    import numpy as np
+    import torch
+
+    import paper_2207_05618_amd as htex
+    from htexgen import pool as gpool
+
+    lr = np.full(m.E, 5, np.uint8)
+    base, total = gpool.layout(lr, True)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    target = htex.Pool(lr, True, texels=T(gpool.fill_level0_host(1, 401, lr, base, total,
+                                                                  m.boundary_edges(), True)))
+    htex.htex_build_mips(target)
+    f = T(np.exp2(np.random.default_rng(406).uniform(-8, 0, q.Q)).astype(np.float32))
+    h, u, v = T(q.h), T(q.u), T(q.v)
+    S, TRI = htex.HTEX_QUERIES_SORTED, htex.HTEX_TRILINEAR
+    y, _ = htex.htex_sample(dm, target, h, u, v, f, filter=TRI)
+    tex = torch.full((total, 4), 0.5, dtype=torch.float32, device="cuda")
+    pool = htex.Pool(lr, True, texels=tex)
+    htex.htex_build_mips(pool)
+    g = torch.from_numpy(np.random.default_rng(407).standard_normal((q.Q, 4)).astype(
+        np.float32)).cuda()
+    out = torch.empty_like(y)
+    dtex = torch.zeros_like(tex)
+    t_fwd = timed(lambda: htex.htex_sample(dm, pool, h, u, v, f, filter=TRI, flags=S, out=out))
+    t_bwd = timed(lambda: htex.htex_sample_backward(dm, pool, h, u, v, g, f, filter=TRI, flags=S,
+                                                    dtexels=dtex))
+    t_mip = timed(lambda: htex.htex_mip_backward(pool, dtex))
+    t_mips = timed(lambda: htex.htex_build_mips(pool))
+    tex.requires_grad_(True)
+    opt = torch.optim.Adam([tex], lr=0.02)
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(steps):
+        with torch.no_grad():
+            htex.htex_build_mips(pool)
+        opt.zero_grad(set_to_none=False)
+        o = htex.HtexSample.apply(tex, dm, pool, h, u, v, f, TRI, S, True)
+        loss = ((o - y) ** 2).mean()
+        loss.backward()
+        opt.step()
+        if it % 20 == 0 or it == steps - 1:
+            losses.append(float(loss.item()))
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t0
+    tex.requires_grad_(False)
+    return {"texels": int(total), "forward_us": t_fwd * 1e6, "backward_us": t_bwd * 1e6,
+            "mip_backward_us": t_mip * 1e6, "build_mips_us": t_mips * 1e6,
             "adam_steps": steps, "adam_seconds": fit_s, "loss_first": losses[0],
             "loss_last": losses[-1], "loss_reduction": losses[0] / max(losses[-1], 1e-30),
             "loss_curve_every_20": losses}
