@@ -78,6 +78,8 @@ def lib():
         L.ora_texture_fetch.restype = None
         L.ora_texture_fetch.argtypes = [p, C.c_int32, C.c_int, C.c_double, C.c_double,
                                         C.c_double, p, p]
+        L.ora_triangle_vertices.restype = C.c_int64
+        L.ora_triangle_vertices.argtypes = [p, p, C.c_int32, p, p]
         L.ora_corner_average.restype = None
         L.ora_corner_average.argtypes = [p, p, p, C.c_int32, C.c_int32, p, p]
         L.ora_validate.restype = C.c_int
@@ -246,6 +248,17 @@ def quantize_e4m3(log2res, base, has_mips, texels_f32):
     scale = np.zeros(p.E, dtype=np.float32)
     lib().ora_quantize_e4m3(C.byref(p._s), _ptr(t), t.shape[0], _ptr(codes), _ptr(scale))
     return codes, scale
+
+
+def triangle_vertices(mesh: Mesh, vert, positions):
+    """Alg. 1 for every halfedge: float64 [H, 3, 3] = (v0, v1, v2) per
+    intrinsic triangle, and the number of halfedges that could not be
+    resolved (NaN rows)."""
+    vt = _c(vert, np.int32)
+    pos = _c(positions, np.float64).reshape(-1, 3)
+    out = np.empty((mesh.H, 3, 3), dtype=np.float64)
+    bad = lib().ora_triangle_vertices(C.byref(mesh._s), _ptr(vt), len(pos), _ptr(pos), _ptr(out))
+    return out, int(bad)
 
 
 def corner_average(mesh: Mesh, pool: Pool, vert, face, V: int, F: int) -> np.ndarray:

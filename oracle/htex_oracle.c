@@ -496,6 +496,51 @@ void ora_build_mips(const ora_pool *P, double *texels)
     }
 }
 
+/* ------------------------------------- intrinsic triangles (Sec. 3.1, Alg. 1) */
+
+/* The triangle of halfedge h (Alg. 1): v0 = the position of Vert(Next h),
+ * v2 = that of Vert(h), and v1 = the mean of the positions of the vertices
+ * of h's face, gathered by following Next from h until it returns.  Section
+ * 4.2 gives its barycentric frame: (u, v, w) = (1, 0, 0) is v2, (0, 1, 0)
+ * is v0 and (0, 0, 1) is v1.  pos is [V][3]; out is [H][3][3] = v0, v1, v2.
+ * Returns the number of halfedges whose face walk does not return within
+ * H steps or names a vertex outside [0, V) (their rows are NaN). */
+int64_t ora_triangle_vertices(const ora_mesh *M, const int32_t *vert, int32_t V, const double *pos,
+                              double *out)
+{
+    int64_t bad = 0;
+    for (int32_t h = 0; h < M->H; ++h) {
+        double *o = out + 9 * (int64_t)h;
+        double c[3] = {0, 0, 0};
+        int64_t n = 0;
+        int32_t g = h;
+        int ok = 1;
+        do {
+            if (g < 0 || g >= M->H || vert[g] < 0 || vert[g] >= V || n > M->H) {
+                ok = 0;
+                break;
+            }
+            for (int d = 0; d < 3; ++d)
+                c[d] += pos[3 * (int64_t)vert[g] + d];
+            n += 1;
+            g = M->next[g];
+        } while (g != h);
+        const int32_t nx = M->next[h];
+        if (!ok || nx < 0 || nx >= M->H || vert[nx] < 0 || vert[nx] >= V) {
+            for (int d = 0; d < 9; ++d)
+                o[d] = NAN;
+            bad += 1;
+            continue;
+        }
+        for (int d = 0; d < 3; ++d) {
+            o[d] = pos[3 * (int64_t)vert[nx] + d];
+            o[3 + d] = c[d] / (double)n;
+            o[6 + d] = pos[3 * (int64_t)vert[h] + d];
+        }
+    }
+    return bad;
+}
+
 /* ------------------------------------------ corner pre-processing (Sec. 4.4) */
 
 /* Quad corners on the mesh.  The halfedge g of an edge with the larger id
