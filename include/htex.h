@@ -167,6 +167,22 @@ htex_status htex_mesh_validate(const htex_mesh *mesh, int32_t *first_bad_host,
  * the same memory as pool->texels, writable. */
 htex_status htex_build_mips(const htex_pool *pool, void *texels_rw, void *stream);
 
+/* Intrinsic triangle of every halfedge (Section 3.1, Alg. 1): out[h] =
+ * (v0, v1, v2) as 9 floats, v0 = positions[Vert(Next h)], v2 =
+ * positions[Vert(h)], v1 = the mean of the positions of the vertices of h's
+ * face (found by following Next from h), summed in float64 from the face's
+ * smallest halfedge and rounded once (every triangle of a face gets the
+ * same v1 bit for bit).  Section 4.2's frame: the
+ * query (h, u, v) is the point u v2 + v v0 + (1 - u - v) v1.  vert: device
+ * int32 [H] (the Vert operator, not part of htex_mesh since sampling never
+ * needs it); positions: device float32 [V][3]; out: device float32 [H][9].
+ * A face ring longer than 65536 halfedges, a walk leaving [0, H) or a
+ * vertex id outside [0, V) gives a NaN row and increments *err_count
+ * (device, nullable). */
+htex_status htex_triangle_vertices(const htex_mesh *mesh, const int32_t *vert, int32_t V,
+                                   const float *positions, float *out, int32_t *err_count,
+                                   void *stream);
+
 /* Transpose of htex_build_mips, for training a pool whose coarser levels
  * are box means of level 0: in place on `dtexels` (float32, the pool's
  * layout and channels, aligned to 4 C bytes), from the coarsest level

@@ -18,7 +18,8 @@ from ._lib import (DEBUG_FIELDS, HTEX_BF16, HTEX_BILINEAR, HTEX_F32, HTEX_FP8_E4
                    HTEX_QUERIES_SORTED, HTEX_TRILINEAR, HtexError, check, load)
 
 __all__ = ["Mesh", "Pool", "htex_pool_layout", "htex_mesh_validate", "htex_build_mips",
-           "htex_corner_average", "htex_mip_backward", "htex_quantize", "htex_sample", "htex_sample_backward", "HtexSample",
+           "htex_corner_average", "htex_mip_backward", "htex_triangle_vertices",
+           "htex_quantize", "htex_sample", "htex_sample_backward", "HtexSample",
            "htex_prepare", "htex_sample_prepared", "Prepared",
            "htex_sample_aniso", "htex_sample_aniso_prepared",
            "htex_sort_queries", "htex_permute_queries", "htex_unpermute_results",
@@ -129,6 +130,20 @@ def htex_mesh_validate(mesh: Mesh, stream=None):
 
 def htex_build_mips(pool: Pool, stream=None):
     check(load().htex_build_mips(C.byref(pool.c), pool.texels.data_ptr(), _stream(stream)))
+
+
+def htex_triangle_vertices(mesh: Mesh, vert, positions, err_count=None, stream=None):
+    """Alg. 1 on the device -> float32 [H, 3, 3] = (v0, v1, v2) per halfedge."""
+    vert = _dev(vert, torch.int32, "vert")
+    positions = _dev(positions, torch.float32, "positions")
+    if positions.dim() != 2 or positions.shape[1] != 3:
+        raise ValueError("positions must be [V, 3]")
+    out = torch.empty((mesh.H, 3, 3), dtype=torch.float32, device=vert.device)
+    err = None if err_count is None else _dev(err_count, torch.int32, "err_count").data_ptr()
+    check(load().htex_triangle_vertices(C.byref(mesh.c), vert.data_ptr(), positions.shape[0],
+                                        positions.data_ptr(), out.data_ptr(), err,
+                                        _stream(stream)))
+    return out
 
 
 def htex_mip_backward(pool: Pool, dtexels: torch.Tensor, clear_coarse: bool = False,

@@ -59,6 +59,7 @@ SIGNATURES = {
     "htex_build_mips": (C.c_int32, [_P, _P, _P]),
     "htex_corner_average": (C.c_int32, [_P, _P, _P, _P, _P]),
     "htex_mip_backward": (C.c_int32, [_P, _P, C.c_int32, _P]),
+    "htex_triangle_vertices": (C.c_int32, [_P, _P, C.c_int32, _P, _P, _P, _P]),
     "htex_quantize": (C.c_int32, [_P, C.c_int32, _P, _P, _P]),
     "htex_sample": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_uint32, _P, _P, _P, _P]),
     "htex_sample_backward": (C.c_int32, [_P, _P, _P, C.c_int32, C.c_uint32, _P, _P, _P]),

@@ -210,6 +210,23 @@ htex_status htex_build_mips(const htex_pool *pool, void *texels_rw, void *stream
                     "mip build");
 }
 
+htex_status htex_triangle_vertices(const htex_mesh *mesh, const int32_t *vert, int32_t V,
+                                   const float *positions, float *out, int32_t *err_count,
+                                   void *stream)
+{
+    htex_status st = check_mesh(mesh);
+    if (st) return st;
+    if (V < 0) return fail(HTEX_E_ARG, "negative V");
+    if (mesh->H > 0 && (!vert || !positions || !out))
+        return fail(HTEX_E_ARG, "vert, positions and out must be non-NULL");
+    if (mesh->H > 0 && V == 0) return fail(HTEX_E_ARG, "a mesh with halfedges needs vertices");
+    if (!aligned(vert, 4) || !aligned(positions, 4) || !aligned(out, 4))
+        return fail(HTEX_E_ARG, "arrays must be 4-byte aligned");
+    return from_hip(htex::launch_triangle_vertices(*mesh, vert, V, positions, out, err_count,
+                                                   static_cast<hipStream_t>(stream)),
+                    "triangle vertices");
+}
+
 htex_status htex_mip_backward(const htex_pool *pool, float *dtexels, int32_t clear_coarse,
                               void *stream)
 {

@@ -89,6 +89,8 @@ hipError_t launch_quantize_fp8(const float *src, uint8_t *dst, float *scale,
 hipError_t launch_corner_average(const htex_mesh &m, float *texels, const uint8_t *log2res,
                                  const int64_t *base, int channels, int has_mips, int kmax,
                                  int32_t *err, hipStream_t s);
+hipError_t launch_triangle_vertices(const htex_mesh &m, const int32_t *vert, int32_t V,
+                                    const float *pos, float *out, int32_t *err, hipStream_t s);
 hipError_t launch_validate(const htex_mesh &m, int32_t *ws_use, int32_t *ws_bad,
                            hipStream_t s);
 
