@@ -404,6 +404,73 @@ def displacement_benchmark(mesh, dmesh, rgb_step, Q_rgb, T=4, n_iter=10, with_by
     return res
 
 
+# ------------------------------------------------------- rasterized view --
+
+def raster_benchmark(mesh, dmesh, prep, pool, n_iter=10):
+    """A rendered 4K view of the frame mesh instead of synthetic queries:
+    the intrinsic triangles (Alg. 1) on the device, then a software
+    rasterizer on the host gives one query per covered pixel with its
+    perspective-correct (u, v) and screen derivatives.  Trilinear (footprint
+    = the longer derivative) and anisotropic sampling, in scanline order and
+    in halfedge order."""
+    import numpy as np
+    import torch
+
+    import paper_2207_05618_amd as htex
+    from htexgen.raster import rasterize, sphere_view
+
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    vert, pos = T(mesh.vert), T(mesh.positions.astype(np.float32))
+    htex.htex_triangle_vertices(dmesh, vert, pos)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    tri = htex.htex_triangle_vertices(dmesh, vert, pos)
+    e1.record()
+    torch.cuda.synchronize()
+    alg1_us = e0.elapsed_time(e1) * 1e3
+    t0 = time.perf_counter()
+    cam = sphere_view()
+    fr = rasterize(tri.cpu().numpy().astype(np.float64), cam)
+    raster_s = time.perf_counter() - t0
+    f = fr.footprint()
+    order = np.argsort(fr.h, kind="stable")
+    scan = (T(fr.h), T(fr.u), T(fr.v), T(f), T(fr.jac))
+    srt = (T(fr.h[order]), T(fr.u[order]), T(fr.v[order]), T(f[order]), T(fr.jac[order]))
+    out = torch.empty((fr.Q, 4), dtype=torch.float32, device="cuda")
+    TRI, S = htex.HTEX_TRILINEAR, htex.HTEX_QUERIES_SORTED
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(n_iter):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t1) / n_iter
+
+    res = {"width": cam.width, "height": cam.height, "queries": int(fr.Q),
+           "coverage": fr.Q / (cam.width * cam.height),
+           "visible_halfedges": int(len(np.unique(fr.h))), "alg1_kernel_us": alg1_us,
+           "host_raster_s": raster_s,
+           "log2_footprint_p5_p50_p95": [float(x) for x in np.percentile(np.log2(f), [5, 50, 95])]}
+    for name, (h, u, v, ff, jac), flags in (("scanline", scan, 0), ("halfedge_order", srt, S)):
+        t_tri = timed(lambda: htex.htex_sample_prepared(prep, pool, h, u, v, ff, filter=TRI,
+                                                        flags=flags, out=out))
+        t_an = timed(lambda: htex.htex_sample_aniso_prepared(prep, pool, h, u, v, jac,
+                                                             flags=flags, out=out))
+        res[name] = {"trilinear_samples_per_s": fr.Q / t_tri, "trilinear_ms": t_tri * 1e3,
+                     "aniso_samples_per_s": fr.Q / t_an, "aniso_ms": t_an * 1e3}
+    j = fr.jac.astype(np.float64)
+    px, py = np.hypot(j[:, 0], j[:, 1]), np.hypot(j[:, 2], j[:, 3])
+    with np.errstate(divide="ignore"):
+        res["mean_probes"] = float(np.minimum(np.ceil(np.maximum(px, py) / np.minimum(px, py)),
+                                              16).mean())
+    del scan, srt, out, tri
+    return res
+
+
 # ------------------------------------------------------------ anisotropy --
 
 def aniso_benchmark(prep, pool, batches, dev_batches, Q, max_aniso=16, n_iter=10):
@@ -769,6 +836,8 @@ def main():
         if args.workload == "frame4k":
             extra["rgb_plus_displacement"] = displacement_benchmark(
                 mesh, dmesh, step, Q, with_bytes=not args.no_bytes)
+            extra["rasterized_view"] = raster_benchmark(mesh, dmesh, prep, pool)
+            log(f"raster {json.dumps(extra['rasterized_view'])}")
             extra["anisotropic"] = aniso_benchmark(prep, pool, batches, dev_batches, Q)
             a = extra["anisotropic"]
             a["cost_vs_trilinear"] = value / a["samples_per_s"]

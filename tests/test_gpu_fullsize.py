@@ -220,3 +220,37 @@ def test_frame_displacement_sampled_parity_and_crack_free(disp_frame):
     assert len(pairs) > len(hs)
     got = o[idx]
     assert np.abs(got[pairs[:, 0]] - got[pairs[:, 1]]).max() < 4e-7
+
+
+# ------------------------------------------------------ rasterized 4K frame --
+
+def test_frame_rasterized_view_sampled_parity(frame):
+    """The benchmark's rasterized view of the frame mesh (3840 x 2160, the
+    oracle's intrinsic triangles): the whole frame sampled on the GPU in
+    scanline order (trilinear at each pixel's footprint, and anisotropic
+    with its derivatives); a contiguous run of pixels and scattered pixels
+    checked against the oracle."""
+    from htexgen.raster import rasterize, sphere_view
+    mesh, lr, pool, dm, q, out = frame
+    om = oracle.Mesh.of(mesh)
+    T, bad = oracle.triangle_vertices(om, mesh.vert, mesh.positions)
+    assert bad == 0
+    fr = rasterize(T, sphere_view())
+    f = fr.footprint()
+    prep = htex.Prepared(dm, pool)
+    o_tri = htex.htex_sample_prepared(prep, pool, t(fr.h), t(fr.u), t(fr.v), t(f),
+                                      filter=htex.HTEX_TRILINEAR)
+    o_an = htex.htex_sample_aniso_prepared(prep, pool, t(fr.h), t(fr.u), t(fr.v), t(fr.jac))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(12)
+    lo = fr.Q // 2
+    idx = np.unique(np.concatenate([np.arange(lo, lo + 2500), rng.choice(fr.Q, 500, replace=False)]))
+    from htexgen.queries import Queries
+    qs = Queries(fr.h[idx], fr.u[idx], fr.v[idx], f[idx])
+    sub_m, sub_p, remap = _oracle_for(mesh, lr, qs)
+    ref, errs, _ = oracle.sample(sub_m, sub_p, qs.h, qs.u, qs.v, qs.f, filter=oracle.TRILINEAR)
+    assert errs == 0
+    assert_rel(o_tri.cpu().numpy()[idx], ref, 1e-5)
+    ref_a, errs, _ = oracle.sample_aniso(sub_m, sub_p, qs.h, qs.u, qs.v, fr.jac[idx])
+    assert errs == 0
+    assert_rel(o_an.cpu().numpy()[idx], ref_a, 1e-5)
