@@ -698,25 +698,37 @@ __global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
 
 // Backward with a per-workgroup cache of gradient tiles in LDS.  A block
 // takes kBwdChunk consecutive queries (sorted queries meet few textures
-// there) and accumulates each tap into an LDS slot holding one (edge, level)
-// of at most kSlotFloats / CH texels; slots are claimed on first use by a
-// compare-and-swap on their tag and flushed to the gradient pool once, with
-// one float atomic per non-zero texel channel.  Taps of levels that are too
-// large, or that find every slot taken, go straight to global atomics.
-constexpr int kSlots = 4;
-constexpr int kSlotFloats = 4096;
+// there) and accumulates each tap into an on-chip tile holding one whole
+// (edge, level) of the gradient.  Tiles live in an arena of kArenaFloats
+// floats: the first tap of a new (edge, level) appends an entry to a table
+// of kTiles entries (tag, offset) and reserves the level's texels with an
+// atomic bump; later taps find the entry by a scan of the table.  Two lanes
+// may append the same (edge, level) at once; both tiles are flushed, so the
+// sums stay exact.  A level that no longer fits, or a full table, sends its
+// taps straight to global atomics.  At the end every tile is added to the
+// gradient pool once, one float atomic per non-zero texel channel.
+// Trilinear batches touch about 3 edges x 6 levels per block, which is why
+// tiles are sized per level rather than fixed.
+constexpr int kTiles = 32;
+constexpr int kArenaFloats = 16384;   // 64 KB
 constexpr int kBwdPerThread = 16;
 constexpr int kBwdChunk = kBlock * kBwdPerThread;
 
 template <int CH, bool TRI>
 __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
 {
-    constexpr int kSlotTexels = kSlotFloats / CH;
-    __shared__ float acc[kSlots][kSlotFloats];
-    __shared__ int32_t tag[kSlots];   // edge * 16 + level, or -1
-    float *accf = &acc[0][0];
-    for (int i = threadIdx.x; i < kSlots * kSlotFloats; i += kBlock) accf[i] = 0.0f;
-    if (threadIdx.x < kSlots) tag[threadIdx.x] = -1;
+    __shared__ float arena[kArenaFloats];
+    // entry = (edge * 16 + level) << 32 | float offset in the arena, written
+    // and read as one 64-bit word; kFree / kDead mark unused entries
+    __shared__ uint64_t entry[kTiles];
+    __shared__ int32_t ntiles, used;
+    constexpr uint64_t kFree = ~0ull, kDead = ~1ull;
+    for (int i = threadIdx.x; i < kArenaFloats; i += kBlock) arena[i] = 0.0f;
+    if (threadIdx.x < kTiles) entry[threadIdx.x] = kFree;
+    if (threadIdx.x == 0) {
+        ntiles = 0;
+        used = 0;
+    }
     __syncthreads();
     const int64_t q0 = (int64_t)blockIdx.x * kBwdChunk;
     for (int r = 0; r < kBwdPerThread; ++r) {
@@ -760,14 +772,28 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
                 if (!p.act) continue;
                 const int m = ks[s] - lv[sl];
                 const uint32_t lo = level_offset32(ks[s], lv[sl]);
-                // slot of this (edge, level), if it fits
-                int slot = -1;
-                if ((1 << (2 * m)) <= kSlotTexels) {
-                    const int32_t key = es[s] * 16 + lv[sl];
-                    for (int t = 0; t < kSlots && slot < 0; ++t) {
-                        int32_t cur = tag[t];
-                        if (cur == -1) cur = atomicCAS(&tag[t], -1, key);
-                        if (cur == -1 || cur == key) slot = t;
+                // the tile of this (edge, level): find it, or append it
+                const int32_t key = es[s] * 16 + lv[sl];
+                const int32_t need = CH << (2 * m);
+                int32_t base_f = -1;
+                const int32_t nt = min(__atomic_load_n(&ntiles, __ATOMIC_RELAXED), kTiles);
+                for (int t = 0; t < nt; ++t) {
+                    const uint64_t en = __atomic_load_n(&entry[t], __ATOMIC_RELAXED);
+                    if (en < kDead && (int32_t)(en >> 32) == key) {
+                        base_f = (int32_t)(en & 0xffffffffu);
+                        break;
+                    }
+                }
+                if (base_f < 0 && need <= kArenaFloats) {
+                    const int32_t t = atomicAdd(&ntiles, 1);
+                    if (t < kTiles) {
+                        const int32_t o = atomicAdd(&used, need);
+                        if (o + need <= kArenaFloats) {
+                            atomicExch(&entry[t], ((uint64_t)(uint32_t)key << 32) | (uint32_t)o);
+                            base_f = o;
+                        } else {
+                            atomicExch(&entry[t], kDead);
+                        }
                     }
                 }
                 const float w[4] = {p.wx0 * p.wy0, p.wx1 * p.wy0, p.wx0 * p.wy1, p.wx1 * p.wy1};
@@ -776,8 +802,8 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
                 for (int t = 0; t < 4; ++t) {
                     if (!((p.mask >> t) & 1)) continue;
                     const float wt = w[t] * rW;
-                    if (slot >= 0) {
-                        float *c = &acc[slot][CH * (off[t] - lo)];
+                    if (base_f >= 0) {
+                        float *c = &arena[base_f + CH * (int32_t)(off[t] - lo)];
                         atomicAdd(c + 0, wt * g4.x);
                         if constexpr (CH == 4) {
                             atomicAdd(c + 1, wt * g4.y);
@@ -798,16 +824,18 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
         }
     }
     __syncthreads();
-    // flush the claimed slots
-    for (int t = 0; t < kSlots; ++t) {
-        const int32_t key = tag[t];
-        if (key < 0) continue;
+    // flush the tiles
+    const int32_t nt = min(ntiles, kTiles);
+    for (int t = 0; t < nt; ++t) {
+        const uint64_t en = entry[t];
+        if (en >= kDead) continue;
+        const int32_t key = (int32_t)(en >> 32);
         const int32_t e = key >> 4, l = key & 15;
         const int k = a.log2res[e];
-        const int cnt = 1 << (2 * (k - l));
+        const int cnt = CH << (2 * (k - l));
         float *dst = a.dtex + CH * (a.base[e] + level_offset32(k, l));
-        const float *src = &acc[t][0];
-        for (int i = threadIdx.x; i < CH * cnt; i += kBlock) {
+        const float *src = &arena[(int32_t)(en & 0xffffffffu)];
+        for (int i = threadIdx.x; i < cnt; i += kBlock) {
             const float val = src[i];
             if (val != 0.0f) unsafeAtomicAdd(dst + i, val);
         }
