@@ -80,6 +80,8 @@ def lib():
                                         C.c_double, p, p]
         L.ora_triangle_vertices.restype = C.c_int64
         L.ora_triangle_vertices.argtypes = [p, p, C.c_int32, p, p]
+        L.ora_texel_positions.restype = None
+        L.ora_texel_positions.argtypes = [p, p, p, p]
         L.ora_corner_average.restype = None
         L.ora_corner_average.argtypes = [p, p, p, C.c_int32, C.c_int32, p, p]
         L.ora_validate.restype = C.c_int
@@ -259,6 +261,15 @@ def triangle_vertices(mesh: Mesh, vert, positions):
     out = np.empty((mesh.H, 3, 3), dtype=np.float64)
     bad = lib().ora_triangle_vertices(C.byref(mesh._s), _ptr(vt), len(pos), _ptr(pos), _ptr(out))
     return out, int(bad)
+
+
+def texel_positions(mesh: Mesh, tri, pool: Pool) -> np.ndarray:
+    """Surface point of every texel centre (Section 4.2 read backwards,
+    Alg. 1 triangles `tri` [H, 3, 3]): float64 [total, 3], NaN on padding."""
+    T = _c(tri, np.float64)
+    out = np.full((len(pool.texels), 3), np.nan)
+    lib().ora_texel_positions(C.byref(mesh._s), _ptr(T), C.byref(pool._s), _ptr(out))
+    return out
 
 
 def corner_average(mesh: Mesh, pool: Pool, vert, face, V: int, F: int) -> np.ndarray:

@@ -541,6 +541,51 @@ int64_t ora_triangle_vertices(const ora_mesh *M, const int32_t *vert, int32_t V,
     return bad;
 }
 
+/* Surface point of every texel centre (Section 4.2 read backwards): texel
+ * (i, j) of a level of n texels sits at quad coordinates x = (i + 1/2) / n,
+ * y = (j + 1/2) / n.  Where x + y <= 1 it lies on the triangle of the
+ * edge's larger halfedge g with (u, v) = (x, y) (Alg. 2 keeps them);
+ * elsewhere on the twin's triangle with (u, v) = (1 - x, 1 - y) (Alg. 2
+ * reflects them); a boundary edge has no twin and mirrors its lower-left
+ * half across x + y = 1, so such a texel takes the point of its mirror
+ * image (n-1-j, n-1-i).  The point is u v2 + v v0 + (1 - u - v) v1 of that
+ * triangle (Alg. 1, ora_triangle_vertices).  tri is [H][3][3]; out is
+ * [total][3] (padding texels are left untouched). */
+void ora_texel_positions(const ora_mesh *M, const double *tri, const ora_pool *P, double *out)
+{
+    for (int32_t g = 0; g < M->H; ++g) {
+        const int32_t t = M->twin[g];
+        if (!(g > t))
+            continue;
+        const int32_t e = M->edge[g];
+        const int k = P->log2res[e];
+        for (int l = 0; l <= (P->has_mips ? k : 0); ++l) {
+            const int64_t n = (int64_t)1 << (k - l);
+            const int64_t lv = P->base[e] + level_offset(k, l);
+            for (int64_t j = 0; j < n; ++j)
+                for (int64_t i = 0; i < n; ++i) {
+                    int64_t si = i, sj = j;
+                    if (t < 0 && i + j > n - 1) {
+                        si = n - 1 - j;
+                        sj = n - 1 - i;
+                    }
+                    const double x = (si + 0.5) / (double)n, y = (sj + 0.5) / (double)n;
+                    int32_t hh = g;
+                    double u = x, v = y;
+                    if (x + y > 1.0) {
+                        hh = t;
+                        u = 1.0 - x;
+                        v = 1.0 - y;
+                    }
+                    const double *T = tri + 9 * (int64_t)hh;
+                    const double w = 1.0 - u - v;
+                    for (int d = 0; d < 3; ++d)
+                        out[3 * (lv + j * n + i) + d] = u * T[6 + d] + v * T[d] + w * T[3 + d];
+                }
+        }
+    }
+}
+
 /* ------------------------------------------ corner pre-processing (Sec. 4.4) */
 
 /* Quad corners on the mesh.  The halfedge g of an edge with the larger id

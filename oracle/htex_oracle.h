@@ -61,6 +61,7 @@ void ora_texture_fetch(const ora_pool *P, int32_t e, int filter, double f, doubl
                        double y, double C[4], double *W);
 int64_t ora_triangle_vertices(const ora_mesh *M, const int32_t *vert, int32_t V, const double *pos,
                               double *out);
+void ora_texel_positions(const ora_mesh *M, const double *tri, const ora_pool *P, double *out);
 void ora_corner_average(const ora_mesh *M, const int32_t *vert, const int32_t *face, int32_t V,
                         int32_t F, const ora_pool *P, double *texels);
 int ora_validate(const ora_mesh *M, const int32_t *vert, int32_t *first_bad);
