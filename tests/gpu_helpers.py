@@ -73,7 +73,9 @@ def assert_debug_equal(dg, do, wtol=1e-5):
     valid = dg["next"] >= 0
     np.testing.assert_allclose(dg["W"][valid], do["W"][valid], rtol=wtol, atol=1e-6)
     np.testing.assert_allclose(dg["wf"][valid], do["wf"][valid], rtol=wtol, atol=1e-6)
-    np.testing.assert_allclose(dg["phi"][valid], do["phi"][valid], rtol=0, atol=2e-7)
+    # phi = log2(m) from a float32 series with a hardware reciprocal: a few
+    # float32 ulps near 1 (it enters the colour linearly, far inside 1e-5)
+    np.testing.assert_allclose(dg["phi"][valid], do["phi"][valid], rtol=0, atol=4e-7)
 
 
 __all__ = ["Setup", "assert_rel", "assert_debug_equal", "t", "uniform_queries"]
