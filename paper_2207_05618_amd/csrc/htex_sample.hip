@@ -700,15 +700,16 @@ __global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
 // takes kBwdChunk consecutive queries (sorted queries meet few textures
 // there) and accumulates each tap into an on-chip tile holding one whole
 // (edge, level) of the gradient.  Tiles live in an arena of kArenaFloats
-// floats: the first tap of a new (edge, level) appends an entry to a table
-// of kTiles entries (tag, offset) and reserves the level's texels with an
-// atomic bump; later taps find the entry by a scan of the table.  Two lanes
-// may append the same (edge, level) at once; both tiles are flushed, so the
-// sums stay exact.  A level that no longer fits, or a full table, sends its
-// taps straight to global atomics.  At the end every tile is added to the
-// gradient pool once, one float atomic per non-zero texel channel.
-// Trilinear batches touch about 3 edges x 6 levels per block, which is why
-// tiles are sized per level rather than fixed.
+// floats, found through an open-addressing table of kTiles 64-bit entries
+// (key << 32 | arena offset) keyed by edge * 16 + level.  The first lane to
+// meet a key claims a free entry with a compare-and-swap (marking it
+// pending), reserves the level's texels with an atomic bump and publishes
+// the offset; lanes that meet the key while it is pending, or whose level
+// does not fit, or that find the table full, add their taps straight to
+// the gradient pool with global atomics.  A key is never claimed twice.
+// At the end every tile is added to the pool once, one float atomic per
+// non-zero texel channel.  Trilinear batches touch about 3 edges x 6
+// levels per block, which is why tiles are sized per level.
 constexpr int kTiles = 32;
 constexpr int kArenaFloats = 16384;   // 64 KB
 constexpr int kBwdPerThread = 16;
@@ -718,17 +719,16 @@ template <int CH, bool TRI>
 __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
 {
     __shared__ float arena[kArenaFloats];
-    // entry = (edge * 16 + level) << 32 | float offset in the arena, written
-    // and read as one 64-bit word; kFree / kDead mark unused entries
+    // entry = key << 32 | offset, read and written as one 64-bit word; the
+    // low word is an arena offset, kPending while its owner reserves space,
+    // or kNoRoom; kFree marks an unclaimed entry
     __shared__ uint64_t entry[kTiles];
-    __shared__ int32_t ntiles, used;
-    constexpr uint64_t kFree = ~0ull, kDead = ~1ull;
+    __shared__ int32_t used;
+    constexpr uint64_t kFree = ~0ull;
+    constexpr uint32_t kPending = 0xfffffffeu, kNoRoom = 0xfffffffdu;
     for (int i = threadIdx.x; i < kArenaFloats; i += kBlock) arena[i] = 0.0f;
     if (threadIdx.x < kTiles) entry[threadIdx.x] = kFree;
-    if (threadIdx.x == 0) {
-        ntiles = 0;
-        used = 0;
-    }
+    if (threadIdx.x == 0) used = 0;
     __syncthreads();
     const int64_t q0 = (int64_t)blockIdx.x * kBwdChunk;
     for (int r = 0; r < kBwdPerThread; ++r) {
@@ -776,24 +776,27 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
                 const int32_t key = es[s] * 16 + lv[sl];
                 const int32_t need = CH << (2 * m);
                 int32_t base_f = -1;
-                const int32_t nt = min(__atomic_load_n(&ntiles, __ATOMIC_RELAXED), kTiles);
-                for (int t = 0; t < nt; ++t) {
-                    const uint64_t en = __atomic_load_n(&entry[t], __ATOMIC_RELAXED);
-                    if (en < kDead && (int32_t)(en >> 32) == key) {
-                        base_f = (int32_t)(en & 0xffffffffu);
-                        break;
-                    }
-                }
-                if (base_f < 0 && need <= kArenaFloats) {
-                    const int32_t t = atomicAdd(&ntiles, 1);
-                    if (t < kTiles) {
-                        const int32_t o = atomicAdd(&used, need);
-                        if (o + need <= kArenaFloats) {
-                            atomicExch(&entry[t], ((uint64_t)(uint32_t)key << 32) | (uint32_t)o);
-                            base_f = o;
-                        } else {
-                            atomicExch(&entry[t], kDead);
+                const uint32_t h0 = ((uint32_t)key * 2654435761u) >> 27;   // 5 bits
+                for (int pr = 0; pr < kTiles; ++pr) {
+                    const int t = (int)((h0 + pr) & (kTiles - 1));
+                    uint64_t en = __atomic_load_n(&entry[t], __ATOMIC_RELAXED);
+                    if (en == kFree) {
+                        const uint64_t mine = ((uint64_t)(uint32_t)key << 32) | kPending;
+                        en = atomicCAS(&entry[t], kFree, mine);
+                        if (en == kFree) {   // claimed: reserve the level's texels
+                            const int32_t o = need <= kArenaFloats ? atomicAdd(&used, need)
+                                                                   : kArenaFloats;
+                            const bool fits = o + need <= kArenaFloats;
+                            atomicExch(&entry[t], ((uint64_t)(uint32_t)key << 32) |
+                                                      (fits ? (uint32_t)o : kNoRoom));
+                            if (fits) base_f = o;
+                            break;
                         }
+                    }
+                    if ((uint32_t)(en >> 32) == (uint32_t)key) {
+                        const uint32_t lo32 = (uint32_t)(en & 0xffffffffu);
+                        if (lo32 < (uint32_t)kArenaFloats) base_f = (int32_t)lo32;
+                        break;   // pending or no room: global atomics
                     }
                 }
                 const float w[4] = {p.wx0 * p.wy0, p.wx1 * p.wy0, p.wx0 * p.wy1, p.wx1 * p.wy1};
@@ -825,10 +828,9 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
     }
     __syncthreads();
     // flush the tiles
-    const int32_t nt = min(ntiles, kTiles);
-    for (int t = 0; t < nt; ++t) {
+    for (int t = 0; t < kTiles; ++t) {
         const uint64_t en = entry[t];
-        if (en >= kDead) continue;
+        if (en == kFree || (uint32_t)(en & 0xffffffffu) >= (uint32_t)kArenaFloats) continue;
         const int32_t key = (int32_t)(en >> 32);
         const int32_t e = key >> 4, l = key & 15;
         const int k = a.log2res[e];
