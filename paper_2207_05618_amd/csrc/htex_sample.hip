@@ -731,6 +731,12 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
     if (threadIdx.x == 0) used = 0;
     __syncthreads();
     const int64_t q0 = (int64_t)blockIdx.x * kBwdChunk;
+    // the last tile each of a lane's six (fetch, level) slots resolved: a
+    // lane's consecutive queries are usually on the same halfedge
+    int32_t memo_key[3][2], memo_base[3][2];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+        for (int sl = 0; sl < 2; ++sl) memo_key[s][sl] = -1;
     for (int r = 0; r < kBwdPerThread; ++r) {
         const int64_t q = q0 + (int64_t)r * kBlock + threadIdx.x;
         if (q >= a.Q) break;
@@ -767,17 +773,20 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
             float om[2];
             const int nlev = fetch_levels(L, ks[s], lv, om);
             const int64_t eb = a.base[es[s]];
-            for (int sl = 0; sl < nlev; ++sl) {
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl) {
+                if (sl >= nlev) break;
                 const LevelPlan p = plan_level(ks[s], lv[sl], om[sl], fs[s], flips[s]);
                 if (!p.act) continue;
                 const int m = ks[s] - lv[sl];
                 const uint32_t lo = level_offset32(ks[s], lv[sl]);
-                // the tile of this (edge, level): find it, or append it
+                // the tile of this (edge, level): remembered, found, or claimed
                 const int32_t key = es[s] * 16 + lv[sl];
                 const int32_t need = CH << (2 * m);
                 int32_t base_f = -1;
                 const uint32_t h0 = ((uint32_t)key * 2654435761u) >> 27;   // 5 bits
-                for (int pr = 0; pr < kTiles; ++pr) {
+                if (memo_key[s][sl] == key) base_f = memo_base[s][sl];
+                else for (int pr = 0; pr < kTiles; ++pr) {
                     const int t = (int)((h0 + pr) & (kTiles - 1));
                     uint64_t en = __atomic_load_n(&entry[t], __ATOMIC_RELAXED);
                     if (en == kFree) {
@@ -798,6 +807,10 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
                         if (lo32 < (uint32_t)kArenaFloats) base_f = (int32_t)lo32;
                         break;   // pending or no room: global atomics
                     }
+                }
+                if (base_f >= 0) {
+                    memo_key[s][sl] = key;
+                    memo_base[s][sl] = base_f;
                 }
                 const float w[4] = {p.wx0 * p.wy0, p.wx1 * p.wy0, p.wx0 * p.wy1, p.wx1 * p.wy1};
                 const uint32_t off[4] = {p.o00, p.o01, p.o10, p.o11};
