@@ -180,9 +180,17 @@ def cpu_baseline(mesh, log2res, base, pool_dev, batch, has_mips=True, want_s=10.
         oracle.sample(om, op, sl.h, sl.u, sl.v, sl.f, filter=filt, nthreads=cores)
         times.append(time.perf_counter() - t0)
     med = statistics.median(times)
+    # and on one core (a fifth of the sample)
+    q1 = sl.take(np.arange(Qs // 5))
+    one_times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.sample(om, op, q1.h, q1.u, q1.v, q1.f, filter=filt, nthreads=1)
+        one_times.append(time.perf_counter() - t0)
     return {"value": Qs / med, "unit": "samples/s", "cores": cores, "kind": "oracle",
             "sample": f"{Qs} consecutive queries of the sorted frame batch "
-                      f"({len(edges)} edges, FP64, median of {len(times)} runs)"}
+                      f"({len(edges)} edges, FP64, median of {len(times)} runs)",
+            "single_core_value": q1.Q / statistics.median(one_times)}
 
 
 # ------------------------------------------------------- differentiation --
@@ -759,12 +767,23 @@ def main():
     out = torch.empty((Q, 4), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
+    # device-to-device copy rate of 1 GiB (the practical HBM ceiling, and the
+    # calibration kernel of the committed counter summaries)
+    x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
     if args.copy_probe:
-        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
-        y.copy_(x)
+        copy_gbs = None
+    else:
+        ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ce0.record(stream)
+        for _ in range(5):
+            y.copy_(x)
+        ce1.record(stream)
         torch.cuda.synchronize()
-        del x, y
+        copy_gbs = 5 * 2 * x.numel() * 4 / (ce0.elapsed_time(ce1) / 1e3) / 1e9
+    del x, y
 
     def step(i, p=pool, bs=dev_batches):
         h, u, v, f = bs[i % len(bs)]
@@ -786,6 +805,7 @@ def main():
     elapsed = time.perf_counter() - t0
     kern_ms = [a.elapsed_time(b) for a, b in evs]
     avg_kernel_s = sum(kern_ms) / len(kern_ms) / 1e3
+    median_kernel_s = statistics.median(kern_ms) / 1e3
     value = args.steps * Q / elapsed
     log(f"{args.steps} steps in {elapsed * 1e3:.2f} ms; kernel avg {avg_kernel_s * 1e6:.1f} us")
 
@@ -802,6 +822,35 @@ def main():
     extra = {}
     if not args.no_extra:
         extra["unsorted_samples_per_s"] = rate(pool, [to_dev(unsorted)])
+        if args.workload == "frame4k":
+            # footprints over the whole mip range, log2 f ~ U[-8, 0]
+            from htexgen.queries import uniform_queries
+            stress = [to_dev(uniform_queries(mesh.H, Q, 205 + i, log2f=(-8.0, 0.0), sort=True))
+                      for i in range(2)]
+            extra["full_mip_range_samples_per_s"] = rate(pool, stress)
+            del stress
+            # one GPU's share of the frame on eight GPUs: a contiguous eighth
+            # of each sorted batch
+            share = [tuple(a[:Q // 8].contiguous() if a is not None else None for a in b)
+                     for b in dev_batches]
+            out8 = out[:Q // 8]
+
+            def share_step(i):
+                h, u, v, f = share[i % len(share)]
+                htex.htex_sample_prepared(prep, pool, h, u, v, f, filter=htex.HTEX_TRILINEAR,
+                                          flags=htex.HTEX_QUERIES_SORTED, out=out8)
+
+            for i in range(3):
+                share_step(i)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for i in range(20):
+                share_step(i)
+            torch.cuda.synchronize()
+            t_share = (time.perf_counter() - t1) / 20
+            extra["one_of_eight_share"] = {"queries": Q // 8, "us": t_share * 1e6,
+                                           "samples_per_s": (Q // 8) / t_share}
+            del share, out8
         # unsorted batch put in halfedge order first (sort, permute, sample,
         # results back to input order), timed as a whole
         hu, uu, vu, fu = to_dev(unsorted)
@@ -860,6 +909,17 @@ def main():
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                     "kernel": "htex::k_sample_prep<f32,trilinear>",
                     "avg_kernel_us": avg_kernel_s * 1e6,
+                    "median_kernel_us": median_kernel_s * 1e6,
+                    "copy_GBs": copy_gbs,
+                    # the other two readings of the roofline: counted DRAM
+                    # traffic (when the counters match this source) and
+                    # 64-byte-segment-granular unique bytes
+                    "dram_GBs": traffic / avg_kernel_s / 1e9 if traffic else None,
+                    "dram_frac": traffic / avg_kernel_s / 1e9 / HBM_PEAK_GBS if traffic else None,
+                    "dram_vs_copy": (traffic / avg_kernel_s / 1e9 / copy_gbs
+                                     if traffic and copy_gbs else None),
+                    "segment64_frac": alg["segment_bytes_per_query"] * Q / avg_kernel_s / 1e9
+                    / HBM_PEAK_GBS,
                     "alg_bytes_per_query": alg["bytes_per_query"],
                     "alg_texel_bytes_per_query": alg["texel_bytes_per_query"],
                     "segment64_bytes_per_query": alg["segment_bytes_per_query"],
