@@ -880,8 +880,9 @@ def main():
         del q8
         torch.cuda.empty_cache()
         for kk in list(extra):
-            extra[kk.replace("samples_per_s", "speedup_vs_f32")] = extra[kk] / value
-        log(f"extra {json.dumps({k: round(v, 3) for k, v in extra.items()})}")
+            if kk.endswith("samples_per_s"):
+                extra[kk.replace("samples_per_s", "speedup_vs_f32")] = extra[kk] / value
+        log(f"extra {json.dumps(extra)}")
         if args.workload == "frame4k":
             extra["rgb_plus_displacement"] = displacement_benchmark(
                 mesh, dmesh, step, Q, with_bytes=not args.no_bytes)
