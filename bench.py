@@ -912,13 +912,15 @@ def main():
                     "avg_kernel_us": avg_kernel_s * 1e6,
                     "median_kernel_us": median_kernel_s * 1e6,
                     "copy_GBs": copy_gbs,
-                    # the other two readings of the roofline: counted DRAM
-                    # traffic (when the counters match this source) and
-                    # 64-byte-segment-granular unique bytes
-                    "dram_GBs": traffic / avg_kernel_s / 1e9 if traffic else None,
-                    "dram_frac": traffic / avg_kernel_s / 1e9 / HBM_PEAK_GBS if traffic else None,
-                    "dram_vs_copy": (traffic / avg_kernel_s / 1e9 / copy_gbs
-                                     if traffic and copy_gbs else None),
+                    # the other two readings of the roofline: counted traffic
+                    # between the L2 and the memory fabric (HBM plus hits in
+                    # the fabric-side cache; when the counters match this
+                    # source) and 64-byte-segment-granular unique bytes
+                    "l2_fabric_GBs": traffic / avg_kernel_s / 1e9 if traffic else None,
+                    "l2_fabric_frac": (traffic / avg_kernel_s / 1e9 / HBM_PEAK_GBS
+                                       if traffic else None),
+                    "l2_fabric_vs_copy": (traffic / avg_kernel_s / 1e9 / copy_gbs
+                                          if traffic and copy_gbs else None),
                     "segment64_frac": alg["segment_bytes_per_query"] * Q / avg_kernel_s / 1e9
                     / HBM_PEAK_GBS,
                     "alg_bytes_per_query": alg["bytes_per_query"],
