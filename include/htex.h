@@ -170,12 +170,13 @@ htex_status htex_build_mips(const htex_pool *pool, void *texels_rw, void *stream
 /* Intrinsic triangle of every halfedge (Section 3.1, Alg. 1): out[h] =
  * (v0, v1, v2) as 9 floats, v0 = positions[Vert(Next h)], v2 =
  * positions[Vert(h)], v1 = the mean of the positions of the vertices of h's
- * face (found by following Next from h), summed in float64 from the face's
- * smallest halfedge and rounded once (every triangle of a face gets the
- * same v1 bit for bit).  Section 4.2's frame: the
- * query (h, u, v) is the point u v2 + v v0 + (1 - u - v) v1.  vert: device
- * int32 [H] (the Vert operator, not part of htex_mesh since sampling never
- * needs it); positions: device float32 [V][3]; out: device float32 [H][9].
+ * face (found by following Next from h), summed in float32 with every
+ * rounding error kept, from the face's smallest halfedge, and rounded once
+ * (every triangle of a face gets the same v1 bit for bit).  Section 4.2's
+ * frame: the query (h, u, v) is the point u v2 + v v0 + (1 - u - v) v1.
+ * vert: device int32 [H] (the Vert operator, not part of htex_mesh since
+ * sampling never needs it); positions: device float32 [V][3]; out: device
+ * float32 [H][9].
  * A face ring longer than 65536 halfedges, a walk leaving [0, H) or a
  * vertex id outside [0, V) gives a NaN row and increments *err_count
  * (device, nullable). */
@@ -198,7 +199,8 @@ htex_status htex_mip_backward(const htex_pool *pool, float *dtexels, int32_t cle
 /* Corner pre-processing (Section 4.4, "Corner Pre-processing"), in place on
  * a float32 pool: on every level of n >= 2 texels per side, the corner
  * texels that lie on one mesh vertex, or on one face centroid, all receive
- * the mean of their values (computed in float64, rounded once to float32);
+ * the mean of their values (float32 sums with every rounding error kept,
+ * rounded once);
  * levels of different edges are grouped by equal n.  With one resolution
  * everywhere, filtering is then continuous at vertices and face centroids
  * too (the seams are continuous already), which displacement needs to stay

@@ -25,9 +25,9 @@
 //
 // One lane per halfedge.  The lane of a face's smallest halfedge, of an
 // interior vertex's smallest outgoing halfedge, or of a boundary vertex's
-// chain start owns that group: it sums the group's corner texels in float64
-// (walk order, so the result is deterministic) and writes the mean, rounded
-// once to float32, to every one of them.  Groups are disjoint sets of
+// chain start owns that group: it sums the group's corner texels as float32
+// pairs with every rounding error kept (walk order, so the result is
+// deterministic) and writes the mean, rounded once, to every one of them.  Groups are disjoint sets of
 // texels, so owners never read what another owner writes.  Walks are
 // bounded: a ring longer than kMaxRing halfedges, or one that leaves
 // [0, H), is counted as an error and its group is left unchanged.
@@ -149,17 +149,17 @@ __device__ void average_group(const CornerArgs &a, int32_t g)
 {
     const int C = a.channels;
     for (int r = 1; r <= a.kmax; ++r) {
-        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        PairSum s[4];
         int32_t cnt = 0;
         ring<FACE>(a, g, [&](int32_t e, int c, bool) {
             const int64_t t = corner_texel(a, e, r, c);
             if (t < 0) return;
-            for (int ch = 0; ch < C; ++ch) s[ch] += (double)a.tex[C * t + ch];
+            for (int ch = 0; ch < C; ++ch) s[ch].add(a.tex[C * t + ch]);
             ++cnt;
         });
         if (cnt == 0) continue;
         float mean[4];
-        for (int ch = 0; ch < 4; ++ch) mean[ch] = (float)(s[ch] / (double)cnt);
+        for (int ch = 0; ch < 4; ++ch) mean[ch] = s[ch].mean(cnt);
         ring<FACE>(a, g, [&](int32_t e, int c, bool mirrored) {
             const int64_t t = corner_texel(a, e, r, c);
             if (t < 0) return;

@@ -5,9 +5,9 @@
 // and (0, 0, 1) at v1, so a query (h, u, v) is the surface point
 // u v2 + v v0 + (1 - u - v) v1.
 //
-// One lane per halfedge.  The centroid is summed in float64, starting at the
-// face's smallest halfedge, and rounded once, so every triangle of a face
-// gets the same v1 bit for bit.  The walk
+// One lane per halfedge.  The centroid is summed as float32 pairs with every
+// rounding error kept, starting at the face's smallest halfedge, and
+// rounded once, so every triangle of a face gets the same v1 bit for bit.  The walk
 // is bounded: a face ring longer than kMaxRing halfedges, a walk that leaves
 // [0, H) or a vertex id outside [0, V) makes the lane write NaN and count
 // an error.
@@ -54,18 +54,18 @@ __global__ void __launch_bounds__(kBlock) k_triangle_vertices(htex_mesh m, const
         if (err) atomicAdd(err, 1);
         return;
     }
-    double c[3] = {0.0, 0.0, 0.0};
+    PairSum c[3];
     g = first;
     do {
         const int64_t vg = vert[g];
-        c[0] += (double)pos[3 * vg + 0];
-        c[1] += (double)pos[3 * vg + 1];
-        c[2] += (double)pos[3 * vg + 2];
+        c[0].add(pos[3 * vg + 0]);
+        c[1].add(pos[3 * vg + 1]);
+        c[2].add(pos[3 * vg + 2]);
         g = m.next[g];
     } while (g != first);
     for (int d = 0; d < 3; ++d) {
         o[d] = pos[3 * (int64_t)v0 + d];
-        o[3 + d] = (float)(c[d] / (double)n);
+        o[3 + d] = c[d].mean(n);
         o[6 + d] = pos[3 * (int64_t)v2 + d];
     }
 }

@@ -41,6 +41,33 @@ __host__ __device__ inline int64_t level_offset(int k, int l)
     return ((int64_t(1) << (2 * k + 2)) - (int64_t(1) << (2 * (k - l) + 2))) / 3;
 }
 
+// A sum of float32 values kept as an unevaluated pair hi + lo: each
+// addition's rounding error is recovered exactly (Knuth's TwoSum) and
+// collected in lo, so a mean of a few values comes out correctly rounded
+// without leaving float32 arithmetic.
+struct PairSum {
+    float hi = 0.0f, lo = 0.0f;
+
+    __device__ __forceinline__ void add(float x)
+    {
+        const float s = hi + x;
+        const float bb = s - hi;
+        const float e = (hi - (s - bb)) + (x - bb);
+        hi = s;
+        lo += e;
+    }
+
+    // (hi + lo) / n: the remainder of the first quotient, hi - q0 n, is exact
+    // in one fused multiply-add, and is folded back with lo.
+    __device__ __forceinline__ float mean(int n) const
+    {
+        const float fn = (float)n;
+        const float q0 = hi / fn;
+        const float r = __builtin_fmaf(-q0, fn, hi) + lo;
+        return q0 + r / fn;
+    }
+};
+
 // Serving: a resident mesh (prepared records + pool) and a tile of one
 // request's queries.
 struct ServeMesh {
