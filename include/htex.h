@@ -373,7 +373,8 @@ typedef struct htex_server_config {
     int32_t grid_blocks;      /* blocks per launch; 0 = 4 per compute unit     */
     int32_t max_meshes;       /* resident meshes (> 0)                         */
     int32_t copy_streams;     /* host<->device copy streams per direction, 1..4 */
-    int32_t reserved;         /* 0                                             */
+    int32_t channels;         /* channels of every pool and result row: 1 or 4
+                                 (0 means 4)                                   */
 } htex_server_config;
 
 typedef struct htex_server_stats {
@@ -389,16 +390,16 @@ typedef struct htex_server_stats {
 htex_status htex_server_create(const htex_server_config *cfg, htex_server **out);
 
 /* Registers a resident mesh: its prepared records (htex_prepare, H records)
- * and its pool (dtype must match the server's; trilinear needs mips; RGBA
- * pools only).  The
+ * and its pool (dtype and channels must match the server's; trilinear needs
+ * mips).  The
  * device memory stays owned by the caller and must outlive the server.  Up
  * to max_meshes calls; *mesh_id receives 0, 1, ... */
 htex_status htex_server_add_mesh(htex_server *srv, int32_t H, const void *prep,
                                  const htex_pool *pool, int32_t *mesh_id);
 
 /* Queues a request of Q queries on mesh `mesh_id`: h, u, v (and footprint
- * for trilinear) are HOST arrays of Q entries, out a HOST array of Q x 4
- * floats; all must stay valid until the request completes (page-locked
+ * for trilinear) are HOST arrays of Q entries, out a HOST array of Q x C
+ * floats (C = the server's channels); all must stay valid until the request completes (page-locked
  * memory gives asynchronous copies).  Never blocks.  Returns HTEX_E_NOMEM
  * if the request alone exceeds the arena, HTEX_E_ARG for a bad mesh id or
  * pointer.  *request_id receives a number increasing from 0. */

@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(kBlock) k_sample_prep(SampleArgs a)
 // Serving: one launch covers a list of tiles, each up to kBlock queries of
 // one request on one resident mesh.  A fixed grid walks the list (block b
 // takes tiles b, b + G, ...), so every block exits once the list is done.
-template <int DT, bool TRI>
+template <int DT, int CH, bool TRI>
 __global__ void __launch_bounds__(kBlock) k_serve(const ServeMesh *meshes, const ServeTile *tiles,
                                                   int32_t ntiles, int32_t *err)
 {
@@ -492,7 +492,7 @@ __global__ void __launch_bounds__(kBlock) k_serve(const ServeMesh *meshes, const
             a.qf = T.f;
             a.out = T.out;
             a.err = err;
-            sample_one_prepared<DT, 4, TRI>(a, T.q0 + threadIdx.x);
+            sample_one_prepared<DT, CH, TRI>(a, T.q0 + threadIdx.x);
         }
     }
 }
@@ -909,18 +909,27 @@ template <int DT, int CH, bool TRI> struct FwdPrep {
 }  // namespace
 
 hipError_t launch_serve(const ServeMesh *meshes, const ServeTile *tiles, int32_t ntiles,
-                        int32_t grid, int dtype, int filter, int32_t *err, hipStream_t s)
+                        int32_t grid, int dtype, int channels, int filter, int32_t *err,
+                        hipStream_t s)
 {
     if (ntiles == 0) return hipSuccess;
     const uint32_t G = (uint32_t)(grid < ntiles ? grid : ntiles);
-    const bool tri = filter == HTEX_TRILINEAR;
-#define HTEX_SERVE(DTV, TRV) \
-    hipLaunchKernelGGL((k_serve<DTV, TRV>), dim3(G), dim3(kBlock), 0, s, meshes, tiles, ntiles, err)
-    switch (dtype) {
-    case HTEX_F32: if (tri) HTEX_SERVE(HTEX_F32, true); else HTEX_SERVE(HTEX_F32, false); break;
-    case HTEX_BF16: if (tri) HTEX_SERVE(HTEX_BF16, true); else HTEX_SERVE(HTEX_BF16, false); break;
-    default: if (tri) HTEX_SERVE(HTEX_FP8_E4M3, true); else HTEX_SERVE(HTEX_FP8_E4M3, false); break;
+    const bool tri = filter == HTEX_TRILINEAR, one = channels == 1;
+#define HTEX_SERVE(DTV, CHV, TRV)                                                          \
+    hipLaunchKernelGGL((k_serve<DTV, CHV, TRV>), dim3(G), dim3(kBlock), 0, s, meshes, tiles, \
+                       ntiles, err)
+#define HTEX_SERVE_DT(DTV)                                                                 \
+    if (one) {                                                                             \
+        if (tri) HTEX_SERVE(DTV, 1, true); else HTEX_SERVE(DTV, 1, false);                 \
+    } else {                                                                               \
+        if (tri) HTEX_SERVE(DTV, 4, true); else HTEX_SERVE(DTV, 4, false);                 \
     }
+    switch (dtype) {
+    case HTEX_F32: HTEX_SERVE_DT(HTEX_F32); break;
+    case HTEX_BF16: HTEX_SERVE_DT(HTEX_BF16); break;
+    default: HTEX_SERVE_DT(HTEX_FP8_E4M3); break;
+    }
+#undef HTEX_SERVE_DT
 #undef HTEX_SERVE
     return hipGetLastError();
 }

@@ -111,6 +111,7 @@ struct Batch {
 
 struct htex_server {
     htex_server_config cfg{};
+    int channels = 4;          // values per texel and per result row
     int device = 0;
     int grid = 0;
     int tiles_cap = 0;
@@ -161,7 +162,7 @@ hipError_t upload(htex_server *S, Request *r)
     r->du = reinterpret_cast<float *>(carve(4 * Q));
     r->dv = reinterpret_cast<float *>(carve(4 * Q));
     r->df = tri ? reinterpret_cast<float *>(carve(4 * Q)) : nullptr;
-    r->dout = reinterpret_cast<float *>(carve(16 * Q));
+    r->dout = reinterpret_cast<float *>(carve(4 * S->channels * Q));
     hipError_t e = hipMemcpyAsync(r->dh, r->h, 4 * Q, hipMemcpyHostToDevice, su);
     if (!e) e = hipMemcpyAsync(r->du, r->u, 4 * Q, hipMemcpyHostToDevice, su);
     if (!e) e = hipMemcpyAsync(r->dv, r->v, 4 * Q, hipMemcpyHostToDevice, su);
@@ -176,7 +177,7 @@ int64_t request_bytes(const htex_server *S, int64_t Q)
 {
     const int64_t a = (4 * Q + 255) / 256 * 256;
     const int64_t arrays = S->cfg.filter == HTEX_TRILINEAR ? 4 : 3;
-    return arrays * a + (16 * Q + 255) / 256 * 256;
+    return arrays * a + (4 * S->channels * Q + 255) / 256 * 256;
 }
 
 }  // namespace
@@ -249,14 +250,15 @@ bool htex_server::step()
         if (b.reqs.empty()) continue;
         hipError_t e = hipMemcpyAsync(b.tiles_dev, b.tiles_host, sizeof(htex::ServeTile) * ntiles,
                                       hipMemcpyHostToDevice, b.stream);
-        if (!e) e = htex::launch_serve(meshes_dev, b.tiles_dev, ntiles, grid, cfg.dtype, cfg.filter,
-                                       err_dev, b.stream);
+        if (!e) e = htex::launch_serve(meshes_dev, b.tiles_dev, ntiles, grid, cfg.dtype, channels,
+                                       cfg.filter, err_dev, b.stream);
         if (!e) e = hipEventRecord(b.ev_done, b.stream);
         for (hipStream_t sd : s_down)
             if (!e) e = hipStreamWaitEvent(sd, b.ev_done, 0);
         for (Request *r : b.reqs) {
             hipStream_t sd = s_down[down_rr++ % s_down.size()];
-            if (!e) e = hipMemcpyAsync(r->out, r->dout, 16 * r->Q, hipMemcpyDeviceToHost, sd);
+            if (!e) e = hipMemcpyAsync(r->out, r->dout, 4 * channels * r->Q, hipMemcpyDeviceToHost,
+                                       sd);
             if (!e) e = hipEventRecord(r->ev_down, sd);
             downloading.push_back(r);
         }
@@ -349,8 +351,11 @@ htex_status htex_server_create(const htex_server_config *cfg, htex_server **out)
         cfg->arena_bytes <= 0 || cfg->max_batch_queries <= 0 || cfg->max_meshes <= 0 ||
         cfg->grid_blocks < 0)
         return fail(HTEX_E_ARG, "bad server configuration");
+    if (cfg->channels != 0 && cfg->channels != 1 && cfg->channels != 4)
+        return fail(HTEX_E_ARG, "channels must be 0 (RGBA), 1 or 4");
     htex_server *S = new htex_server();
     S->cfg = *cfg;
+    S->channels = cfg->channels ? cfg->channels : 4;
     hipError_t e = hipGetDevice(&S->device);
     int cus = 0;
     if (!e) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device);
@@ -393,8 +398,8 @@ htex_status htex_server_add_mesh(htex_server *S, int32_t H, const void *prep, co
 {
     if (!S || !prep || !pool || !mesh_id || H <= 0) return fail(HTEX_E_ARG, "bad argument");
     if (pool->dtype != S->cfg.dtype) return fail(HTEX_E_ARG, "pool dtype differs from the server's");
-    if (pool->channels != 4)
-        return fail(HTEX_E_UNSUPPORTED, "the server serves RGBA (4-channel) pools");
+    if (pool->channels != S->channels)
+        return fail(HTEX_E_ARG, "pool has %d channels, the server %d", pool->channels, S->channels);
     if (S->cfg.filter == HTEX_TRILINEAR && !pool->has_mips)
         return fail(HTEX_E_ARG, "trilinear serving needs pools with mips");
     if (!pool->texels || (pool->dtype == HTEX_FP8_E4M3 && !pool->scale))

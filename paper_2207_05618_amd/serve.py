@@ -22,11 +22,12 @@ class Server:
     # 0.6-1.3 with more streams).
     def __init__(self, dtype, filter, arena_bytes=1 << 30, max_inflight=64,
                  compute_streams=1, max_batch_queries=1 << 22, grid_blocks=0,
-                 max_meshes=64, copy_streams=1):
+                 max_meshes=64, copy_streams=1, channels=4):
         cfg = _lib.htex_server_config(int(dtype), int(filter), int(max_inflight),
                                       int(compute_streams), int(arena_bytes),
                                       int(max_batch_queries), int(grid_blocks), int(max_meshes),
-                                      int(copy_streams), 0)
+                                      int(copy_streams), int(channels))
+        self.channels = int(channels)
         self._h = C.c_void_p()
         check(load().htex_server_create(C.byref(cfg), C.byref(self._h)))
         self.filter = filter
@@ -50,7 +51,7 @@ class Server:
         """h, u, v, f: page-locked CPU tensors; returns the request id."""
         Q = h.numel()
         if out is None:
-            out = torch.empty((Q, 4), dtype=torch.float32, pin_memory=True)
+            out = torch.empty((Q, self.channels), dtype=torch.float32, pin_memory=True)
         rid = C.c_int64()
         check(load().htex_server_submit(self._h, int(mesh_id), Q, h.data_ptr(), u.data_ptr(),
                                         v.data_ptr(), f.data_ptr() if f is not None else None,

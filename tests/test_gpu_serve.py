@@ -131,3 +131,35 @@ def test_server_rejects_mismatched_pool(meshes):
     with pytest.raises(htex.HtexError):
         srv.add_mesh(meshes[0][2], meshes[0][1])     # a BF16 pool
     srv.close()
+
+
+@pytest.mark.parametrize("dtype", [htex.HTEX_F32, htex.HTEX_BF16])
+def test_serving_one_channel_pools(dtype):
+    """A server of one-channel (displacement) pools: bilinear requests come
+    back as Q x 1 results equal to the same queries sampled alone; an RGBA
+    pool is refused."""
+    m = cube_mesh(n=3, seed=5, n_split=2, n_merge=1)
+    s = Setup(m, np.full(m.E, 5), has_mips=False, kind=1, seed=78, channels=1)
+    pool = s.pool if dtype == htex.HTEX_F32 else htex.htex_quantize(s.pool, dtype)
+    prep = htex.Prepared(s.dmesh, pool)
+    srv = Server(dtype, htex.HTEX_BILINEAR, arena_bytes=1 << 22, channels=1)
+    srv.add_mesh(prep, pool)
+    P = Server.pinned
+    rids, qs = [], []
+    for i in range(10):
+        q = uniform_queries(m.H, 3000 * (i + 1), 90 + i)
+        qs.append(q)
+        rids.append(srv.submit(0, P(q.h, torch.int32), P(q.u, torch.float32),
+                               P(q.v, torch.float32)))
+    srv.drain(60)
+    for rid, q in zip(rids, qs):
+        o = htex.htex_sample_prepared(prep, pool, t(q.h), t(q.u), t(q.v))
+        torch.cuda.synchronize()
+        got = srv.result(rid).numpy()
+        assert got.shape == (q.Q, 1)
+        np.testing.assert_array_equal(got, o.cpu().numpy())
+    rgba = Setup(m, np.full(m.E, 5), has_mips=False, kind=1, seed=79)
+    with pytest.raises(htex.HtexError):
+        srv.add_mesh(htex.Prepared(rgba.dmesh, rgba.pool) if dtype == htex.HTEX_F32 else prep,
+                     rgba.pool if dtype == htex.HTEX_F32 else htex.htex_quantize(rgba.pool, dtype))
+    srv.close()
