@@ -366,8 +366,11 @@ typedef struct htex_server_config {
     int32_t filter;           /* HTEX_BILINEAR or HTEX_TRILINEAR              */
     int32_t max_inflight;     /* request slots (admitted, not yet complete)    */
     int32_t compute_streams;  /* concurrent batch launches, 1..4 (HIP maps a
-                                 process's streams onto few hardware queues;
-                                 1 compute + 1 + 1 copy streams measured best) */
+                                 process's streams onto GPU_MAX_HW_QUEUES
+                                 hardware queues, 4 by default, and streams
+                                 sharing a queue serialize: 1 compute + 1 + 1
+                                 copy streams in a process run with 8 queues
+                                 measured best)                                */
     int64_t arena_bytes;      /* device bytes for request buffers (> 0)        */
     int64_t max_batch_queries;/* queries gathered into one launch (> 0)        */
     int32_t grid_blocks;      /* blocks per launch; 0 = 4 per compute unit     */
