@@ -782,7 +782,9 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
                 const uint32_t lo = level_offset32(ks[s], lv[sl]);
                 // the tile of this (edge, level): remembered, found, or claimed
                 const int32_t key = es[s] * 16 + lv[sl];
-                const int32_t need = CH << (2 * m);
+                // floats of this level's tile (computed in 64 bits: a level of
+                // 2^15 x 2^15 RGBA texels needs 2^32 floats; it never fits)
+                const int64_t need = (int64_t)CH << (2 * m);
                 int32_t base_f = -1;
                 const uint32_t h0 = ((uint32_t)key * 2654435761u) >> 27;   // 5 bits
                 if (memo_key[s][sl] == key) base_f = memo_base[s][sl];
@@ -793,8 +795,9 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
                         const uint64_t mine = ((uint64_t)(uint32_t)key << 32) | kPending;
                         en = atomicCAS(&entry[t], kFree, mine);
                         if (en == kFree) {   // claimed: reserve the level's texels
-                            const int32_t o = need <= kArenaFloats ? atomicAdd(&used, need)
-                                                                   : kArenaFloats;
+                            const int32_t o = need <= kArenaFloats
+                                                  ? atomicAdd(&used, (int32_t)need)
+                                                  : kArenaFloats;
                             const bool fits = o + need <= kArenaFloats;
                             atomicExch(&entry[t], ((uint64_t)(uint32_t)key << 32) |
                                                       (fits ? (uint32_t)o : kNoRoom));

@@ -485,3 +485,82 @@ def test_backward_sorted_flag_is_only_a_hint():
     ref, dabs = oracle.backward(s.omesh, s.opool, q.h, q.u, q.v, g, with_abs=True)
     err = np.abs(d.cpu().numpy().astype(np.float64) - ref)
     assert (err <= 1e-4 * dabs + 1e-12).all()
+
+
+def test_largest_resolution_k15():
+    """Two edges of 32768 x 32768 RGBA float32 texels (k = 15, the largest
+    the format allows: 17 GB each) among 4 x 4 ones, level 0 only, every
+    edge a constant colour.  Integer tap bases equal the exact rational
+    floor(x n - 1/2); the output equals the closed-form blend of the edge
+    constants by the traced per-fetch weights; the prepared path gives the
+    same bits; both backward paths conserve the upstream gradient per edge
+    (sum over an edge's texels = sum of dout times that edge's share of the
+    normalized weights)."""
+    from fractions import Fraction
+    m = cube_mesh(n=1, seed=1, n_split=0, n_merge=0)
+    lr = np.full(m.E, 2, np.uint8)
+    big = sorted({int(m.edge[0]), int(m.edge[m.next[0]])})
+    lr[big] = 15
+    pool = htex.Pool(lr, False)
+    const = 0.1 + 0.05 * np.arange(m.E)
+    for e in range(m.E):
+        b = int(pool.base_host[e])
+        pool.texels[b:b + 4 ** int(lr[e])] = torch.tensor(
+            (const[e] * np.array([1.0, 2.0, 3.0, 4.0])).astype(np.float32), device="cuda")
+    dm = htex.Mesh.of(m)
+    rng = np.random.default_rng(151)
+    Q = 40000
+    hs = np.array([0, m.next[0], m.prev[0], m.twin[0]], np.int32)
+    q = uniform_queries(m.H, Q, 152)
+    q.h = rng.choice(hs, Q).astype(np.int32)
+    # a few coordinates exactly on texel centres and edges of the big grid
+    k = rng.integers(0, 32768, 200)
+    q.u[:200] = ((k + rng.choice([0.0, 0.5], 200)) / 32768.0).astype(np.float32) * np.float32(0.5)
+    out, dbg = htex.htex_sample(dm, pool, t(q.h), t(q.u), t(q.v), debug=True)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    d = htex.debug_records(dbg)
+    # (1) tap bases against rationals
+    maps = lambda u, v: ((u, v), (v, -u), (-v, u))
+    for i in range(0, Q, 20):
+        u, v = Fraction(float(q.u[i])), Fraction(float(q.v[i]))
+        g = (int(q.h[i]), int(m.next[q.h[i]]), int(m.prev[q.h[i]]))
+        for s, (a, b) in enumerate(maps(u, v)):
+            x, y = (a, b) if g[s] > m.twin[g[s]] else (1 - a, 1 - b)
+            n = 1 << int(lr[m.edge[g[s]]])
+            xi = x * n - Fraction(1, 2)
+            yi = y * n - Fraction(1, 2)
+            if abs(xi) < 4 * n and abs(yi) < 4 * n:
+                assert d["i0"][i, s, 0] == (xi.numerator // xi.denominator), (i, s)
+                assert d["j0"][i, s, 0] == (yi.numerator // yi.denominator), (i, s)
+    # (2) the blend of constants
+    ce = const[d["edge"]]                                   # [Q, 3]
+    ref = (ce * d["wf"]).sum(1)[:, None] / d["W"][:, None] * np.array([1.0, 2.0, 3.0, 4.0])
+    assert_rel(got, ref, 2e-6)
+    np.testing.assert_allclose(d["wf"].sum(1), d["W"], rtol=1e-6)
+    # (3) prepared path
+    prep = htex.Prepared(dm, pool)
+    o2 = htex.htex_sample_prepared(prep, pool, t(q.h), t(q.u), t(q.v))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(o2.cpu().numpy(), got)
+    # (4) gradient conservation per edge, plain atomics and the LDS tiles
+    order = np.argsort(q.h, kind="stable")
+    g4 = rng.standard_normal((Q, 4)).astype(np.float32)
+    share = np.zeros((m.E, 4))
+    for s in range(3):
+        np.add.at(share, d["edge"][:, s],
+                  (d["wf"][:, s] / d["W"])[:, None].astype(np.float64) * g4)
+    dtex = torch.zeros_like(pool.texels)
+    for flags, idx in ((0, np.arange(Q)), (htex.HTEX_QUERIES_SORTED, order)):
+        dtex.zero_()
+        htex.htex_sample_backward(dm, pool, t(q.h[idx]), t(q.u[idx]), t(q.v[idx]),
+                                  t(g4[idx]), flags=flags, dtexels=dtex)
+        torch.cuda.synchronize()
+        for e in range(m.E):
+            b, cnt = int(pool.base_host[e]), 4 ** int(lr[e])
+            acc = torch.zeros(4, dtype=torch.float64, device="cuda")
+            for c0 in range(0, cnt, 1 << 26):
+                acc += dtex[b + c0:b + min(cnt, c0 + (1 << 26))].double().sum(0)
+            np.testing.assert_allclose(acc.cpu().numpy(), share[e], rtol=1e-4, atol=1e-3)
+    del dtex, pool
+    torch.cuda.empty_cache()
