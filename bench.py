@@ -729,11 +729,19 @@ def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9),
 
 # ------------------------------------------------------------- profiles --
 
+def kernel_source_sha256():
+    """Hash of the sources the frame kernel is built from (its file and the
+    device building blocks it includes)."""
+    h = hashlib.sha256()
+    for f in ("htex_sample.hip", "htex_filter.h"):
+        h.update(open(os.path.join(ROOT, "paper_2207_05618_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def recorded_traffic():
     """HBM traffic per launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
+    if it was taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "k_sample_prep_frame4k_pmc.md")
-    src = os.path.join(ROOT, "paper_2207_05618_amd", "csrc", "htex_sample.hip")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -741,8 +749,7 @@ def recorded_traffic():
     b = re.search(r"traffic_bytes_per_launch:\s*([0-9.e+]+)", txt)
     if not m or not b:
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    return float(b.group(1)) if sha == m.group(1) else None
+    return float(b.group(1)) if kernel_source_sha256() == m.group(1) else None
 
 
 # ----------------------------------------------------------------- main --
