@@ -231,3 +231,30 @@ def test_mixed_resolutions_may_crack():
     M, P, C = _setup(m, k=4, mixed=True)
     key, after = _vertex_and_centroid_samples(m, M, C, oracle.BILINEAR, None)
     assert _spread(key, after) > 1e-6
+
+
+@pytest.mark.parametrize("mesh_i", [0, 3, 4])
+def test_corner_averaging_is_an_orthogonal_projection(mesh_i):
+    """Averaging over disjoint groups (plus copying the mirrored corner) is
+    linear; on the texels it treats as free it is symmetric and idempotent,
+    so its transpose is itself: a gradient passes through the
+    pre-processing by applying the same averaging to it.  Checked with the
+    adjoint identity on random pools (mirror copies excluded, as they are
+    not free parameters)."""
+    m = _meshes()[mesh_i]
+    M, P, _ = _setup(m, k=3)
+    rows = _corner_points(m, P)
+    mirror = np.zeros(len(P.texels), bool)
+    mirror[[r[0] for r in rows if r[3]]] = True
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(P.texels.shape)
+    y = rng.standard_normal(P.texels.shape)
+    x[mirror] = 0.0
+    y[mirror] = 0.0
+    Px = oracle.corner_average(M, oracle.Pool(P.log2res, P.base, x, True), m.vert, m.face, m.V, m.F)
+    Py = oracle.corner_average(M, oracle.Pool(P.log2res, P.base, y, True), m.vert, m.face, m.V, m.F)
+    Px[mirror] = 0.0
+    Py[mirror] = 0.0
+    lhs = float((Px * y).sum())
+    rhs = float((x * Py).sum())
+    assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(lhs))
