@@ -588,7 +588,8 @@ def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9),
     """Serving form: 16 resident meshes (5k-500k faces, log-uniform) with
     BF16 textures + mips sized to about 200 GB, Poisson streams of requests
     of 4k-2M queries (log-uniform, frame-like, sorted by halfedge) to random
-    meshes at 0.3 / 0.6 / 0.9 of the measured saturation throughput."""
+    meshes at 0.3 / 0.6 / 0.9 of the measured capacity (the smaller of a burst's
+    rate and the rate sustained under overload)."""
     import numpy as np
     import torch
 
@@ -682,19 +683,12 @@ def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9),
     for rid, _ in srv.poll(1 << 16):
         srv.release(rid)
     same = all(np.array_equal(payloads[j][6].numpy(), alone[j].numpy()) for j in range(16))
-    log(f"serve: saturation {sat_rate:.3e} samples/s; sequential {seq_rate:.3e}; "
+    log(f"serve: burst {sat_rate:.3e} samples/s; sequential {seq_rate:.3e}; "
         f"mix==alone {same}")
 
-    out = {"resident_bytes": pool_bytes, "meshes": 16,
-           "faces": int(sum(m[5] for m in meshes)), "edges": int(sum(m[4] for m in meshes)),
-           "log2res": [int(k) for k in ks], "mean_queries_per_request": mean_q,
-           "saturation_samples_per_s": sat_rate, "sequential_samples_per_s": seq_rate,
-           "sequential_p50_ms": float(np.percentile(seq_lat, 50) * 1e3),
-           "speedup_vs_sequential": sat_rate / seq_rate, "results_mix_equal_alone": bool(same),
-           "rates": []}
-    lam_sat = sat_rate / mean_q
-    for frac in rates:
-        lam = frac * lam_sat
+    def poisson(lam):
+        """Poisson arrivals at lam requests/s for run_s seconds; returns the
+        achieved samples/s (until the last result) and the latencies."""
         arr = np.cumsum(rng.exponential(1.0 / lam, size=int(lam * run_s) + 1))
         arr = arr[arr < run_s]
         picks = rng.integers(0, 48, size=len(arr))
@@ -711,12 +705,33 @@ def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9),
         lat = np.array([l for _, l in done])
         for rid, _ in done:
             srv.release(rid)
-        rec = {"load": frac, "requests": int(len(arr)), "offered_req_per_s": lam,
-               "achieved_samples_per_s": nq / wall,
+        return nq / wall, lat, len(arr)
+
+    # sustained capacity: arrivals offered 25% above the burst rate keep the
+    # server busy for the whole run; a burst of queued requests batches more
+    # than a stream of arrivals does, so the loads below are set against the
+    # smaller of the two
+    sustained, _, _ = poisson(1.25 * sat_rate / mean_q)
+    capacity = min(sat_rate, sustained)
+    log(f"serve: sustained {sustained:.3e} samples/s under overload; capacity {capacity:.3e}")
+    out = {"resident_bytes": pool_bytes, "meshes": 16,
+           "faces": int(sum(m[5] for m in meshes)), "edges": int(sum(m[4] for m in meshes)),
+           "log2res": [int(k) for k in ks], "mean_queries_per_request": mean_q,
+           "saturation_samples_per_s": capacity, "burst_samples_per_s": sat_rate,
+           "sustained_samples_per_s": sustained, "sequential_samples_per_s": seq_rate,
+           "sequential_p50_ms": float(np.percentile(seq_lat, 50) * 1e3),
+           "speedup_vs_sequential": capacity / seq_rate, "results_mix_equal_alone": bool(same),
+           "rates": []}
+    lam_sat = capacity / mean_q
+    for frac in rates:
+        lam = frac * lam_sat
+        achieved, lat, nreq = poisson(lam)
+        rec = {"load": frac, "requests": int(nreq), "offered_req_per_s": lam,
+               "achieved_samples_per_s": achieved,
                "p50_ms": float(np.percentile(lat, 50) * 1e3),
                "p99_ms": float(np.percentile(lat, 99) * 1e3)}
         out["rates"].append(rec)
-        log(f"serve: load {frac}: {len(arr)} requests, p50 {rec['p50_ms']:.2f} ms, "
+        log(f"serve: load {frac}: {nreq} requests, p50 {rec['p50_ms']:.2f} ms, "
             f"p99 {rec['p99_ms']:.2f} ms, {rec['achieved_samples_per_s']:.3e} samples/s")
     st = srv.stats()
     srv.close()
