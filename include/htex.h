@@ -302,7 +302,11 @@ htex_status htex_prepare(const htex_mesh *mesh, const htex_pool *pool, void *pre
 /* Same result as htex_sample (bit for bit) from prepared descriptors: the
  * fast path for repeated sampling of one mesh.  `H` is the number of
  * halfedges the records cover (queries with h outside [0, H) are invalid as
- * in htex_sample).  No debug trace. */
+ * in htex_sample).  No debug trace.  The HTEX_QUERIES_SORTED hint picks the
+ * kernel: for halfedge-ordered batches every tap of a sampled level is read
+ * (neighbouring queries share the cache lines); without it only in-bounds
+ * taps are read, which saves line fetches when queries are scattered.  Both
+ * give the same results. */
 htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *pool,
                                  const htex_queries *queries, int32_t filter,
                                  uint32_t flags, float *out, int32_t *err_count,

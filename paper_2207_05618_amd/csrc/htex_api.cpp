@@ -432,6 +432,7 @@ htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *p
     a.err = err_count;
     a.prep = prep;
     return from_hip(htex::launch_sample_prepared(a, pool->dtype, filter,
+                                                 (flags & HTEX_QUERIES_SORTED) != 0,
                                                  static_cast<hipStream_t>(stream)),
                     "prepared sample launch");
 }

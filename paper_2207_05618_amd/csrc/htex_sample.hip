@@ -79,7 +79,9 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a)
 // one prepared record per query (bit-identical results).  Shared by the
 // batch kernel and the serving kernel, so a query's result does not depend
 // on which launch, batch or tile computes it.
-template <int DT, int CH, bool TRI>
+// SCATTERED selects the per-tap predicated fetch for batches that are not
+// ordered by halfedge (same results).
+template <int DT, int CH, bool TRI, bool SCATTERED>
 __device__ __forceinline__ void sample_one_prepared(const SampleArgs &a, int64_t q)
 {
     const int32_t h = __builtin_nontemporal_load(a.qh + q);
@@ -102,8 +104,9 @@ __device__ __forceinline__ void sample_one_prepared(const SampleArgs &a, int64_t
     for (int s = 0; s < 3; ++s) {
         float4 Cf = make_float4(0.f, 0.f, 0.f, 0.f);
         float Wf = 0.0f;
-        fetch<DT, CH, TRI, false>(a, L, fs[s], resolve_prepared<DT, CH>(a, rec.w[s], rec.e[s]),
-                                  Cf, Wf, nullptr, s);
+        const Resolved R = resolve_prepared<DT, CH>(a, rec.w[s], rec.e[s]);
+        if constexpr (SCATTERED) fetch_in_bounds<DT, CH, TRI>(a, L, fs[s], R, Cf, Wf);
+        else fetch<DT, CH, TRI, false>(a, L, fs[s], R, Cf, Wf, nullptr, s);
         C.x += Cf.x;
         C.y += Cf.y;
         C.z += Cf.z;
@@ -114,12 +117,12 @@ __device__ __forceinline__ void sample_one_prepared(const SampleArgs &a, int64_t
     store_row<CH>(a.out, q, C.x * r, C.y * r, C.z * r, C.w * r);
 }
 
-template <int DT, int CH, bool TRI>
+template <int DT, int CH, bool TRI, bool SCATTERED>
 __global__ void __launch_bounds__(kBlock) k_sample_prep(SampleArgs a)
 {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q >= a.Q) return;
-    sample_one_prepared<DT, CH, TRI>(a, q);
+    sample_one_prepared<DT, CH, TRI, SCATTERED>(a, q);
 }
 
 // Serving: one launch covers a list of tiles, each up to kBlock queries of
@@ -145,7 +148,7 @@ __global__ void __launch_bounds__(kBlock) k_serve(const ServeMesh *meshes, const
             a.qf = T.f;
             a.out = T.out;
             a.err = err;
-            sample_one_prepared<DT, CH, TRI>(a, T.q0 + threadIdx.x);
+            sample_one_prepared<DT, CH, TRI, false>(a, T.q0 + threadIdx.x);
         }
     }
 }
@@ -183,11 +186,11 @@ hipError_t launch_fwd(const SampleArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int DT, int CH, bool TRI>
+template <int DT, int CH, bool TRI, bool SCATTERED>
 hipError_t launch_fwd_prep(const SampleArgs &a, hipStream_t s)
 {
     const uint32_t G = (uint32_t)ceil_div(a.Q, kBlock);
-    hipLaunchKernelGGL((k_sample_prep<DT, CH, TRI>), dim3(G), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_sample_prep<DT, CH, TRI, SCATTERED>), dim3(G), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
@@ -215,7 +218,13 @@ template <int DT, int CH, bool TRI> struct Fwd {
 template <int DT, int CH, bool TRI> struct FwdPrep {
     static hipError_t run(const SampleArgs &a, hipStream_t s)
     {
-        return launch_fwd_prep<DT, CH, TRI>(a, s);
+        return launch_fwd_prep<DT, CH, TRI, false>(a, s);
+    }
+};
+template <int DT, int CH, bool TRI> struct FwdPrepScattered {
+    static hipError_t run(const SampleArgs &a, hipStream_t s)
+    {
+        return launch_fwd_prep<DT, CH, TRI, true>(a, s);
     }
 };
 
@@ -255,10 +264,12 @@ hipError_t launch_prepare(const SampleArgs &a, void *prep, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, hipStream_t s)
+hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, bool sorted,
+                                  hipStream_t s)
 {
     if (a.Q == 0) return hipSuccess;
-    return dispatch<FwdPrep>(a, dtype, filter, s);
+    return sorted ? dispatch<FwdPrep>(a, dtype, filter, s)
+                  : dispatch<FwdPrepScattered>(a, dtype, filter, s);
 }
 
 hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t s)

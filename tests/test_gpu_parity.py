@@ -419,11 +419,13 @@ def test_mesh_validate_on_gpu():
 
 @pytest.mark.parametrize("mesh_i", [0, 1, 2, 3])
 @pytest.mark.parametrize("dtype", [htex.HTEX_F32, htex.HTEX_BF16, htex.HTEX_FP8_E4M3])
-def test_prepared_path_is_bit_identical(mesh_i, dtype):
+@pytest.mark.parametrize("flags", [0, htex.HTEX_QUERIES_SORTED])
+def test_prepared_path_is_bit_identical(mesh_i, dtype, flags):
     """htex_sample_prepared reads the navigation from per-halfedge records;
     its results must equal htex_sample's bit for bit (and so the oracle's to
     the same tolerance), for every storage type and filter, including
-    invalid queries."""
+    invalid queries, with either kernel the sorted hint selects (all taps
+    of a level read, or in-bounds taps only)."""
     m = tiny_meshes()[mesh_i]
     rng = np.random.default_rng(70 + mesh_i)
     s = Setup(m, rng.integers(0, 7, m.E), has_mips=True, kind=1)
@@ -437,7 +439,7 @@ def test_prepared_path_is_bit_identical(mesh_i, dtype):
         a, _ = s.gpu(q, filt, pool=pool)
         err = torch.zeros(1, dtype=torch.int32, device="cuda")
         b = htex.htex_sample_prepared(prep, pool, t(q.h), t(q.u), t(q.v), t(q.f), filter=filt,
-                                      err_count=err)
+                                      flags=flags, err_count=err)
         torch.cuda.synchronize()
         np.testing.assert_array_equal(b.cpu().numpy(), a)
         assert int(err.item()) == 4
