@@ -8,8 +8,9 @@ texture per edge with its full mip chain (34.8 GB resident in HBM), texels
 from seeded smooth lattice noise; 3840 x 2160 = 8,294,400 queries per step
 (uniform halfedge, uniform barycentric point, log2 footprint ~ U[-3.2, -1.2])
 sorted by halfedge, trilinear filtering.  A step is one htex_sample call over
-one frame batch; four distinct seeded batches rotate so consecutive steps do
-not replay the same addresses.  All inputs are resident in HBM before the
+one frame batch; eight distinct seeded batches rotate, so each batch comes
+back only after seven others have streamed several GB of texel lines through
+the caches.  All inputs are resident in HBM before the
 timed region.
 
 Printed: one JSON line with samples/s, the roofline of the sampling kernel
@@ -74,11 +75,11 @@ def build_workload(name):
     if name == "frame4k":
         mesh = sphere_mesh(n=183, seed=201)
         k, Q, log2f, kind, tex_seed = 6, 3840 * 2160, (-3.2, -1.2), 1, 202
-        qseeds = [203, 213, 223, 233]
+        qseeds = [203 + 10 * i for i in range(8)]
     else:
         mesh = cube_mesh()
         k, Q, log2f, kind, tex_seed = 4, 65536, (-6.0, 0.0), 0, 102
-        qseeds = [103, 113, 123, 133]
+        qseeds = [103 + 10 * i for i in range(8)]
     batches = [uniform_queries(mesh.H, Q, s, log2f=log2f, sort=True) for s in qseeds]
     unsorted = uniform_queries(mesh.H, Q, qseeds[0], log2f=log2f, sort=False,
                                shuffle_seed=204)
