@@ -858,9 +858,10 @@ def main():
 
     extra = {}
     if not args.no_extra:
-        # the unsorted batch without the sorted hint: the kernel that reads
+        # the unsorted batch with the scattered hint: the kernel that reads
         # in-bounds taps only
-        extra["unsorted_samples_per_s"] = rate(pool, [to_dev(unsorted)], flags=0)
+        extra["unsorted_samples_per_s"] = rate(pool, [to_dev(unsorted)],
+                                               flags=htex.HTEX_QUERIES_SCATTERED)
         if args.workload == "frame4k":
             # footprints over the whole mip range, log2 f ~ U[-8, 0]
             from htexgen.queries import uniform_queries

@@ -75,7 +75,10 @@ typedef int32_t htex_status;
 #define HTEX_BILINEAR 0
 #define HTEX_TRILINEAR 1
 /* flags */
-#define HTEX_QUERIES_SORTED (1u << 0) /* hint: queries arrive ordered by h    */
+#define HTEX_QUERIES_SORTED (1u << 0)    /* hint: queries arrive ordered by h */
+#define HTEX_QUERIES_SCATTERED (1u << 1) /* hint: neighbouring queries share  */
+                                         /* no texels (random order); not    */
+                                         /* together with _SORTED            */
 
 /* Halfedge arrays (Section 2, Fig. 2), device, int32 [H] each.  Twin(h) = -1
  * marks a boundary halfedge; Edge(h) in [0, E) names h's quad and texture.
@@ -302,10 +305,11 @@ htex_status htex_prepare(const htex_mesh *mesh, const htex_pool *pool, void *pre
 /* Same result as htex_sample (bit for bit) from prepared descriptors: the
  * fast path for repeated sampling of one mesh.  `H` is the number of
  * halfedges the records cover (queries with h outside [0, H) are invalid as
- * in htex_sample).  No debug trace.  The HTEX_QUERIES_SORTED hint picks the
- * kernel: for halfedge-ordered batches every tap of a sampled level is read
- * (neighbouring queries share the cache lines); without it only in-bounds
- * taps are read, which saves line fetches when queries are scattered.  Both
+ * in htex_sample).  No debug trace.  The HTEX_QUERIES_SCATTERED hint picks
+ * the kernel: by default every tap of a sampled level is read, which suits
+ * coherent batches (ordered by halfedge, or rasterized, where neighbouring
+ * queries share the cache lines); with the hint only in-bounds taps are
+ * read, which saves line fetches when no two queries share texels.  Both
  * give the same results. */
 htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *pool,
                                  const htex_queries *queries, int32_t filter,

@@ -15,7 +15,8 @@ import torch
 
 from . import _lib
 from ._lib import (DEBUG_FIELDS, HTEX_BF16, HTEX_BILINEAR, HTEX_F32, HTEX_FP8_E4M3,  # noqa: F401
-                   HTEX_QUERIES_SORTED, HTEX_TRILINEAR, HtexError, check, load)
+                   HTEX_QUERIES_SCATTERED, HTEX_QUERIES_SORTED, HTEX_TRILINEAR, HtexError,
+                   check, load)
 
 __all__ = ["Mesh", "Pool", "htex_pool_layout", "htex_mesh_validate", "htex_build_mips",
            "htex_corner_average", "htex_mip_backward", "htex_triangle_vertices",

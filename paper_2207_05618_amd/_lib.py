@@ -22,6 +22,7 @@ STATUS = {0: "HTEX_OK", -1: "HTEX_E_ARG", -2: "HTEX_E_TOPOLOGY", -3: "HTEX_E_RAN
 HTEX_F32, HTEX_BF16, HTEX_FP8_E4M3 = 0, 1, 2
 HTEX_BILINEAR, HTEX_TRILINEAR = 0, 1
 HTEX_QUERIES_SORTED = 1
+HTEX_QUERIES_SCATTERED = 2
 
 
 class htex_mesh(C.Structure):

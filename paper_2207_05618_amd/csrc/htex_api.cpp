@@ -61,6 +61,15 @@ size_t texel_bytes(int32_t dtype, int32_t channels)
     }
 }
 
+htex_status check_flags(uint32_t flags)
+{
+    if (flags & ~(HTEX_QUERIES_SORTED | HTEX_QUERIES_SCATTERED))
+        return fail(HTEX_E_ARG, "unknown flags 0x%x", flags);
+    if ((flags & HTEX_QUERIES_SORTED) && (flags & HTEX_QUERIES_SCATTERED))
+        return fail(HTEX_E_ARG, "HTEX_QUERIES_SORTED and HTEX_QUERIES_SCATTERED contradict");
+    return HTEX_OK;
+}
+
 htex_status check_mesh(const htex_mesh *m)
 {
     if (!m) return fail(HTEX_E_ARG, "mesh is NULL");
@@ -298,7 +307,7 @@ htex_status htex_sample(const htex_mesh *mesh, const htex_pool *pool, const htex
     if (!st) st = check_pool(pool, mesh);
     if (!st) st = check_queries(queries, filter);
     if (st) return st;
-    if (flags & ~HTEX_QUERIES_SORTED) return fail(HTEX_E_ARG, "unknown flags 0x%x", flags);
+    if (const htex_status fs = check_flags(flags)) return fs;
     if (filter == HTEX_TRILINEAR && !pool->has_mips)
         return fail(HTEX_E_ARG, "trilinear filtering needs a pool with mips");
     const size_t row = 4 * (size_t)pool->channels;   // bytes of one result row
@@ -322,7 +331,7 @@ htex_status htex_sample_backward(const htex_mesh *mesh, const htex_pool *pool,
     if (!st) st = check_pool(pool, mesh);
     if (!st) st = check_queries(queries, filter);
     if (st) return st;
-    if (flags & ~HTEX_QUERIES_SORTED) return fail(HTEX_E_ARG, "unknown flags 0x%x", flags);
+    if (const htex_status fs = check_flags(flags)) return fs;
     if (pool->dtype != HTEX_F32) return fail(HTEX_E_UNSUPPORTED, "gradients need a float32 pool");
     if (filter == HTEX_TRILINEAR && !pool->has_mips)
         return fail(HTEX_E_ARG, "trilinear filtering needs a pool with mips");
@@ -409,7 +418,7 @@ htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *p
     if (!st) st = check_queries(queries, filter);
     if (st) return st;
     if (H < 0) return fail(HTEX_E_ARG, "negative H");
-    if (flags & ~HTEX_QUERIES_SORTED) return fail(HTEX_E_ARG, "unknown flags 0x%x", flags);
+    if (const htex_status fs = check_flags(flags)) return fs;
     if (filter == HTEX_TRILINEAR && !pool->has_mips)
         return fail(HTEX_E_ARG, "trilinear filtering needs a pool with mips");
     if (queries->Q > 0) {
@@ -432,7 +441,7 @@ htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *p
     a.err = err_count;
     a.prep = prep;
     return from_hip(htex::launch_sample_prepared(a, pool->dtype, filter,
-                                                 (flags & HTEX_QUERIES_SORTED) != 0,
+                                                 (flags & HTEX_QUERIES_SCATTERED) != 0,
                                                  static_cast<hipStream_t>(stream)),
                     "prepared sample launch");
 }
@@ -444,7 +453,7 @@ htex_status check_aniso(const htex_pool *pool, const htex_queries *q, const floa
 {
     htex_status st = check_queries(q, HTEX_BILINEAR);
     if (st) return st;
-    if (flags & ~HTEX_QUERIES_SORTED) return fail(HTEX_E_ARG, "unknown flags 0x%x", flags);
+    if (const htex_status fs = check_flags(flags)) return fs;
     if (!pool->has_mips) return fail(HTEX_E_ARG, "anisotropic filtering needs a pool with mips");
     if (max_aniso < 1 || max_aniso > HTEX_MAX_ANISO)
         return fail(HTEX_E_ARG, "max_aniso %d outside [1, %d]", max_aniso, HTEX_MAX_ANISO);

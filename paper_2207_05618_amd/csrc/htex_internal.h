@@ -102,7 +102,7 @@ hipError_t launch_serve(const ServeMesh *meshes, const ServeTile *tiles, int32_t
                         hipStream_t s);
 hipError_t launch_backward(const SampleArgs &a, int filter, uint32_t flags, hipStream_t s);
 hipError_t launch_prepare(const SampleArgs &a, void *prep, hipStream_t s);
-hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, bool sorted,
+hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, bool scattered,
                                   hipStream_t s);
 hipError_t launch_sample_aniso(const SampleArgs &a, int dtype, const float *jac, int max_aniso,
                                int32_t *nprobe, hipStream_t s);

@@ -79,8 +79,8 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a)
 // one prepared record per query (bit-identical results).  Shared by the
 // batch kernel and the serving kernel, so a query's result does not depend
 // on which launch, batch or tile computes it.
-// SCATTERED selects the per-tap predicated fetch for batches that are not
-// ordered by halfedge (same results).
+// SCATTERED selects the per-tap predicated fetch for batches in random
+// order (same results).
 template <int DT, int CH, bool TRI, bool SCATTERED>
 __device__ __forceinline__ void sample_one_prepared(const SampleArgs &a, int64_t q)
 {
@@ -264,12 +264,12 @@ hipError_t launch_prepare(const SampleArgs &a, void *prep, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, bool sorted,
+hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, bool scattered,
                                   hipStream_t s)
 {
     if (a.Q == 0) return hipSuccess;
-    return sorted ? dispatch<FwdPrep>(a, dtype, filter, s)
-                  : dispatch<FwdPrepScattered>(a, dtype, filter, s);
+    return scattered ? dispatch<FwdPrepScattered>(a, dtype, filter, s)
+                     : dispatch<FwdPrep>(a, dtype, filter, s);
 }
 
 hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t s)

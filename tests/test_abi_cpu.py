@@ -80,7 +80,7 @@ def _q(Q=1, f=None):
     ("fp8_no_scale", -1), ("bad_filter", -1), ("tri_no_footprint", -1), ("tri_no_mips", -1),
     ("neg_Q", -1), ("misaligned_out", -1), ("bad_flags", -1), ("big_k", -3),
     ("bad_channels", -1), ("reserved_set", -1), ("one_channel_misaligned_out", -1),
-    ("one_channel_misaligned_texels", -1),
+    ("one_channel_misaligned_texels", -1), ("contradictory_hints", -1),
 ])
 def test_sample_rejects_bad_arguments_without_launching(case, status):
     L = _lib.load()
@@ -108,6 +108,8 @@ def test_sample_rejects_bad_arguments_without_launching(case, status):
         out = 20
     elif case == "bad_flags":
         flags = 1 << 7
+    elif case == "contradictory_hints":
+        flags = _lib.HTEX_QUERIES_SORTED | _lib.HTEX_QUERIES_SCATTERED
     elif case == "big_k":
         pool = _pool(maxk=16)
     elif case == "bad_channels":

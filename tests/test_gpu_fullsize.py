@@ -102,8 +102,7 @@ def test_frame_unsorted_equals_sorted(frame):
 
 def test_frame_prepared_equals_plain(frame):
     """The prepared fast path (what the benchmark times) gives the plain
-    path's bits on the whole frame, with either kernel the sorted hint
-    selects."""
+    path's bits on the whole frame, with either kernel the hints select."""
     mesh, lr, pool, dm, q, out = frame
     prep = htex.Prepared(dm, pool)
     o2 = htex.htex_sample_prepared(prep, pool, t(q.h), t(q.u), t(q.v), t(q.f),
@@ -115,7 +114,8 @@ def test_frame_prepared_equals_plain(frame):
     perm = np.random.default_rng(205).permutation(q.Q)
     qu = q.take(perm)
     o3 = htex.htex_sample_prepared(prep, pool, t(qu.h), t(qu.u), t(qu.v), t(qu.f),
-                                   filter=htex.HTEX_TRILINEAR, flags=0)
+                                   filter=htex.HTEX_TRILINEAR,
+                                   flags=htex.HTEX_QUERIES_SCATTERED)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(o3.cpu().numpy(), out[perm])
 

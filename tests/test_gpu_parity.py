@@ -419,13 +419,13 @@ def test_mesh_validate_on_gpu():
 
 @pytest.mark.parametrize("mesh_i", [0, 1, 2, 3])
 @pytest.mark.parametrize("dtype", [htex.HTEX_F32, htex.HTEX_BF16, htex.HTEX_FP8_E4M3])
-@pytest.mark.parametrize("flags", [0, htex.HTEX_QUERIES_SORTED])
+@pytest.mark.parametrize("flags", [0, htex.HTEX_QUERIES_SORTED, htex.HTEX_QUERIES_SCATTERED])
 def test_prepared_path_is_bit_identical(mesh_i, dtype, flags):
     """htex_sample_prepared reads the navigation from per-halfedge records;
     its results must equal htex_sample's bit for bit (and so the oracle's to
     the same tolerance), for every storage type and filter, including
-    invalid queries, with either kernel the sorted hint selects (all taps
-    of a level read, or in-bounds taps only)."""
+    invalid queries, with either kernel the hints select (all taps of a
+    level read, or in-bounds taps only for scattered batches)."""
     m = tiny_meshes()[mesh_i]
     rng = np.random.default_rng(70 + mesh_i)
     s = Setup(m, rng.integers(0, 7, m.E), has_mips=True, kind=1)
