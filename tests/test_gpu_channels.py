@@ -45,9 +45,11 @@ def test_one_channel_sampling_parity(mesh_i, filt):
     assert_rel(got, ref, TOL)
     prep = htex.Prepared(s.dmesh, s.pool)
     f = t(q.f) if q.f is not None else None
-    o2 = htex.htex_sample_prepared(prep, s.pool, t(q.h), t(q.u), t(q.v), f, filter=filt)
-    torch.cuda.synchronize()
-    np.testing.assert_array_equal(o2.cpu().numpy(), got)
+    for flags in (0, htex.HTEX_QUERIES_SCATTERED):
+        o2 = htex.htex_sample_prepared(prep, s.pool, t(q.h), t(q.u), t(q.v), f, filter=filt,
+                                       flags=flags)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(o2.cpu().numpy(), got)
 
 
 @pytest.mark.parametrize("dtype", [htex.HTEX_BF16, htex.HTEX_FP8_E4M3])
@@ -72,6 +74,13 @@ def test_one_channel_quantized(dtype):
     assert_rel(got, ref, TOL)
     ref32, _, _ = s.ref(q, oracle.TRILINEAR)
     assert_rel(got, ref32, 4e-3 if dtype == htex.HTEX_BF16 else 6e-2)
+    # the prepared kernels (all taps, in-bounds taps) give the same bits
+    prep = htex.Prepared(s.dmesh, qp)
+    for flags in (0, htex.HTEX_QUERIES_SCATTERED):
+        o2 = htex.htex_sample_prepared(prep, qp, t(q.h), t(q.u), t(q.v), t(q.f),
+                                       filter=htex.HTEX_TRILINEAR, flags=flags)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(o2.cpu().numpy(), got)
 
 
 @pytest.mark.parametrize("flags", [0, htex.HTEX_QUERIES_SORTED])
