@@ -540,11 +540,12 @@ def test_largest_resolution_k15():
     ref = (ce * d["wf"]).sum(1)[:, None] / d["W"][:, None] * np.array([1.0, 2.0, 3.0, 4.0])
     assert_rel(got, ref, 2e-6)
     np.testing.assert_allclose(d["wf"].sum(1), d["W"], rtol=1e-6)
-    # (3) prepared path
+    # (3) prepared path, both kernels
     prep = htex.Prepared(dm, pool)
-    o2 = htex.htex_sample_prepared(prep, pool, t(q.h), t(q.u), t(q.v))
-    torch.cuda.synchronize()
-    np.testing.assert_array_equal(o2.cpu().numpy(), got)
+    for flags in (0, htex.HTEX_QUERIES_SCATTERED):
+        o2 = htex.htex_sample_prepared(prep, pool, t(q.h), t(q.u), t(q.v), flags=flags)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(o2.cpu().numpy(), got)
     # (4) gradient conservation per edge, plain atomics and the LDS tiles
     order = np.argsort(q.h, kind="stable")
     g4 = rng.standard_normal((Q, 4)).astype(np.float32)
