@@ -117,12 +117,170 @@ __device__ __forceinline__ void sample_one_prepared(const SampleArgs &a, int64_t
     store_row<CH>(a.out, q, C.x * r, C.y * r, C.z * r, C.w * r);
 }
 
+// Whether fetch s (Next or Prev) of a query may have an in-bounds tap: the
+// Next quad's y coordinate is -u (1 + u when reflected) and the Prev quad's
+// x coordinate is -v (1 + v), so a tap row or column of a level with n
+// texels lies inside only when c n <= 1/2; the test uses the coarsest level
+// the fetch samples, so it holds whenever any level has an in-bounds tap.
+__device__ __forceinline__ bool neighbour_may_touch(const Lod &L, int k, float c)
+{
+    int lv[2];
+    float om[2];
+    const int nl = fetch_levels(L, k, lv, om);
+    return ldexpf(c, k - (nl == 2 ? lv[1] : lv[0])) <= 0.5f;
+}
+
+__device__ __forceinline__ int32_t bperm(int32_t byte_addr, int32_t x)
+{
+    return __builtin_amdgcn_ds_bpermute(byte_addr, x);
+}
+__device__ __forceinline__ float bperm(int32_t byte_addr, float x)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(byte_addr, __float_as_int(x)));
+}
+
+// A Next or Prev fetch dealt out to another lane of the wavefront: the
+// owner's coordinates, level selection and the fetch's prepared record word.
+struct alignas(16) Task {
+    float u, v, phi, om0;
+    int32_t lpack;   // E << 2 | mode
+    int32_t e;
+    uint32_t wlo, whi;
+};
+constexpr int kTasks = 128;   // per wavefront: at most one Next and one Prev fetch per lane
+
+// The prepared fast path executed by a whole wavefront at once, for
+// BF16 and FP8 pools.  Every lane computes its own quad's fetch; the Next
+// and Prev fetches, which only queries near the spokes of their triangle
+// need, are compacted: lanes that need one are counted by ballot, write the
+// fetch's inputs to consecutive task slots in LDS, the wave works through
+// the slots 64 at a time, and each owner pulls its results back by
+// ds_bpermute and adds them in Alg. 3's order (a query's Next slot always
+// precedes its Prev slot), so the results are those of
+// sample_one_prepared bit for bit.  Decoding BF16 and FP8 texels makes those
+// launches VALU-bound, and the compaction saves a tenth of their time; the
+// float32 kernel is bound by the memory pipeline, and there the compaction
+// costs 2-3%.  All 64 lanes of the wave must call it; `live` marks lanes
+// that hold a query.
+template <int DT, int CH, bool TRI>
+__device__ __forceinline__ void sample_wave_prepared(const SampleArgs &a, int64_t q, bool live,
+                                                     Task *tasks)
+{
+    const int lane = (int)__lane_id();
+    int32_t h = 0;
+    float u = 0.0f, v = 0.0f, f = 0.0f;
+    if (live) {
+        h = __builtin_nontemporal_load(a.qh + q);
+        u = __builtin_nontemporal_load(a.qu + q);
+        v = __builtin_nontemporal_load(a.qv + q);
+        if constexpr (TRI) f = __builtin_nontemporal_load(a.qf + q);
+    }
+    const bool valid = live && ((uint32_t)h < (uint32_t)a.H) && isfinite(u) && isfinite(v);
+    if (live && !valid) {
+        const float nan = __uint_as_float(0x7fc00000u);
+        store_row<CH>(a.out, q, nan, nan, nan, nan);
+        if (a.err) atomicAdd(a.err, 1);
+    }
+    PrepRec rec;
+    if (valid) rec = static_cast<const PrepRec *>(a.prep)[h];
+    else rec = PrepRec{};
+    Lod L{0, 0, 0.0f, 1.0f};
+    if constexpr (TRI) L = lod_of(f);
+    // the Next and Prev fetches this query may need, posted as tasks
+    const bool need1 = valid && neighbour_may_touch(L, (int)((rec.w[1] >> 40) & 31u), u);
+    const bool need2 = valid && neighbour_may_touch(L, (int)((rec.w[2] >> 40) & 31u), v);
+    const uint64_t b1 = __ballot(need1), b2 = __ballot(need2);
+    const int n1 = __popcll(b1), T = n1 + __popcll(b2);
+    const int s1 = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b1 >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)b1, 0u));
+    const int s2 = n1 + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b2 >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)b2, 0u));
+    if (T > 0) {
+        Task t;
+        t.u = u;
+        t.v = v;
+        t.phi = L.phi;
+        t.om0 = L.om0;
+        t.lpack = (L.E << 2) | L.mode;
+        if (need1) {
+            t.e = rec.e[1];
+            t.wlo = (uint32_t)rec.w[1];
+            t.whi = (uint32_t)(rec.w[1] >> 32);
+            tasks[s1] = t;
+        }
+        if (need2) {
+            t.e = rec.e[2];
+            t.wlo = (uint32_t)rec.w[2];
+            t.whi = (uint32_t)(rec.w[2] >> 32);
+            tasks[s2] = t;
+        }
+    }
+    // Alg. 3's first fetch: the query's own quad at (u, v)
+    float4 C = make_float4(0.f, 0.f, 0.f, 0.f);
+    float W = 0.0f;
+    if (valid) {
+        const FetchSpec f0 = {h, u, v, false, false};
+        fetch<DT, CH, TRI, false>(a, L, f0, resolve_prepared<DT, CH>(a, rec.w[0], rec.e[0]), C, W,
+                                  nullptr, 0);
+    }
+    if (T > 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int base = 0; base < T; base += 64) {
+            const int i = base + lane;
+            const bool has = i < T;
+            const bool nx = i < n1;   // a Next fetch, else a Prev fetch
+            float4 Ct = make_float4(0.f, 0.f, 0.f, 0.f);
+            float Wt = 0.0f;
+            if (has) {
+                const Task t = tasks[i];
+                Lod tL;
+                tL.mode = t.lpack & 3;
+                tL.E = t.lpack >> 2;
+                tL.phi = t.phi;
+                tL.om0 = t.om0;
+                // Next quad at (v, -u), Prev quad at (-v, u)
+                const FetchSpec tf = {0, t.v, t.u, !nx, nx};
+                const uint64_t w = (uint64_t)t.whi << 32 | t.wlo;
+                fetch<DT, CH, TRI, false>(a, tL, tf, resolve_prepared<DT, CH>(a, w, t.e), Ct, Wt,
+                                          nullptr, nx ? 1 : 2);
+            }
+            // owners add the fetches of this round, Next before Prev
+            const int r1 = s1 - base, r2 = s2 - base;
+            const bool got1 = need1 && (uint32_t)r1 < 64u, got2 = need2 && (uint32_t)r2 < 64u;
+            const int a1 = (r1 & 63) << 2, a2 = (r2 & 63) << 2;
+            const float x1 = bperm(a1, Ct.x), x2 = bperm(a2, Ct.x);
+            const float q1 = bperm(a1, Wt), q2 = bperm(a2, Wt);
+            if constexpr (CH == 4) {
+                const float y1 = bperm(a1, Ct.y), z1 = bperm(a1, Ct.z), w1 = bperm(a1, Ct.w);
+                const float y2 = bperm(a2, Ct.y), z2 = bperm(a2, Ct.z), w2 = bperm(a2, Ct.w);
+                if (got1) { C.x += x1; C.y += y1; C.z += z1; C.w += w1; W += q1; }
+                if (got2) { C.x += x2; C.y += y2; C.z += z2; C.w += w2; W += q2; }
+            } else {
+                if (got1) { C.x += x1; W += q1; }
+                if (got2) { C.x += x2; W += q2; }
+            }
+        }
+    }
+    if (valid) {
+        const float r = __builtin_amdgcn_rcpf(W);
+        store_row<CH>(a.out, q, C.x * r, C.y * r, C.z * r, C.w * r);
+    }
+}
+
 template <int DT, int CH, bool TRI, bool SCATTERED>
 __global__ void __launch_bounds__(kBlock) k_sample_prep(SampleArgs a)
 {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q >= a.Q) return;
-    sample_one_prepared<DT, CH, TRI, SCATTERED>(a, q);
+    if constexpr (!SCATTERED && DT != HTEX_F32) {
+        __shared__ Task tasks[kBlock / 64][kTasks];
+        if (q - (int64_t)__lane_id() >= a.Q) return;   // the whole wavefront is past the end
+        sample_wave_prepared<DT, CH, TRI>(a, q, q < a.Q, tasks[threadIdx.x >> 6]);
+    } else {
+        if (q >= a.Q) return;
+        sample_one_prepared<DT, CH, TRI, SCATTERED>(a, q);
+    }
 }
 
 // Serving: one launch covers a list of tiles, each up to kBlock queries of

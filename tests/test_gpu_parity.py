@@ -445,6 +445,29 @@ def test_prepared_path_is_bit_identical(mesh_i, dtype, flags):
         assert int(err.item()) == 4
 
 
+@pytest.mark.parametrize("dtype", [htex.HTEX_BF16, htex.HTEX_FP8_E4M3])
+@pytest.mark.parametrize("channels", [4, 1])
+@pytest.mark.parametrize("Q", [1, 63, 64, 65, 257, 4099])
+def test_prepared_wavefront_path_ragged(dtype, channels, Q):
+    """BF16 and FP8 pools take the wavefront-compacted kernel (Next and Prev
+    fetches dealt out across the wave): partial last wavefronts, invalid
+    lanes among valid ones and both channel counts give htex_sample's bits."""
+    m = tiny_meshes()[0]
+    rng = np.random.default_rng(80 + Q)
+    s = Setup(m, rng.integers(0, 6, m.E), has_mips=True, kind=1, seed=81, channels=channels)
+    pool = htex.htex_quantize(s.pool, dtype)
+    prep = htex.Prepared(s.dmesh, pool)
+    q = uniform_queries(m.H, Q, 82 + Q, log2f=(-9, 1.5))
+    if Q > 3:
+        q.h[1] = -1
+        q.v[2] = np.nan
+    for filt in (htex.HTEX_BILINEAR, htex.HTEX_TRILINEAR):
+        a, _ = s.gpu(q, filt, pool=pool)
+        b = htex.htex_sample_prepared(prep, pool, t(q.h), t(q.u), t(q.v), t(q.f), filter=filt)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(b.cpu().numpy(), a)
+
+
 @pytest.mark.parametrize("Q", [0, 1, 255, 257])
 def test_prepared_ragged(cfg1, Q):
     prep = htex.Prepared(cfg1.dmesh, cfg1.pool)
