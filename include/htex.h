@@ -60,7 +60,7 @@ typedef int32_t htex_status;
 #define HTEX_E_TOPOLOGY (-2)     /* halfedge arrays violate an invariant      */
 #define HTEX_E_RANGE (-3)        /* a size exceeds what the library supports  */
 #define HTEX_E_DEVICE (-4)       /* a HIP call or kernel launch failed        */
-#define HTEX_E_UNSUPPORTED (-5)  /* valid request this build does not do      */
+#define HTEX_E_UNSUPPORTED (-5)  /* valid request the library does not serve  */
 #define HTEX_E_BUSY (-6)         /* resource in use (serving)                 */
 #define HTEX_E_NOMEM (-7)        /* memory budget exhausted (serving)         */
 
