@@ -46,7 +46,7 @@ def test_corner_average_matches_oracle(mesh_i, layout):
     s = Setup(m, lr, has_mips=mips, kind=1, seed=31 + mesh_i)
     before, after, err = _run(s)
     assert err == 0
-    # the oracle starts from the very float32 values the GPU pool held
+    # the oracle starts from the very float32 values the device texel pool held
     op = oracle.Pool(s.log2res, s.opool.base, before.astype(np.float64), mips)
     ref = oracle.corner_average(s.omesh, op, m.vert, m.face, m.V, m.F)
     changed = ref != before
