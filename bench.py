@@ -61,6 +61,9 @@ def parse():
                     help="skip the exact algorithmic-byte count (roofline left null)")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving benchmark (200 GB of resident meshes)")
+    ap.add_argument("--serve-chunk", type=int, default=0,
+                    help="serving: copy requests in round-robin chunks of this many queries "
+                         "(0: whole requests in arrival order)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -585,7 +588,8 @@ def serve_meshes(seed=501):
         return list(ex.map(_gen_sphere, [(int(n), seed * 100 + i) for i, n in enumerate(ns)]))
 
 
-def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9), run_s=2.0):
+def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9), run_s=2.0,
+                    chunk=0):
     """Serving form: 16 resident meshes (5k-500k faces, log-uniform) with
     BF16 textures + mips sized to about 200 GB, Poisson streams of requests
     of 4k-2M queries (log-uniform, frame-like, sorted by halfedge) to random
@@ -659,7 +663,8 @@ def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9),
     seq_rate = sum(payloads[j][1] for j in range(16)) / sum(seq_lat)
 
     srv = Server(htex.HTEX_BF16, htex.HTEX_TRILINEAR, arena_bytes=4 << 30, max_inflight=64,
-                 compute_streams=1, copy_streams=1, max_batch_queries=1 << 22, max_meshes=16)
+                 compute_streams=1, copy_streams=1, max_batch_queries=1 << 22, max_meshes=16,
+                 copy_chunk_queries=chunk)
     for dm, pool, prep, _ in resident:
         srv.add_mesh(prep, pool)
 
@@ -738,6 +743,7 @@ def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9),
     srv.close()
     out["batches"] = st["batches"]
     out["arena_peak_bytes"] = st["arena_peak_bytes"]
+    out["copy_chunk_queries"] = chunk
     del resident, payloads, alone
     torch.cuda.empty_cache()
     return out
@@ -987,7 +993,7 @@ def main():
     if not args.no_serve and args.workload == "frame4k":
         del prep, out, dev_batches, pool
         torch.cuda.empty_cache()
-        serving = serve_benchmark(smeshes)
+        serving = serve_benchmark(smeshes, chunk=args.serve_chunk)
 
     fs = mesh.face_sizes()
     rec = {

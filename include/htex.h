@@ -386,6 +386,12 @@ typedef struct htex_server_config {
     int32_t copy_streams;     /* host<->device copy streams per direction, 1..4 */
     int32_t channels;         /* channels of every pool and result row: 1 or 4
                                  (0 means 4)                                   */
+    int32_t copy_chunk_queries;/* > 0: requests are copied in chunks of this
+                                 many queries, round-robin over the requests
+                                 in flight, so the PCIe link is shared among
+                                 them; 0: each request is copied whole, in
+                                 arrival order                                 */
+    int32_t reserved;         /* 0                                             */
 } htex_server_config;
 
 typedef struct htex_server_stats {

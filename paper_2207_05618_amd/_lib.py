@@ -83,7 +83,8 @@ class htex_server_config(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("filter", C.c_int32), ("max_inflight", C.c_int32),
                 ("compute_streams", C.c_int32), ("arena_bytes", C.c_int64),
                 ("max_batch_queries", C.c_int64), ("grid_blocks", C.c_int32),
-                ("max_meshes", C.c_int32), ("copy_streams", C.c_int32), ("channels", C.c_int32)]
+                ("max_meshes", C.c_int32), ("copy_streams", C.c_int32), ("channels", C.c_int32),
+                ("copy_chunk_queries", C.c_int32), ("reserved", C.c_int32)]
 
 
 class htex_server_stats(C.Structure):

@@ -3,16 +3,23 @@
 // One scheduler thread owns every HIP call of the server.  Its loop:
 //   1. admission: pending requests, in arrival order, take a request slot
 //      and an arena block (32 bytes per query) while both are available;
-//      their queries go to the device on the upload stream;
-//   2. batching: when a compute stream is free, the admitted requests not yet
+//   2. uploads: admitted requests' queries go to the device in chunks of
+//      copy_chunk_queries, taken round-robin over the requests still
+//      uploading (a whole request at a time when the chunk size is 0), with
+//      a few chunks in flight per copy stream;
+//   3. batching: when a compute stream is free, the uploaded requests not yet
 //      launched (in order, up to max_batch_queries) become one tile list and
-//      one k_serve launch; the stream first waits for their uploads, and the
-//      download stream waits for the launch before copying results back;
-//   3. completion: a request whose download has finished is complete: its
-//      arena block and slot are released and its latency recorded.
+//      one k_serve launch;
+//   4. downloads: requests whose batch has finished copy their results back
+//      in chunks, round-robin like the uploads;
+//   5. completion: a request whose last result chunk has arrived is
+//      complete: its arena block and slot are released and its latency
+//      recorded.
 // Requests that arrive while batches run are admitted and launched as soon
 // as a slot, memory and a stream free up, so their work overlaps on the
-// device with the batches in flight.
+// device with the batches in flight.  Round-robin chunks share the PCIe
+// link among the requests in flight (processor sharing): a small request
+// no longer waits behind a large one's copies.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -24,6 +31,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <set>
 #include <stdexcept>
 #include <string>
 #include <thread>
@@ -95,7 +103,15 @@ struct Request {
     // device arrays inside the arena
     int32_t *dh = nullptr;
     float *du = nullptr, *dv = nullptr, *df = nullptr, *dout = nullptr;
-    hipEvent_t ev_up = nullptr, ev_down = nullptr;
+    // queries whose upload / download has been issued, and completed
+    int64_t up_sent = 0, up_done = 0, down_sent = 0, down_done = 0;
+};
+
+// A copy of one request's queries [q0, q0 + n) in flight on a copy stream.
+struct Chunk {
+    hipEvent_t ev;
+    Request *r;
+    int64_t n;
 };
 
 struct Batch {
@@ -136,20 +152,24 @@ struct htex_server {
     std::string worker_error;
 
     // scheduler-thread state
-    std::deque<Request *> pending;     // waiting for admission
-    std::deque<Request *> admitted;    // uploaded (or uploading), not launched
-    std::vector<Request *> downloading;
+    std::deque<Request *> pending;      // waiting for admission
+    std::deque<Request *> uploading;    // admitted, upload chunks left to issue
+    std::deque<Request *> admitted;     // uploaded, not launched
+    std::deque<Request *> downloading;  // batch finished, result chunks left to issue
+    std::vector<Chunk> up_chunks, down_chunks;   // copies in flight
+    std::vector<hipEvent_t> free_events;
     int inflight = 0;
 
     void run();
     bool step();
+    bool idle() const;
 };
 
 namespace {
 
-hipError_t upload(htex_server *S, Request *r)
+// Places a request's device arrays inside its arena block.
+void carve_arrays(htex_server *S, Request *r)
 {
-    hipStream_t su = S->s_up[S->up_rr++ % S->s_up.size()];
     const bool tri = S->cfg.filter == HTEX_TRILINEAR;
     const int64_t Q = r->Q;
     char *base = S->arena_dev + r->arena_off;
@@ -163,13 +183,47 @@ hipError_t upload(htex_server *S, Request *r)
     r->dv = reinterpret_cast<float *>(carve(4 * Q));
     r->df = tri ? reinterpret_cast<float *>(carve(4 * Q)) : nullptr;
     r->dout = reinterpret_cast<float *>(carve(4 * S->channels * Q));
-    hipError_t e = hipMemcpyAsync(r->dh, r->h, 4 * Q, hipMemcpyHostToDevice, su);
-    if (!e) e = hipMemcpyAsync(r->du, r->u, 4 * Q, hipMemcpyHostToDevice, su);
-    if (!e) e = hipMemcpyAsync(r->dv, r->v, 4 * Q, hipMemcpyHostToDevice, su);
-    if (!e && tri) e = hipMemcpyAsync(r->df, r->f, 4 * Q, hipMemcpyHostToDevice, su);
-    if (!e) e = hipEventCreateWithFlags(&r->ev_up, hipEventDisableTiming);
-    if (!e) e = hipEventCreateWithFlags(&r->ev_down, hipEventDisableTiming);
-    if (!e) e = hipEventRecord(r->ev_up, su);
+}
+
+hipError_t take_event(htex_server *S, hipEvent_t *ev)
+{
+    if (!S->free_events.empty()) {
+        *ev = S->free_events.back();
+        S->free_events.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreateWithFlags(ev, hipEventDisableTiming);
+}
+
+// Issues the next upload chunk of r: queries [up_sent, up_sent + n).
+hipError_t upload_chunk(htex_server *S, Request *r, int64_t n, Chunk *c)
+{
+    hipStream_t su = S->s_up[S->up_rr++ % S->s_up.size()];
+    const int64_t q0 = r->up_sent;
+    hipError_t e = hipMemcpyAsync(r->dh + q0, r->h + q0, 4 * n, hipMemcpyHostToDevice, su);
+    if (!e) e = hipMemcpyAsync(r->du + q0, r->u + q0, 4 * n, hipMemcpyHostToDevice, su);
+    if (!e) e = hipMemcpyAsync(r->dv + q0, r->v + q0, 4 * n, hipMemcpyHostToDevice, su);
+    if (!e && r->df) e = hipMemcpyAsync(r->df + q0, r->f + q0, 4 * n, hipMemcpyHostToDevice, su);
+    if (!e) e = take_event(S, &c->ev);
+    if (!e) e = hipEventRecord(c->ev, su);
+    c->r = r;
+    c->n = n;
+    r->up_sent += n;
+    return e;
+}
+
+// Issues the next result chunk of r: rows [down_sent, down_sent + n).
+hipError_t download_chunk(htex_server *S, Request *r, int64_t n, Chunk *c)
+{
+    hipStream_t sd = S->s_down[S->down_rr++ % S->s_down.size()];
+    const int64_t q0 = r->down_sent, row = S->channels;
+    hipError_t e = hipMemcpyAsync(r->out + row * q0, r->dout + row * q0, 4 * row * n,
+                                  hipMemcpyDeviceToHost, sd);
+    if (!e) e = take_event(S, &c->ev);
+    if (!e) e = hipEventRecord(c->ev, sd);
+    c->r = r;
+    c->n = n;
+    r->down_sent += n;
     return e;
 }
 
@@ -193,6 +247,9 @@ bool htex_server::step()
             inbox.pop_front();
         }
     }
+    auto check = [](hipError_t e, const char *what) {
+        if (e) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+    };
     // 1. admission in arrival order
     while (!pending.empty() && inflight < cfg.max_inflight) {
         Request *r = pending.front();
@@ -203,16 +260,44 @@ bool htex_server::step()
         r->arena_bytes = bytes;
         pending.pop_front();
         ++inflight;
-        hipError_t e = upload(this, r);
-        if (e) throw std::runtime_error(std::string("upload: ") + hipGetErrorString(e));
-        admitted.push_back(r);
+        carve_arrays(this, r);
+        uploading.push_back(r);
         worked = true;
     }
-    // 2. batching on free compute streams
+    const int64_t chunk = cfg.copy_chunk_queries > 0 ? cfg.copy_chunk_queries : INT64_MAX;
+    // a few chunks queued per copy stream keep its DMA engine busy between
+    // two passes of this loop
+    const size_t max_up = 4 * s_up.size(), max_down = 4 * s_down.size();
+    // 2. upload chunks, round-robin over the requests still uploading
+    while (!uploading.empty() && up_chunks.size() < max_up) {
+        Request *r = uploading.front();
+        uploading.pop_front();
+        const int64_t left = r->Q - r->up_sent;
+        Chunk c;
+        check(upload_chunk(this, r, left < chunk ? left : chunk, &c), "upload");
+        up_chunks.push_back(c);
+        if (r->up_sent < r->Q) uploading.push_back(r);
+        worked = true;
+    }
+    for (size_t i = 0; i < up_chunks.size();) {
+        const Chunk c = up_chunks[i];
+        if (hipEventQuery(c.ev) != hipSuccess) {
+            ++i;
+            continue;
+        }
+        free_events.push_back(c.ev);
+        up_chunks[i] = up_chunks.back();
+        up_chunks.pop_back();
+        c.r->up_done += c.n;
+        if (c.r->up_done == c.r->Q) admitted.push_back(c.r);
+        worked = true;
+    }
+    // 3. batching on free compute streams
     for (Batch &b : batches) {
         if (b.busy) {
             if (hipEventQuery(b.ev_done) == hipSuccess) {
                 b.busy = false;
+                for (Request *r : b.reqs) downloading.push_back(r);
                 b.reqs.clear();
                 worked = true;
             } else {
@@ -242,27 +327,29 @@ bool htex_server::step()
             }
             ntiles += t;
             nq += r->Q;
-            hipError_t e = hipStreamWaitEvent(b.stream, r->ev_up, 0);
-            if (e) throw std::runtime_error(std::string("wait: ") + hipGetErrorString(e));
             b.reqs.push_back(r);
             admitted.pop_front();
         }
         if (b.reqs.empty()) continue;
+        // the uploads of every request in the batch have completed (their
+        // chunk events were observed above), so the launch waits on nothing
         hipError_t e = hipMemcpyAsync(b.tiles_dev, b.tiles_host, sizeof(htex::ServeTile) * ntiles,
                                       hipMemcpyHostToDevice, b.stream);
         if (!e) e = htex::launch_serve(meshes_dev, b.tiles_dev, ntiles, grid, cfg.dtype, channels,
                                        cfg.filter, err_dev, b.stream);
         if (!e) e = hipEventRecord(b.ev_done, b.stream);
-        for (hipStream_t sd : s_down)
-            if (!e) e = hipStreamWaitEvent(sd, b.ev_done, 0);
-        for (Request *r : b.reqs) {
-            hipStream_t sd = s_down[down_rr++ % s_down.size()];
-            if (!e) e = hipMemcpyAsync(r->out, r->dout, 4 * channels * r->Q, hipMemcpyDeviceToHost,
-                                       sd);
-            if (!e) e = hipEventRecord(r->ev_down, sd);
-            downloading.push_back(r);
+        check(e, "launch");
+        if (cfg.copy_chunk_queries == 0) {
+            // whole-request results: queued now behind the launch, so no host
+            // round trip sits between the batch's end and its downloads
+            for (hipStream_t sd : s_down) check(hipStreamWaitEvent(sd, b.ev_done, 0), "wait");
+            for (Request *r : b.reqs) {
+                Chunk c;
+                check(download_chunk(this, r, r->Q, &c), "download");
+                down_chunks.push_back(c);
+            }
+            b.reqs.clear();   // the download chunks own the requests now
         }
-        if (e) throw std::runtime_error(std::string("launch: ") + hipGetErrorString(e));
         b.busy = true;
         {
             std::lock_guard<std::mutex> lk(mu);
@@ -270,18 +357,34 @@ bool htex_server::step()
         }
         worked = true;
     }
-    // 3. completion
-    for (size_t i = 0; i < downloading.size();) {
-        Request *r = downloading[i];
-        if (hipEventQuery(r->ev_down) != hipSuccess) {
+    // 4. result chunks, round-robin over the requests whose batch finished
+    while (!downloading.empty() && down_chunks.size() < max_down) {
+        Request *r = downloading.front();
+        downloading.pop_front();
+        const int64_t left = r->Q - r->down_sent;
+        Chunk c;
+        check(download_chunk(this, r, left < chunk ? left : chunk, &c), "download");
+        down_chunks.push_back(c);
+        if (r->down_sent < r->Q) downloading.push_back(r);
+        worked = true;
+    }
+    // 5. completion
+    for (size_t i = 0; i < down_chunks.size();) {
+        const Chunk c = down_chunks[i];
+        if (hipEventQuery(c.ev) != hipSuccess) {
             ++i;
             continue;
         }
+        free_events.push_back(c.ev);
+        down_chunks[i] = down_chunks.back();
+        down_chunks.pop_back();
+        Request *r = c.r;
+        r->down_done += c.n;
+        worked = true;
+        if (r->down_done < r->Q) continue;
         const double lat = std::chrono::duration<double>(Clock::now() - r->t_submit).count();
         arena->release(r->arena_off, r->arena_bytes);
         --inflight;
-        (void)hipEventDestroy(r->ev_up);
-        (void)hipEventDestroy(r->ev_down);
         {
             std::lock_guard<std::mutex> lk(mu);
             done.emplace_back(r->id, lat);
@@ -289,12 +392,19 @@ bool htex_server::step()
             queries_done += r->Q;
         }
         delete r;
-        downloading[i] = downloading.back();
-        downloading.pop_back();
-        worked = true;
     }
     if (worked) cv.notify_all();
     return worked;
+}
+
+bool htex_server::idle() const
+{
+    if (!pending.empty() || !uploading.empty() || !admitted.empty() || !downloading.empty() ||
+        !up_chunks.empty() || !down_chunks.empty())
+        return false;
+    for (const Batch &b : batches)
+        if (b.busy) return false;
+    return true;
 }
 
 void htex_server::run()
@@ -307,8 +417,8 @@ void htex_server::run()
     try {
         for (;;) {
             const bool worked = step();
-            const bool idle = pending.empty() && admitted.empty() && downloading.empty();
-            if (stop.load() && idle) {
+            const bool quiet = idle();
+            if (stop.load() && quiet) {
                 bool empty;
                 {
                     std::lock_guard<std::mutex> lk(mu);
@@ -317,7 +427,7 @@ void htex_server::run()
                 if (empty) break;
             }
             if (!worked) {
-                if (idle) {
+                if (quiet) {
                     std::unique_lock<std::mutex> lk(mu);
                     cv.wait_for(lk, std::chrono::microseconds(200),
                                 [&] { return !inbox.empty() || stop.load(); });
@@ -349,7 +459,7 @@ htex_status htex_server_create(const htex_server_config *cfg, htex_server **out)
     if (cfg->max_inflight <= 0 || cfg->compute_streams < 1 || cfg->compute_streams > 4 ||
         cfg->copy_streams < 1 || cfg->copy_streams > 4 ||
         cfg->arena_bytes <= 0 || cfg->max_batch_queries <= 0 || cfg->max_meshes <= 0 ||
-        cfg->grid_blocks < 0)
+        cfg->grid_blocks < 0 || cfg->copy_chunk_queries < 0 || cfg->reserved != 0)
         return fail(HTEX_E_ARG, "bad server configuration");
     if (cfg->channels != 0 && cfg->channels != 1 && cfg->channels != 4)
         return fail(HTEX_E_ARG, "channels must be 0 (RGBA), 1 or 4");
@@ -536,16 +646,26 @@ htex_status htex_server_destroy(htex_server *S)
     if (S->arena_dev) (void)hipFree(S->arena_dev);
     if (S->meshes_dev) (void)hipFree(S->meshes_dev);
     if (S->err_dev) (void)hipFree(S->err_dev);
-    // requests left behind only if the scheduler stopped on an error
-    auto drop = [](Request *r) {
-        if (r->ev_up) (void)hipEventDestroy(r->ev_up);
-        if (r->ev_down) (void)hipEventDestroy(r->ev_down);
-        delete r;
-    };
-    for (Request *r : S->inbox) drop(r);
-    for (Request *r : S->pending) drop(r);
-    for (Request *r : S->admitted) drop(r);
-    for (Request *r : S->downloading) drop(r);
+    // requests left behind only if the scheduler stopped on an error; one
+    // request may sit in several lists (uploading and a chunk in flight)
+    std::set<Request *> left;
+    for (Request *r : S->inbox) left.insert(r);
+    for (Request *r : S->pending) left.insert(r);
+    for (Request *r : S->uploading) left.insert(r);
+    for (Request *r : S->admitted) left.insert(r);
+    for (Request *r : S->downloading) left.insert(r);
+    for (const Batch &b : S->batches)
+        for (Request *r : b.reqs) left.insert(r);
+    for (const Chunk &c : S->up_chunks) {
+        left.insert(c.r);
+        (void)hipEventDestroy(c.ev);
+    }
+    for (const Chunk &c : S->down_chunks) {
+        left.insert(c.r);
+        (void)hipEventDestroy(c.ev);
+    }
+    for (hipEvent_t ev : S->free_events) (void)hipEventDestroy(ev);
+    for (Request *r : left) delete r;
     delete S->arena;
     delete S;
     htex::clear_error();

@@ -23,11 +23,11 @@ class Server:
     # 4 queues, 1.1-1.4e9 with more streams.
     def __init__(self, dtype, filter, arena_bytes=1 << 30, max_inflight=64,
                  compute_streams=1, max_batch_queries=1 << 22, grid_blocks=0,
-                 max_meshes=64, copy_streams=1, channels=4):
+                 max_meshes=64, copy_streams=1, channels=4, copy_chunk_queries=0):
         cfg = _lib.htex_server_config(int(dtype), int(filter), int(max_inflight),
                                       int(compute_streams), int(arena_bytes),
                                       int(max_batch_queries), int(grid_blocks), int(max_meshes),
-                                      int(copy_streams), int(channels))
+                                      int(copy_streams), int(channels), int(copy_chunk_queries), 0)
         self.channels = int(channels)
         self._h = C.c_void_p()
         check(load().htex_server_create(C.byref(cfg), C.byref(self._h)))

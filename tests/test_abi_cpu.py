@@ -175,3 +175,18 @@ def test_aniso_argument_checks():
                                         None) == -1
     assert L.htex_sample_aniso_prepared(4, 24, C.byref(ok_pool), C.byref(q), 16, 4, 0, 16, None,
                                         None) == -1
+
+
+@pytest.mark.parametrize("field, value", [("copy_chunk_queries", -1), ("reserved", 1),
+                                          ("max_inflight", 0), ("copy_streams", 5),
+                                          ("channels", 2)])
+def test_server_config_is_checked_before_any_device_call(field, value):
+    """A bad serving configuration is refused by argument checks alone."""
+    import ctypes as C
+    L = _lib.load()
+    cfg = _lib.htex_server_config(0, 1, 8, 1, 1 << 20, 1 << 16, 0, 4, 1, 4, 0, 0)
+    setattr(cfg, field, value)
+    h = C.c_void_p()
+    assert L.htex_server_create(C.byref(cfg), C.byref(h)) == -1
+    assert not h.value
+    assert L.htex_last_error().decode() != ""

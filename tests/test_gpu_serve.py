@@ -47,9 +47,12 @@ def _alone(meshes, mid, q):
 
 
 @pytest.mark.parametrize("arena", [1 << 28, 1 << 20])
-def test_results_identical_alone_and_in_the_mix(meshes, arena):
+@pytest.mark.parametrize("chunk", [0, 3000])
+def test_results_identical_alone_and_in_the_mix(meshes, arena, chunk):
+    """With whole-request copies and with round-robin chunks of 3000 queries
+    (most requests span several chunks, some fit in one)."""
     srv = Server(htex.HTEX_BF16, htex.HTEX_TRILINEAR, arena_bytes=arena, max_inflight=16,
-                 compute_streams=2, max_batch_queries=1 << 16)
+                 compute_streams=2, max_batch_queries=1 << 16, copy_chunk_queries=chunk)
     ids = [srv.add_mesh(prep, pool) for _, pool, prep in meshes]
     assert ids == [0, 1, 2]
     reqs = _requests(meshes, 60, 11, hi=30000 if arena > 1 << 20 else 20000)
