@@ -357,13 +357,15 @@ htex_status htex_sample_aniso_prepared(int32_t H, const void *prep, const htex_p
  * request slots and device memory (an arena of arena_bytes, 32 bytes per
  * query) free up; admitted requests are copied to the device (on
  * copy_streams upload streams; results come back on as many download
- * streams, both directions at once) and gathered
- * into batches, each computed by one launch over a list of 256-query tiles
- * that mixes requests and meshes; up to compute_streams launches run at
- * once, and requests arriving meanwhile join the next batch.  Results are
- * copied back into the caller's host buffer; a request is complete when its
- * result is in host memory.  Every query is computed by the same device code
- * as htex_sample_prepared, so results are identical alone and in any mix.
+ * streams, both directions at once; whole requests in arrival order, or
+ * round-robin chunks of copy_chunk_queries), and requests whose upload has
+ * completed are gathered into batches, each computed by one launch over a
+ * list of 256-query tiles that mixes requests and meshes; up to
+ * compute_streams launches run at once, and requests arriving meanwhile
+ * join a later batch.  Results are copied back into the caller's host
+ * buffer; a request is complete when its result is in host memory.  Every
+ * query is computed with the arithmetic of htex_sample_prepared, bit for
+ * bit, so results are identical alone and in any mix.
  * A scheduler thread inside the library drives the device; the calls below
  * are thread-safe.  Not part of the paper (which renders frames); this is
  * the batched serving form of its sampling. */
