@@ -98,137 +98,329 @@ __global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
 // At the end every tile is added to the pool once, one float atomic per
 // non-zero texel channel.  Trilinear batches touch about 3 edges x 6
 // levels per block, which is why tiles are sized per level.
+//
+// Dense blocks.  LDS float atomics cost about as much as the rest of the
+// kernel, while LDS integer atomics are cheap.  When a bilinear block's
+// queries all lie on one halfedge whose texture has at most 32 x 32 texels
+// (many samples per texel, as when fitting a texture), the block first bins
+// its queries by the tap cell (i0, j0) of their own fetch, counting with
+// integer atomics, and each thread then walks a run of binned queries:
+// consecutive queries of one cell share their four target texels, so their
+// contributions are summed in registers and added to the tile once per
+// run.  Queries on other halfedges, or whose taps fall outside the cell
+// range, take the per-query path.
 constexpr int kTiles = 32;
 constexpr int kArenaFloats = 16384;   // 64 KB
 constexpr int kBwdPerThread = 16;
 constexpr int kBwdChunk = kBlock * kBwdPerThread;
+constexpr int kDenseMaxLog2 = 5;
+constexpr int kDenseSide = (1 << kDenseMaxLog2) + 1;   // tap bases -1 .. n - 1 per axis
+constexpr int kDenseCells = kDenseSide * kDenseSide;
+constexpr int kCellsPerThread = (kDenseCells + kBlock - 1) / kBlock;
+static_assert(kBwdChunk <= 65536, "binned query indices are 16-bit");
+
+constexpr uint64_t kFree = ~0ull;
+constexpr uint32_t kPending = 0xfffffffeu, kNoRoom = 0xfffffffdu;
+
+struct TileTable {
+    float *arena;
+    uint64_t *entry;   // key << 32 | offset (kPending, kNoRoom) or kFree
+    int32_t *used;
+};
+
+// Arena offset (floats) of the tile `key` of `need` floats: found, or
+// claimed for this block; -1 when it is pending, does not fit, or the
+// table is full.
+__device__ __forceinline__ int32_t find_tile(const TileTable &T, int32_t key, int64_t need)
+{
+    const uint32_t h0 = ((uint32_t)key * 2654435761u) >> 27;   // 5 bits
+    for (int pr = 0; pr < kTiles; ++pr) {
+        const int t = (int)((h0 + pr) & (kTiles - 1));
+        uint64_t en = __atomic_load_n(&T.entry[t], __ATOMIC_RELAXED);
+        if (en == kFree) {
+            const uint64_t mine = ((uint64_t)(uint32_t)key << 32) | kPending;
+            en = atomicCAS(&T.entry[t], kFree, mine);
+            if (en == kFree) {   // claimed: reserve the level's texels
+                const int32_t o = need <= kArenaFloats ? atomicAdd(T.used, (int32_t)need)
+                                                       : kArenaFloats;
+                const bool fits = o + need <= kArenaFloats;
+                atomicExch(&T.entry[t], ((uint64_t)(uint32_t)key << 32) |
+                                            (fits ? (uint32_t)o : kNoRoom));
+                return fits ? o : -1;
+            }
+        }
+        if ((uint32_t)(en >> 32) == (uint32_t)key) {
+            const uint32_t lo32 = (uint32_t)(en & 0xffffffffu);
+            return lo32 < (uint32_t)kArenaFloats ? (int32_t)lo32 : -1;
+        }
+    }
+    return -1;
+}
+
+// Adds w * g to texel `off` of a level: into its tile when it has one,
+// else into the gradient pool.
+template <int CH>
+__device__ __forceinline__ void add_tap(float *arena, int32_t base_f, uint32_t rel, float *pool_c,
+                                        float4 x)
+{
+    if (base_f >= 0) {
+        float *c = &arena[base_f + CH * (int32_t)rel];
+        atomicAdd(c + 0, x.x);
+        if constexpr (CH == 4) {
+            atomicAdd(c + 1, x.y);
+            atomicAdd(c + 2, x.z);
+            atomicAdd(c + 3, x.w);
+        }
+    } else {
+        unsafeAtomicAdd(pool_c + 0, x.x);
+        if constexpr (CH == 4) {
+            unsafeAtomicAdd(pool_c + 1, x.y);
+            unsafeAtomicAdd(pool_c + 2, x.z);
+            unsafeAtomicAdd(pool_c + 3, x.w);
+        }
+    }
+}
+
+// The transpose of Alg. 3 for query q: every in-bounds tap of every fetch
+// and level receives (om w / W) dL/dout.  With `own_run`, the own fetch's
+// level-0 taps are not added but handed back (its plan, 1 / W and
+// dL/dout) for the caller to accumulate.  Returns false for an invalid
+// query.
+template <int CH, bool TRI>
+__device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, const TileTable &T,
+                                              int32_t (&memo_key)[3][2], int32_t (&memo_base)[3][2],
+                                              bool own_run, LevelPlan &own, float &own_rw,
+                                              float4 &own_g)
+{
+    const int32_t h = a.qh[q];
+    const float u = a.qu[q], v = a.qv[q];
+    if (!((uint32_t)h < (uint32_t)a.H) || !isfinite(u) || !isfinite(v)) return false;
+    const int32_t n1 = a.next[h], p1 = a.prev[h];
+    Lod L{0, 0, 0.0f, 1.0f};
+    if constexpr (TRI) L = lod_of(a.qf[q]);
+    FetchSpec fs[3];
+    fetch_specs(h, n1, p1, u, v, fs);
+    int32_t es[3], ks[3];
+    bool flips[3];
+    float W = 0.0f;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int32_t g = fs[s].g;
+        flips[s] = !(g > a.twin[g]);
+        es[s] = a.edge[g];
+        ks[s] = a.log2res[es[s]];
+        int lv[2];
+        float om[2];
+        const int nlev = fetch_levels(L, ks[s], lv, om);
+        for (int sl = 0; sl < nlev; ++sl) {
+            const LevelPlan p = plan_level(ks[s], lv[sl], om[sl], fs[s], flips[s]);
+            W += (p.wx0 + p.wx1) * (p.wy0 + p.wy1);
+        }
+    }
+    const float4 g4 = load_row<CH>(a.dout, q);
+    const float rW = 1.0f / W;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        int lv[2];
+        float om[2];
+        const int nlev = fetch_levels(L, ks[s], lv, om);
+        const int64_t eb = a.base[es[s]];
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+            if (sl >= nlev) break;
+            const LevelPlan p = plan_level(ks[s], lv[sl], om[sl], fs[s], flips[s]);
+            if (!TRI && own_run && s == 0) {
+                own = p;
+                continue;
+            }
+            if (!p.act) continue;
+            const int m = ks[s] - lv[sl];
+            const uint32_t lo = level_offset32(ks[s], lv[sl]);
+            // the tile of this (edge, level): remembered, found, or claimed
+            const int32_t key = es[s] * 16 + lv[sl];
+            // floats of this level's tile (computed in 64 bits: a level of
+            // 2^15 x 2^15 RGBA texels needs 2^32 floats; it never fits)
+            const int64_t need = (int64_t)CH << (2 * m);
+            int32_t base_f = memo_key[s][sl] == key ? memo_base[s][sl] : find_tile(T, key, need);
+            if (base_f >= 0) {
+                memo_key[s][sl] = key;
+                memo_base[s][sl] = base_f;
+            }
+            const float w[4] = {p.wx0 * p.wy0, p.wx1 * p.wy0, p.wx0 * p.wy1, p.wx1 * p.wy1};
+            const uint32_t off[4] = {p.o00, p.o01, p.o10, p.o11};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (!((p.mask >> t) & 1)) continue;
+                const float wt = w[t] * rW;
+                add_tap<CH>(T.arena, base_f, off[t] - lo, a.dtex + CH * (eb + off[t]),
+                            make_float4(wt * g4.x, wt * g4.y, wt * g4.z, wt * g4.w));
+            }
+        }
+    }
+    own_rw = rW;
+    own_g = g4;
+    return true;
+}
 
 template <int CH, bool TRI>
 __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
 {
     __shared__ float arena[kArenaFloats];
-    // entry = key << 32 | offset, read and written as one 64-bit word; the
-    // low word is an arena offset, kPending while its owner reserves space,
-    // or kNoRoom; kFree marks an unclaimed entry
     __shared__ uint64_t entry[kTiles];
     __shared__ int32_t used;
-    constexpr uint64_t kFree = ~0ull;
-    constexpr uint32_t kPending = 0xfffffffeu, kNoRoom = 0xfffffffdu;
+    // dense blocks: per-cell counts, then offsets; the binned query order
+    __shared__ int32_t cell_ofs[kDenseCells];
+    __shared__ int32_t part[kBlock];
+    __shared__ uint16_t order[kBwdChunk];
+    __shared__ int32_t dense_h, nbinned, own_base;
     for (int i = threadIdx.x; i < kArenaFloats; i += kBlock) arena[i] = 0.0f;
     if (threadIdx.x < kTiles) entry[threadIdx.x] = kFree;
-    if (threadIdx.x == 0) used = 0;
-    __syncthreads();
     const int64_t q0 = (int64_t)blockIdx.x * kBwdChunk;
+    if (threadIdx.x == 0) {
+        used = 0;
+        dense_h = -1;
+        if constexpr (!TRI) {
+            // bilinear, and the block's first and last queries on one
+            // halfedge with a small texture: bin by tap cell
+            const int64_t ql = (q0 + kBwdChunk < a.Q ? q0 + kBwdChunk : a.Q) - 1;
+            const int32_t hf = a.qh[q0], hl = a.qh[ql];
+            if (hf == hl && (uint32_t)hf < (uint32_t)a.H && a.log2res[a.edge[hf]] <= kDenseMaxLog2)
+                dense_h = hf;
+        }
+    }
+    __syncthreads();
+    const TileTable T{arena, entry, &used};
     // the last tile each of a lane's six (fetch, level) slots resolved: a
     // lane's consecutive queries are usually on the same halfedge
     int32_t memo_key[3][2], memo_base[3][2];
 #pragma unroll
     for (int s = 0; s < 3; ++s)
         for (int sl = 0; sl < 2; ++sl) memo_key[s][sl] = -1;
-    for (int r = 0; r < kBwdPerThread; ++r) {
-        const int64_t q = q0 + (int64_t)r * kBlock + threadIdx.x;
-        if (q >= a.Q) break;
-        const int32_t h = a.qh[q];
-        const float u = a.qu[q], v = a.qv[q];
-        if (!((uint32_t)h < (uint32_t)a.H) || !isfinite(u) || !isfinite(v)) continue;
-        const int32_t n1 = a.next[h], p1 = a.prev[h];
-        Lod L{0, 0, 0.0f, 1.0f};
-        if constexpr (TRI) L = lod_of(a.qf[q]);
-        FetchSpec fs[3];
-        fetch_specs(h, n1, p1, u, v, fs);
-        int32_t es[3], ks[3];
-        bool flips[3];
-        float W = 0.0f;
+    LevelPlan own;
+    float own_rw;
+    float4 own_g;
+    const int32_t hb = dense_h;
+    if (TRI || hb < 0) {
+        for (int r = 0; r < kBwdPerThread; ++r) {
+            const int64_t q = q0 + (int64_t)r * kBlock + threadIdx.x;
+            if (q >= a.Q) break;
+            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, false, own, own_rw, own_g);
+        }
+    } else {
+        // 1. the own fetch's tap cell of each query on halfedge hb
+        const int32_t e0 = a.edge[hb];
+        const int k0 = a.log2res[e0];
+        const bool flip0 = !(hb > a.twin[hb]);
+        for (int i = threadIdx.x; i < kDenseCells; i += kBlock) cell_ofs[i] = 0;
+        if (threadIdx.x == 0) own_base = find_tile(T, e0 * 16, (int64_t)CH << (2 * k0));
+        __syncthreads();
+        int32_t cell[kBwdPerThread];
 #pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            const int32_t g = fs[s].g;
-            flips[s] = !(g > a.twin[g]);
-            es[s] = a.edge[g];
-            ks[s] = a.log2res[es[s]];
-            int lv[2];
-            float om[2];
-            const int nlev = fetch_levels(L, ks[s], lv, om);
-            for (int sl = 0; sl < nlev; ++sl) {
-                const LevelPlan p = plan_level(ks[s], lv[sl], om[sl], fs[s], flips[s]);
-                W += (p.wx0 + p.wx1) * (p.wy0 + p.wy1);
+        for (int r = 0; r < kBwdPerThread; ++r) {
+            const int64_t q = q0 + (int64_t)r * kBlock + threadIdx.x;
+            cell[r] = -2;   // no query
+            if (q >= a.Q) continue;
+            cell[r] = -1;   // per-query path
+            const int32_t h = a.qh[q];
+            const float u = a.qu[q], v = a.qv[q];
+            if (h != hb || !isfinite(u) || !isfinite(v)) continue;
+            const FetchSpec f0 = {h, u, v, false, false};
+            const LevelPlan p = plan_level(k0, 0, 1.0f, f0, flip0);
+            const int32_t n = 1 << k0;
+            if (p.i0 < -1 || p.i0 > n - 1 || p.j0 < -1 || p.j0 > n - 1) continue;
+            cell[r] = (p.j0 + 1) * kDenseSide + (p.i0 + 1);
+            atomicAdd(&cell_ofs[cell[r]], 1);
+        }
+        __syncthreads();
+        // 2. exclusive offsets: per-thread sums, one wavefront scans them
+        int32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < kCellsPerThread; ++j) {
+            const int c = threadIdx.x * kCellsPerThread + j;
+            if (c < kDenseCells) sum += cell_ofs[c];
+        }
+        part[threadIdx.x] = sum;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int l = threadIdx.x;
+            const int32_t v0 = part[4 * l], v1 = part[4 * l + 1], v2 = part[4 * l + 2],
+                          v3 = part[4 * l + 3];
+            const int32_t tot = v0 + v1 + v2 + v3;
+            int32_t inc = tot;
+            for (int d = 1; d < 64; d <<= 1) {
+                const int32_t y = __shfl_up(inc, d);
+                if (l >= d) inc += y;
+            }
+            const int32_t ex = inc - tot;
+            part[4 * l] = ex;
+            part[4 * l + 1] = ex + v0;
+            part[4 * l + 2] = ex + v0 + v1;
+            part[4 * l + 3] = ex + v0 + v1 + v2;
+            if (l == 63) nbinned = inc;
+        }
+        __syncthreads();
+        int32_t run = part[threadIdx.x];
+#pragma unroll
+        for (int j = 0; j < kCellsPerThread; ++j) {
+            const int c = threadIdx.x * kCellsPerThread + j;
+            if (c < kDenseCells) {
+                const int32_t cnt = cell_ofs[c];
+                cell_ofs[c] = run;
+                run += cnt;
             }
         }
-        const float4 g4 = load_row<CH>(a.dout, q);
-        const float rW = 1.0f / W;
+        __syncthreads();
+        // 3. the binned order
 #pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            int lv[2];
-            float om[2];
-            const int nlev = fetch_levels(L, ks[s], lv, om);
-            const int64_t eb = a.base[es[s]];
+        for (int r = 0; r < kBwdPerThread; ++r)
+            if (cell[r] >= 0) order[atomicAdd(&cell_ofs[cell[r]], 1)] =
+                                  (uint16_t)(r * kBlock + threadIdx.x);
+        __syncthreads();
+        // 4. runs of binned queries, kBwdPerThread consecutive entries per
+        // thread; contributions of one cell are summed before being added
+        const int i0 = threadIdx.x * kBwdPerThread;
+        const int i1 = i0 + kBwdPerThread < nbinned ? i0 + kBwdPerThread : nbinned;
+        const int64_t eb0 = a.base[e0];
+        int32_t cur = -1;
+        LevelPlan cp;
+        float4 acc[4];
+        auto flush = [&]() {
+            if (cur < 0) return;
+            const uint32_t off[4] = {cp.o00, cp.o01, cp.o10, cp.o11};
 #pragma unroll
-            for (int sl = 0; sl < 2; ++sl) {
-                if (sl >= nlev) break;
-                const LevelPlan p = plan_level(ks[s], lv[sl], om[sl], fs[s], flips[s]);
-                if (!p.act) continue;
-                const int m = ks[s] - lv[sl];
-                const uint32_t lo = level_offset32(ks[s], lv[sl]);
-                // the tile of this (edge, level): remembered, found, or claimed
-                const int32_t key = es[s] * 16 + lv[sl];
-                // floats of this level's tile (computed in 64 bits: a level of
-                // 2^15 x 2^15 RGBA texels needs 2^32 floats; it never fits)
-                const int64_t need = (int64_t)CH << (2 * m);
-                int32_t base_f = -1;
-                const uint32_t h0 = ((uint32_t)key * 2654435761u) >> 27;   // 5 bits
-                if (memo_key[s][sl] == key) base_f = memo_base[s][sl];
-                else for (int pr = 0; pr < kTiles; ++pr) {
-                    const int t = (int)((h0 + pr) & (kTiles - 1));
-                    uint64_t en = __atomic_load_n(&entry[t], __ATOMIC_RELAXED);
-                    if (en == kFree) {
-                        const uint64_t mine = ((uint64_t)(uint32_t)key << 32) | kPending;
-                        en = atomicCAS(&entry[t], kFree, mine);
-                        if (en == kFree) {   // claimed: reserve the level's texels
-                            const int32_t o = need <= kArenaFloats
-                                                  ? atomicAdd(&used, (int32_t)need)
-                                                  : kArenaFloats;
-                            const bool fits = o + need <= kArenaFloats;
-                            atomicExch(&entry[t], ((uint64_t)(uint32_t)key << 32) |
-                                                      (fits ? (uint32_t)o : kNoRoom));
-                            if (fits) base_f = o;
-                            break;
-                        }
-                    }
-                    if ((uint32_t)(en >> 32) == (uint32_t)key) {
-                        const uint32_t lo32 = (uint32_t)(en & 0xffffffffu);
-                        if (lo32 < (uint32_t)kArenaFloats) base_f = (int32_t)lo32;
-                        break;   // pending or no room: global atomics
-                    }
-                }
-                if (base_f >= 0) {
-                    memo_key[s][sl] = key;
-                    memo_base[s][sl] = base_f;
-                }
-                const float w[4] = {p.wx0 * p.wy0, p.wx1 * p.wy0, p.wx0 * p.wy1, p.wx1 * p.wy1};
-                const uint32_t off[4] = {p.o00, p.o01, p.o10, p.o11};
+            for (int t = 0; t < 4; ++t)
+                if ((cp.mask >> t) & 1)
+                    add_tap<CH>(arena, own_base, off[t], a.dtex + CH * (eb0 + off[t]), acc[t]);
+        };
+        for (int i = i0; i < i1; ++i) {
+            const int64_t q = q0 + order[i];
+            scatter_query<CH, false>(a, q, T, memo_key, memo_base, true, own, own_rw, own_g);
+            const int32_t c = (own.j0 + 1) * kDenseSide + (own.i0 + 1);
+            if (c != cur) {
+                flush();
+                cur = c;
+                cp = own;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    if (!((p.mask >> t) & 1)) continue;
-                    const float wt = w[t] * rW;
-                    if (base_f >= 0) {
-                        float *c = &arena[base_f + CH * (int32_t)(off[t] - lo)];
-                        atomicAdd(c + 0, wt * g4.x);
-                        if constexpr (CH == 4) {
-                            atomicAdd(c + 1, wt * g4.y);
-                            atomicAdd(c + 2, wt * g4.z);
-                            atomicAdd(c + 3, wt * g4.w);
-                        }
-                    } else {
-                        float *pg = a.dtex + CH * (eb + off[t]);
-                        unsafeAtomicAdd(pg + 0, wt * g4.x);
-                        if constexpr (CH == 4) {
-                            unsafeAtomicAdd(pg + 1, wt * g4.y);
-                            unsafeAtomicAdd(pg + 2, wt * g4.z);
-                            unsafeAtomicAdd(pg + 3, wt * g4.w);
-                        }
-                    }
-                }
+                for (int t = 0; t < 4; ++t) acc[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            const float w[4] = {own.wx0 * own.wy0, own.wx1 * own.wy0, own.wx0 * own.wy1,
+                                own.wx1 * own.wy1};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float wt = w[t] * own_rw;
+                acc[t].x += wt * own_g.x;
+                acc[t].y += wt * own_g.y;
+                acc[t].z += wt * own_g.z;
+                acc[t].w += wt * own_g.w;
             }
         }
+        flush();
+        // the queries left to the per-query path
+#pragma unroll
+        for (int r = 0; r < kBwdPerThread; ++r)
+            if (cell[r] == -1)
+                scatter_query<CH, false>(a, q0 + (int64_t)r * kBlock + threadIdx.x, T, memo_key,
+                                         memo_base, false, own, own_rw, own_g);
     }
     __syncthreads();
     // flush the tiles
