@@ -100,23 +100,40 @@ __global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
 // levels per block, which is why tiles are sized per level.
 //
 // Dense blocks.  LDS float atomics cost about as much as the rest of the
-// kernel, while LDS integer atomics are cheap.  When a bilinear block's
-// queries all lie on one halfedge whose texture has at most 32 x 32 texels
+// kernel, while LDS integer atomics are cheap.  When a block's first and
+// last queries lie on one halfedge whose texture has at most 32 x 32 texels
 // (many samples per texel, as when fitting a texture), the block first bins
-// its queries by the tap cell (i0, j0) of their own fetch, counting with
-// integer atomics, and each thread then walks a run of binned queries:
-// consecutive queries of one cell share their four target texels, so their
-// contributions are summed in registers and added to the tile once per
-// run.  Queries on other halfedges, or whose taps fall outside the cell
-// range, take the per-query path.
+// its queries by the level and tap cell (i0, j0) of their own fetch's finer
+// level, counting with integer atomics, and each thread then walks a run of
+// binned queries: consecutive queries of one cell share their four target
+// texels, so their contributions are summed in registers and added to the
+// tile once per run (the coarser level of a trilinear fetch keeps a run of
+// its own).  Queries on other halfedges, or whose taps fall outside the
+// cell range, take the per-query path.
 constexpr int kTiles = 32;
 constexpr int kArenaFloats = 16384;   // 64 KB
 constexpr int kBwdPerThread = 16;
 constexpr int kBwdChunk = kBlock * kBwdPerThread;
 constexpr int kDenseMaxLog2 = 5;
-constexpr int kDenseSide = (1 << kDenseMaxLog2) + 1;   // tap bases -1 .. n - 1 per axis
-constexpr int kDenseCells = kDenseSide * kDenseSide;
+// tap cells: bases -1 .. n - 1 per axis on every level of a texture of up to
+// 2^kDenseMaxLog2 texels a side, level after level
+__host__ __device__ constexpr int dense_cells_before(int k, int l)
+{
+    int c = 0;
+    for (int m = 0; m < l; ++m) c += ((1 << (k - m)) + 1) * ((1 << (k - m)) + 1);
+    return c;
+}
+constexpr int kDenseCells = dense_cells_before(kDenseMaxLog2, kDenseMaxLog2 + 1);
 constexpr int kCellsPerThread = (kDenseCells + kBlock - 1) / kBlock;
+
+// Cell key of a level plan on level l of a texture of log2 size k, or -1
+// when its tap bases fall outside -1 .. n - 1.
+__device__ __forceinline__ int32_t dense_cell(int k, int l, const LevelPlan &p)
+{
+    const int32_t n = 1 << (k - l);
+    if (p.i0 < -1 || p.i0 > n - 1 || p.j0 < -1 || p.j0 > n - 1) return -1;
+    return dense_cells_before(k, l) + (p.j0 + 1) * (n + 1) + (p.i0 + 1);
+}
 static_assert(kBwdChunk <= 65536, "binned query indices are 16-bit");
 
 constexpr uint64_t kFree = ~0ull;
@@ -183,14 +200,21 @@ __device__ __forceinline__ void add_tap(float *arena, int32_t base_f, uint32_t r
 
 // The transpose of Alg. 3 for query q: every in-bounds tap of every fetch
 // and level receives (om w / W) dL/dout.  With `own_run`, the own fetch's
-// level-0 taps are not added but handed back (its plan, 1 / W and
+// taps are not added but handed back (its levels and their plans, 1 / W and
 // dL/dout) for the caller to accumulate.  Returns false for an invalid
 // query.
+struct OwnFetch {
+    int nlev;
+    int lv[2];
+    LevelPlan p[2];
+    float rw;      // 1 / W
+    float4 g;      // dL/dout
+};
+
 template <int CH, bool TRI>
 __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, const TileTable &T,
                                               int32_t (&memo_key)[3][2], int32_t (&memo_base)[3][2],
-                                              bool own_run, LevelPlan &own, float &own_rw,
-                                              float4 &own_g)
+                                              bool own_run, OwnFetch &own)
 {
     const int32_t h = a.qh[q];
     const float u = a.qu[q], v = a.qv[q];
@@ -229,8 +253,10 @@ __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, co
         for (int sl = 0; sl < 2; ++sl) {
             if (sl >= nlev) break;
             const LevelPlan p = plan_level(ks[s], lv[sl], om[sl], fs[s], flips[s]);
-            if (!TRI && own_run && s == 0) {
-                own = p;
+            if (own_run && s == 0) {
+                own.nlev = nlev;
+                own.lv[sl] = lv[sl];
+                own.p[sl] = p;
                 continue;
             }
             if (!p.act) continue;
@@ -257,8 +283,8 @@ __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, co
             }
         }
     }
-    own_rw = rW;
-    own_g = g4;
+    own.rw = rW;
+    own.g = g4;
     return true;
 }
 
@@ -268,25 +294,24 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
     __shared__ float arena[kArenaFloats];
     __shared__ uint64_t entry[kTiles];
     __shared__ int32_t used;
-    // dense blocks: per-cell counts, then offsets; the binned query order
+    // dense blocks: per-cell counts, then offsets; the binned query order;
+    // the tile of each level of the block's own texture
     __shared__ int32_t cell_ofs[kDenseCells];
     __shared__ int32_t part[kBlock];
     __shared__ uint16_t order[kBwdChunk];
-    __shared__ int32_t dense_h, nbinned, own_base;
+    __shared__ int32_t own_base[kDenseMaxLog2 + 1];
+    __shared__ int32_t dense_h, nbinned;
     for (int i = threadIdx.x; i < kArenaFloats; i += kBlock) arena[i] = 0.0f;
     if (threadIdx.x < kTiles) entry[threadIdx.x] = kFree;
     const int64_t q0 = (int64_t)blockIdx.x * kBwdChunk;
     if (threadIdx.x == 0) {
         used = 0;
-        dense_h = -1;
-        if constexpr (!TRI) {
-            // bilinear, and the block's first and last queries on one
-            // halfedge with a small texture: bin by tap cell
-            const int64_t ql = (q0 + kBwdChunk < a.Q ? q0 + kBwdChunk : a.Q) - 1;
-            const int32_t hf = a.qh[q0], hl = a.qh[ql];
-            if (hf == hl && (uint32_t)hf < (uint32_t)a.H && a.log2res[a.edge[hf]] <= kDenseMaxLog2)
-                dense_h = hf;
-        }
+        // the block's first and last queries on one halfedge whose texture
+        // is small: bin by tap cell
+        const int64_t ql = (q0 + kBwdChunk < a.Q ? q0 + kBwdChunk : a.Q) - 1;
+        const int32_t hf = a.qh[q0], hl = a.qh[ql];
+        dense_h = (hf == hl && (uint32_t)hf < (uint32_t)a.H &&
+                   a.log2res[a.edge[hf]] <= kDenseMaxLog2) ? hf : -1;
     }
     __syncthreads();
     const TileTable T{arena, entry, &used};
@@ -296,23 +321,23 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
 #pragma unroll
     for (int s = 0; s < 3; ++s)
         for (int sl = 0; sl < 2; ++sl) memo_key[s][sl] = -1;
-    LevelPlan own;
-    float own_rw;
-    float4 own_g;
+    OwnFetch own;
     const int32_t hb = dense_h;
-    if (TRI || hb < 0) {
+    if (hb < 0) {
         for (int r = 0; r < kBwdPerThread; ++r) {
             const int64_t q = q0 + (int64_t)r * kBlock + threadIdx.x;
             if (q >= a.Q) break;
-            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, false, own, own_rw, own_g);
+            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, false, own);
         }
     } else {
-        // 1. the own fetch's tap cell of each query on halfedge hb
+        // 1. the tap cell of each query's own fetch on its finer level
         const int32_t e0 = a.edge[hb];
         const int k0 = a.log2res[e0];
         const bool flip0 = !(hb > a.twin[hb]);
         for (int i = threadIdx.x; i < kDenseCells; i += kBlock) cell_ofs[i] = 0;
-        if (threadIdx.x == 0) own_base = find_tile(T, e0 * 16, (int64_t)CH << (2 * k0));
+        if (threadIdx.x <= (TRI ? k0 : 0))
+            own_base[threadIdx.x] = find_tile(T, e0 * 16 + (int)threadIdx.x,
+                                              (int64_t)CH << (2 * (k0 - (int)threadIdx.x)));
         __syncthreads();
         int32_t cell[kBwdPerThread];
 #pragma unroll
@@ -324,12 +349,16 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
             const int32_t h = a.qh[q];
             const float u = a.qu[q], v = a.qv[q];
             if (h != hb || !isfinite(u) || !isfinite(v)) continue;
+            Lod L{0, 0, 0.0f, 1.0f};
+            if constexpr (TRI) L = lod_of(a.qf[q]);
+            int lv[2];
+            float om[2];
+            fetch_levels(L, k0, lv, om);
             const FetchSpec f0 = {h, u, v, false, false};
-            const LevelPlan p = plan_level(k0, 0, 1.0f, f0, flip0);
-            const int32_t n = 1 << k0;
-            if (p.i0 < -1 || p.i0 > n - 1 || p.j0 < -1 || p.j0 > n - 1) continue;
-            cell[r] = (p.j0 + 1) * kDenseSide + (p.i0 + 1);
-            atomicAdd(&cell_ofs[cell[r]], 1);
+            const int32_t c = dense_cell(k0, lv[0], plan_level(k0, lv[0], om[0], f0, flip0));
+            if (c < 0) continue;
+            cell[r] = c;
+            atomicAdd(&cell_ofs[c], 1);
         }
         __syncthreads();
         // 2. exclusive offsets: per-thread sums, one wavefront scans them
@@ -377,50 +406,83 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
                                   (uint16_t)(r * kBlock + threadIdx.x);
         __syncthreads();
         // 4. runs of binned queries, kBwdPerThread consecutive entries per
-        // thread; contributions of one cell are summed before being added
+        // thread.  Queries of one cell share the four texels of their finer
+        // level, so those contributions are summed over the run; the coarser
+        // level's cell changes less often than the query does and gets a
+        // run of its own.
         const int i0 = threadIdx.x * kBwdPerThread;
         const int i1 = i0 + kBwdPerThread < nbinned ? i0 + kBwdPerThread : nbinned;
         const int64_t eb0 = a.base[e0];
-        int32_t cur = -1;
-        LevelPlan cp;
-        float4 acc[4];
-        auto flush = [&]() {
-            if (cur < 0) return;
-            const uint32_t off[4] = {cp.o00, cp.o01, cp.o10, cp.o11};
+        int32_t cur[2] = {-1, -1};
+        int curl[2] = {0, 0};
+        LevelPlan cp[2];
+        float4 acc[2][4];
+        auto flush = [&](int j) {
+            if (cur[j] < 0) return;
+            const uint32_t off[4] = {cp[j].o00, cp[j].o01, cp[j].o10, cp[j].o11};
+            const uint32_t lo = level_offset32(k0, curl[j]);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
-                if ((cp.mask >> t) & 1)
-                    add_tap<CH>(arena, own_base, off[t], a.dtex + CH * (eb0 + off[t]), acc[t]);
+                if ((cp[j].mask >> t) & 1)
+                    add_tap<CH>(arena, own_base[curl[j]], off[t] - lo,
+                                a.dtex + CH * (eb0 + off[t]), acc[j][t]);
         };
         for (int i = i0; i < i1; ++i) {
             const int64_t q = q0 + order[i];
-            scatter_query<CH, false>(a, q, T, memo_key, memo_base, true, own, own_rw, own_g);
-            const int32_t c = (own.j0 + 1) * kDenseSide + (own.i0 + 1);
-            if (c != cur) {
-                flush();
-                cur = c;
-                cp = own;
+            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, true, own);
+            for (int j = 0; j < 2; ++j) {
+                if (j >= own.nlev || !own.p[j].act) continue;
+                const int32_t c = dense_cell(k0, own.lv[j], own.p[j]);
+                if (c < 0) {
+                    // a coarser level's taps outside the cell range (only
+                    // when the finer level's cell sits at its range's edge):
+                    // added directly
+                    const LevelPlan &p = own.p[j];
+                    const float w[4] = {p.wx0 * p.wy0, p.wx1 * p.wy0, p.wx0 * p.wy1,
+                                        p.wx1 * p.wy1};
+                    const uint32_t off[4] = {p.o00, p.o01, p.o10, p.o11};
+                    const uint32_t lo = level_offset32(k0, own.lv[j]);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) acc[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-            const float w[4] = {own.wx0 * own.wy0, own.wx1 * own.wy0, own.wx0 * own.wy1,
-                                own.wx1 * own.wy1};
+                    for (int t = 0; t < 4; ++t) {
+                        if (!((p.mask >> t) & 1)) continue;
+                        const float wt = w[t] * own.rw;
+                        add_tap<CH>(arena, own_base[own.lv[j]], off[t] - lo,
+                                    a.dtex + CH * (eb0 + off[t]),
+                                    make_float4(wt * own.g.x, wt * own.g.y, wt * own.g.z,
+                                                wt * own.g.w));
+                    }
+                    continue;
+                }
+                if (c != cur[j]) {
+                    flush(j);
+                    cur[j] = c;
+                    curl[j] = own.lv[j];
+                    cp[j] = own.p[j];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const float wt = w[t] * own_rw;
-                acc[t].x += wt * own_g.x;
-                acc[t].y += wt * own_g.y;
-                acc[t].z += wt * own_g.z;
-                acc[t].w += wt * own_g.w;
+                    for (int t = 0; t < 4; ++t) acc[j][t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                const LevelPlan &p = own.p[j];
+                const float w[4] = {p.wx0 * p.wy0, p.wx1 * p.wy0, p.wx0 * p.wy1, p.wx1 * p.wy1};
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float wt = w[t] * own.rw;
+                    acc[j][t].x += wt * own.g.x;
+                    acc[j][t].y += wt * own.g.y;
+                    acc[j][t].z += wt * own.g.z;
+                    acc[j][t].w += wt * own.g.w;
+                }
             }
         }
-        flush();
+        flush(0);
+        flush(1);
         // the queries left to the per-query path
+        uint32_t rest = 0;
 #pragma unroll
         for (int r = 0; r < kBwdPerThread; ++r)
-            if (cell[r] == -1)
-                scatter_query<CH, false>(a, q0 + (int64_t)r * kBlock + threadIdx.x, T, memo_key,
-                                         memo_base, false, own, own_rw, own_g);
+            if (cell[r] == -1) rest |= 1u << r;
+        for (; rest; rest &= rest - 1)
+            scatter_query<CH, TRI>(a, q0 + (int64_t)__builtin_ctz(rest) * kBlock + threadIdx.x, T,
+                                   memo_key, memo_base, false, own);
     }
     __syncthreads();
     // flush the tiles

@@ -514,21 +514,22 @@ def test_backward_sorted_flag_is_only_a_hint():
 
 @pytest.mark.parametrize("channels", [4, 1])
 @pytest.mark.parametrize("k", [0, 3, 5, 6])
-def test_backward_dense_blocks(channels, k):
+@pytest.mark.parametrize("tri", [False, True])
+def test_backward_dense_blocks(channels, k, tri):
     """Blocks of 4096 queries on one halfedge take the binned scatter (runs of
-    queries with one tap cell summed before they are added) when the
-    texture has at most 32 x 32 texels (k <= 5), the per-query scatter
-    otherwise.  The batch mixes in what must leave the binned path: queries
+    queries with one tap cell summed before they are added; trilinear
+    fetches keep a second run for their coarser level) when the texture has
+    at most 32 x 32 texels (k <= 5), the per-query scatter otherwise.  The batch mixes in what must leave the binned path: queries
     on other halfedges, invalid h, NaN u, coordinates outside the quad
     (tap cells outside the binned range), and one block whose first and
     last queries share a halfedge while its middle does not (a batch
     wrongly flagged sorted).  Against the oracle within 1e-4 of
     sum |contributions|, and against the plain-atomic path."""
     m = cube_mesh()
-    s = Setup(m, np.full(m.E, k), has_mips=False, kind=1, seed=91, channels=channels)
+    s = Setup(m, np.full(m.E, k), has_mips=tri, kind=1, seed=91, channels=channels)
     rng = np.random.default_rng(92)
     Q = 4096 * 5 + 777
-    q = uniform_queries(m.H, Q, 93)
+    q = uniform_queries(m.H, Q, 93, log2f=(-9.0, 1.0) if tri else None)
     q.h[:] = np.repeat(np.array([3, 3, 17, 17, 40, 40], np.int32), Q // 6 + 1)[:Q]
     odd = rng.choice(Q, 300, replace=False)
     q.h[odd[:100]] = rng.integers(0, m.H, 100)
@@ -541,11 +542,13 @@ def test_backward_dense_blocks(channels, k):
     q.h[b3] = rng.integers(0, m.H, 4096)
     q.h[3 * 4096] = q.h[4 * 4096 - 1] = 5
     g = rng.standard_normal((Q, channels)).astype(np.float32)
-    ref, dabs = oracle.backward(s.omesh, s.opool, q.h, q.u, q.v, g.astype(np.float64),
-                                with_abs=True)
+    filt, ofilt = ((htex.HTEX_TRILINEAR, oracle.TRILINEAR) if tri
+                   else (htex.HTEX_BILINEAR, oracle.BILINEAR))
+    ref, dabs = oracle.backward(s.omesh, s.opool, q.h, q.u, q.v, g.astype(np.float64), q.f,
+                                filter=ofilt, with_abs=True)
     for flags in (htex.HTEX_QUERIES_SORTED, 0):
         d = htex.htex_sample_backward(s.dmesh, s.pool, t(q.h), t(q.u), t(q.v), t(g),
-                                      flags=flags)
+                                      t(q.f) if tri else None, filter=filt, flags=flags)
         torch.cuda.synchronize()
         got = d.cpu().numpy().astype(np.float64).reshape(ref.shape)
         err = np.abs(got - ref)
