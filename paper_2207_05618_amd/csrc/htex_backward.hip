@@ -100,8 +100,8 @@ __global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
 // levels per block, which is why tiles are sized per level.
 //
 // Dense blocks.  LDS float atomics cost about as much as the rest of the
-// kernel, while LDS integer atomics are cheap.  When a block's first and
-// last queries lie on one halfedge whose texture has at most 32 x 32 texels
+// kernel, while LDS integer atomics are cheap.  When most of a block's
+// queries lie on one halfedge whose texture has at most 32 x 32 texels
 // (many samples per texel, as when fitting a texture), the block first bins
 // its queries by the level and tap cell (i0, j0) of their own fetch's finer
 // level, counting with integer atomics, and each thread then walks a run of
@@ -306,12 +306,14 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
     const int64_t q0 = (int64_t)blockIdx.x * kBwdChunk;
     if (threadIdx.x == 0) {
         used = 0;
-        // the block's first and last queries on one halfedge whose texture
-        // is small: bin by tap cell
+        // bin by tap cell when the block's middle query shares its
+        // halfedge with the first or the last (in a sorted batch that
+        // halfedge then holds at least half of the block) and its texture
+        // is small
         const int64_t ql = (q0 + kBwdChunk < a.Q ? q0 + kBwdChunk : a.Q) - 1;
-        const int32_t hf = a.qh[q0], hl = a.qh[ql];
-        dense_h = (hf == hl && (uint32_t)hf < (uint32_t)a.H &&
-                   a.log2res[a.edge[hf]] <= kDenseMaxLog2) ? hf : -1;
+        const int32_t hf = a.qh[q0], hm = a.qh[q0 + (ql - q0) / 2], hl = a.qh[ql];
+        dense_h = ((hm == hf || hm == hl) && (uint32_t)hm < (uint32_t)a.H &&
+                   a.log2res[a.edge[hm]] <= kDenseMaxLog2) ? hm : -1;
     }
     __syncthreads();
     const TileTable T{arena, entry, &used};

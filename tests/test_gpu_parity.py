@@ -521,9 +521,9 @@ def test_backward_dense_blocks(channels, k, tri):
     fetches keep a second run for their coarser level) when the texture has
     at most 32 x 32 texels (k <= 5), the per-query scatter otherwise.  The batch mixes in what must leave the binned path: queries
     on other halfedges, invalid h, NaN u, coordinates outside the quad
-    (tap cells outside the binned range), and one block whose first and
-    last queries share a halfedge while its middle does not (a batch
-    wrongly flagged sorted).  Against the oracle within 1e-4 of
+    (tap cells outside the binned range), and one block whose first half
+    shares a halfedge while its second half does not (a batch wrongly
+    flagged sorted).  Against the oracle within 1e-4 of
     sum |contributions|, and against the plain-atomic path."""
     m = cube_mesh()
     s = Setup(m, np.full(m.E, k), has_mips=tri, kind=1, seed=91, channels=channels)
@@ -537,10 +537,11 @@ def test_backward_dense_blocks(channels, k, tri):
     q.u[odd[110:120]] = np.nan
     q.u[odd[120:160]] = rng.uniform(1.0, 2.5, 40).astype(np.float32)
     q.v[odd[160:200]] = rng.uniform(-1.5, -0.01, 40).astype(np.float32)
-    # block 3: first and last queries on halfedge 5, the middle on others
+    # block 3: its first half (the middle query included) on halfedge 5, its
+    # second half on random halfedges (a batch wrongly flagged sorted)
     b3 = slice(3 * 4096, 4 * 4096)
     q.h[b3] = rng.integers(0, m.H, 4096)
-    q.h[3 * 4096] = q.h[4 * 4096 - 1] = 5
+    q.h[3 * 4096:3 * 4096 + 2049] = 5
     g = rng.standard_normal((Q, channels)).astype(np.float32)
     filt, ofilt = ((htex.HTEX_TRILINEAR, oracle.TRILINEAR) if tri
                    else (htex.HTEX_BILINEAR, oracle.BILINEAR))
