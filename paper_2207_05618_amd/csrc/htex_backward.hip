@@ -211,28 +211,52 @@ struct OwnFetch {
     float4 g;      // dL/dout
 };
 
+// The navigation of one halfedge's three fetches: their edges, log2
+// resolutions, reflections and texel bases.
+struct Topo {
+    int32_t n1, p1;
+    int32_t es[3], ks[3];
+    bool flips[3];
+    int64_t ebs[3];
+};
+
+__device__ __forceinline__ Topo topo_of(const SampleArgs &a, int32_t h)
+{
+    Topo t;
+    t.n1 = a.next[h];
+    t.p1 = a.prev[h];
+    const int32_t g[3] = {h, t.n1, t.p1};
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        t.flips[s] = !(g[s] > a.twin[g[s]]);
+        t.es[s] = a.edge[g[s]];
+        t.ks[s] = a.log2res[t.es[s]];
+        t.ebs[s] = a.base[t.es[s]];
+    }
+    return t;
+}
+
+// `known` (nullable): the navigation of the query's halfedge, when the
+// caller already has it (every binned query of a dense block shares it).
 template <int CH, bool TRI>
 __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, const TileTable &T,
                                               int32_t (&memo_key)[3][2], int32_t (&memo_base)[3][2],
-                                              bool own_run, OwnFetch &own)
+                                              bool own_run, OwnFetch &own, int32_t hk,
+                                              const Topo *known)
 {
-    const int32_t h = a.qh[q];
+    const int32_t h = known ? hk : a.qh[q];
     const float u = a.qu[q], v = a.qv[q];
     if (!((uint32_t)h < (uint32_t)a.H) || !isfinite(u) || !isfinite(v)) return false;
-    const int32_t n1 = a.next[h], p1 = a.prev[h];
+    const Topo tp = known ? *known : topo_of(a, h);
     Lod L{0, 0, 0.0f, 1.0f};
     if constexpr (TRI) L = lod_of(a.qf[q]);
     FetchSpec fs[3];
-    fetch_specs(h, n1, p1, u, v, fs);
-    int32_t es[3], ks[3];
-    bool flips[3];
+    fetch_specs(h, tp.n1, tp.p1, u, v, fs);
+    const int32_t *es = tp.es, *ks = tp.ks;
+    const bool *flips = tp.flips;
     float W = 0.0f;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-        const int32_t g = fs[s].g;
-        flips[s] = !(g > a.twin[g]);
-        es[s] = a.edge[g];
-        ks[s] = a.log2res[es[s]];
         int lv[2];
         float om[2];
         const int nlev = fetch_levels(L, ks[s], lv, om);
@@ -248,7 +272,7 @@ __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, co
         int lv[2];
         float om[2];
         const int nlev = fetch_levels(L, ks[s], lv, om);
-        const int64_t eb = a.base[es[s]];
+        const int64_t eb = tp.ebs[s];
 #pragma unroll
         for (int sl = 0; sl < 2; ++sl) {
             if (sl >= nlev) break;
@@ -329,7 +353,7 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
         for (int r = 0; r < kBwdPerThread; ++r) {
             const int64_t q = q0 + (int64_t)r * kBlock + threadIdx.x;
             if (q >= a.Q) break;
-            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, false, own);
+            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, false, own, 0, nullptr);
         }
     } else {
         // 1. the tap cell of each query's own fetch on its finer level
@@ -429,9 +453,10 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
                     add_tap<CH>(arena, own_base[curl[j]], off[t] - lo,
                                 a.dtex + CH * (eb0 + off[t]), acc[j][t]);
         };
+        const Topo tb = topo_of(a, hb);
         for (int i = i0; i < i1; ++i) {
             const int64_t q = q0 + order[i];
-            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, true, own);
+            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, true, own, hb, &tb);
             for (int j = 0; j < 2; ++j) {
                 if (j >= own.nlev || !own.p[j].act) continue;
                 const int32_t c = dense_cell(k0, own.lv[j], own.p[j]);
@@ -484,7 +509,7 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
             if (cell[r] == -1) rest |= 1u << r;
         for (; rest; rest &= rest - 1)
             scatter_query<CH, TRI>(a, q0 + (int64_t)__builtin_ctz(rest) * kBlock + threadIdx.x, T,
-                                   memo_key, memo_base, false, own);
+                                   memo_key, memo_base, false, own, 0, nullptr);
     }
     __syncthreads();
     // flush the tiles
