@@ -348,7 +348,8 @@ htex_status htex_sample_backward(const htex_mesh *mesh, const htex_pool *pool,
     a.dtex = dtexels;
     // the LDS tile cache keys (edge, level) as edge * 16 + level in an int32
     if (mesh->E >= (1 << 27)) flags &= ~HTEX_QUERIES_SORTED;
-    return from_hip(htex::launch_backward(a, filter, flags, static_cast<hipStream_t>(stream)),
+    return from_hip(htex::launch_backward(a, filter, flags, pool->max_log2res,
+                                          static_cast<hipStream_t>(stream)),
                     "backward launch");
 }
 

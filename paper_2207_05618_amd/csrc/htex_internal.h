@@ -100,7 +100,8 @@ hipError_t launch_unpermute(const int32_t *perm, int64_t Q, const float *in, flo
 hipError_t launch_serve(const ServeMesh *meshes, const ServeTile *tiles, int32_t ntiles,
                         int32_t grid, int dtype, int channels, int filter, int32_t *err,
                         hipStream_t s);
-hipError_t launch_backward(const SampleArgs &a, int filter, uint32_t flags, hipStream_t s);
+hipError_t launch_backward(const SampleArgs &a, int filter, uint32_t flags, int max_log2res,
+                           hipStream_t s);
 hipError_t launch_prepare(const SampleArgs &a, void *prep, hipStream_t s);
 hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, bool scattered,
                                   hipStream_t s);
