@@ -250,7 +250,9 @@ def grad_benchmark(steps=200):
         return e0.elapsed_time(e1) / n / 1e3
 
     S = htex.HTEX_QUERIES_SORTED
-    t_fwd = timed(lambda: htex.htex_sample(dm, pool, h, u, v, flags=S, out=out))
+    prep = htex.Prepared(dm, pool)
+    t_fwd = timed(lambda: htex.htex_sample_prepared(prep, pool, h, u, v, flags=S, out=out))
+    t_fwd_plain = timed(lambda: htex.htex_sample(dm, pool, h, u, v, flags=S, out=out))
     t_bwd = timed(lambda: htex.htex_sample_backward(dm, pool, h, u, v, g, flags=S, dtexels=dtex))
     t_bwd_plain = timed(lambda: htex.htex_sample_backward(dm, pool, h, u, v, g, dtexels=dtex))
     tex.requires_grad_(True)
@@ -260,7 +262,8 @@ def grad_benchmark(steps=200):
     t0 = time.perf_counter()
     for it in range(steps):
         opt.zero_grad(set_to_none=False)
-        o = htex.HtexSample.apply(tex, dm, pool, h, u, v, None, htex.HTEX_BILINEAR, S)
+        o = htex.HtexSample.apply(tex, dm, pool, h, u, v, None, htex.HTEX_BILINEAR, S, False,
+                                  prep)
         loss = ((o - y) ** 2).mean()
         loss.backward()
         opt.step()
@@ -272,7 +275,8 @@ def grad_benchmark(steps=200):
     tri = grad_trilinear(m, dm, q, timed, steps)
     return {"queries": q.Q, "edges": int(m.E), "texels": int(total),
             "forward_samples_per_s": q.Q / t_fwd, "backward_samples_per_s": q.Q / t_bwd,
-            "forward_us": t_fwd * 1e6, "backward_us": t_bwd * 1e6,
+            "forward_us": t_fwd * 1e6, "forward_plain_us": t_fwd_plain * 1e6,
+            "backward_us": t_bwd * 1e6,
             "backward_plain_atomics_us": t_bwd_plain * 1e6,
             "adam_steps": steps, "adam_seconds": fit_s, "loss_first": losses[0],
             "loss_last": losses[-1], "loss_reduction": losses[0] / max(losses[-1], 1e-30),
@@ -307,7 +311,11 @@ def grad_trilinear(m, dm, q, timed, steps):
         np.float32)).cuda()
     out = torch.empty_like(y)
     dtex = torch.zeros_like(tex)
-    t_fwd = timed(lambda: htex.htex_sample(dm, pool, h, u, v, f, filter=TRI, flags=S, out=out))
+    prep = htex.Prepared(dm, pool)
+    t_fwd = timed(lambda: htex.htex_sample_prepared(prep, pool, h, u, v, f, filter=TRI, flags=S,
+                                                    out=out))
+    t_fwd_plain = timed(lambda: htex.htex_sample(dm, pool, h, u, v, f, filter=TRI, flags=S,
+                                                 out=out))
     t_bwd = timed(lambda: htex.htex_sample_backward(dm, pool, h, u, v, g, f, filter=TRI, flags=S,
                                                     dtexels=dtex))
     t_mip = timed(lambda: htex.htex_mip_backward(pool, dtex))
@@ -321,7 +329,7 @@ def grad_trilinear(m, dm, q, timed, steps):
         with torch.no_grad():
             htex.htex_build_mips(pool)
         opt.zero_grad(set_to_none=False)
-        o = htex.HtexSample.apply(tex, dm, pool, h, u, v, f, TRI, S, True)
+        o = htex.HtexSample.apply(tex, dm, pool, h, u, v, f, TRI, S, True, prep)
         loss = ((o - y) ** 2).mean()
         loss.backward()
         opt.step()
@@ -330,7 +338,8 @@ def grad_trilinear(m, dm, q, timed, steps):
     torch.cuda.synchronize()
     fit_s = time.perf_counter() - t0
     tex.requires_grad_(False)
-    return {"texels": int(total), "forward_us": t_fwd * 1e6, "backward_us": t_bwd * 1e6,
+    return {"texels": int(total), "forward_us": t_fwd * 1e6,
+            "forward_plain_us": t_fwd_plain * 1e6, "backward_us": t_bwd * 1e6,
             "mip_backward_us": t_mip * 1e6, "build_mips_us": t_mips * 1e6,
             "adam_steps": steps, "adam_seconds": fit_s, "loss_first": losses[0],
             "loss_last": losses[-1], "loss_reduction": losses[0] / max(losses[-1], 1e-30),

@@ -309,8 +309,11 @@ htex_status htex_prepare(const htex_mesh *mesh, const htex_pool *pool, void *pre
  * the kernel: by default every tap of a sampled level is read, which suits
  * coherent batches (ordered by halfedge, or rasterized, where neighbouring
  * queries share the cache lines); with the hint only in-bounds taps are
- * read, which saves line fetches when no two queries share texels.  Both
- * give the same results. */
+ * read, which saves line fetches when no two queries share texels.  Without
+ * the hint, BF16 and FP8 pools and pools of at most 256 MB (which stay in
+ * the caches, so the launch is bound by arithmetic rather than memory) take
+ * a variant that deals the Next and Prev fetches out across the
+ * wavefront.  Every kernel gives the same results. */
 htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *pool,
                                  const htex_queries *queries, int32_t filter,
                                  uint32_t flags, float *out, int32_t *err_count,

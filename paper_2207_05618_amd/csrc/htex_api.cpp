@@ -441,8 +441,12 @@ htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *p
     a.out = out;
     a.err = err_count;
     a.prep = prep;
+    // a pool that fits the 256 MB fabric-side cache leaves the sampler
+    // bound by the VALU rather than by memory
+    const bool resident = pool->total_texels * (int64_t)texel_bytes(pool->dtype, pool->channels) <=
+                          (int64_t(256) << 20);
     return from_hip(htex::launch_sample_prepared(a, pool->dtype, filter,
-                                                 (flags & HTEX_QUERIES_SCATTERED) != 0,
+                                                 (flags & HTEX_QUERIES_SCATTERED) != 0, resident,
                                                  static_cast<hipStream_t>(stream)),
                     "prepared sample launch");
 }

@@ -104,7 +104,7 @@ hipError_t launch_backward(const SampleArgs &a, int filter, uint32_t flags, int 
                            hipStream_t s);
 hipError_t launch_prepare(const SampleArgs &a, void *prep, hipStream_t s);
 hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, bool scattered,
-                                  hipStream_t s);
+                                  bool cache_resident, hipStream_t s);
 hipError_t launch_sample_aniso(const SampleArgs &a, int dtype, const float *jac, int max_aniso,
                                int32_t *nprobe, hipStream_t s);
 hipError_t launch_build_mips(float *texels, const uint8_t *log2res, const int64_t *base,

@@ -150,18 +150,18 @@ struct alignas(16) Task {
 constexpr int kTasks = 128;   // per wavefront: at most one Next and one Prev fetch per lane
 
 // The prepared fast path executed by a whole wavefront at once, for
-// BF16 and FP8 pools.  Every lane computes its own quad's fetch; the Next
-// and Prev fetches, which only queries near the spokes of their triangle
-// need, are compacted: lanes that need one are counted by ballot, write the
-// fetch's inputs to consecutive task slots in LDS, the wave works through
-// the slots 64 at a time, and each owner pulls its results back by
+// launches bound by the VALU.  Every lane computes its own quad's fetch;
+// the Next and Prev fetches, which only queries near the spokes of their
+// triangle need, are compacted: lanes that need one are counted by ballot,
+// write the fetch's inputs to consecutive task slots in LDS, the wave works
+// through the slots 64 at a time, and each owner pulls its results back by
 // ds_bpermute and adds them in Alg. 3's order (a query's Next slot always
-// precedes its Prev slot), so the results are those of
-// sample_one_prepared bit for bit.  Decoding BF16 and FP8 texels makes those
-// launches VALU-bound, and the compaction saves a tenth of their time; the
-// float32 kernel is bound by the memory pipeline, and there the compaction
-// costs 2-3%.  All 64 lanes of the wave must call it; `live` marks lanes
-// that hold a query.
+// precedes its Prev slot), so the results are those of sample_one_prepared
+// bit for bit.  Decoding BF16 and FP8 texels makes their launches
+// VALU-bound, and so does a float32 pool small enough to stay in the
+// caches; the compaction saves 6-10% there.  A large float32 pool is bound
+// by the memory pipeline, and there the compaction costs 2-3%.  All 64
+// lanes of the wave must call it; `live` marks lanes that hold a query.
 template <int DT, int CH, bool TRI>
 __device__ __forceinline__ void sample_wave_prepared(const SampleArgs &a, int64_t q, bool live,
                                                      Task *tasks)
@@ -269,17 +269,23 @@ __device__ __forceinline__ void sample_wave_prepared(const SampleArgs &a, int64_
     }
 }
 
-template <int DT, int CH, bool TRI, bool SCATTERED>
+// Prepared-record kernels: MODE 0 one lane per query, all taps of a
+// sampled level read (coherent batches); 1 one lane per query, in-bounds
+// taps only (scattered batches); 2 the wavefront-compacted path
+// (VALU-bound launches).  All three give the same bits.
+enum { kPrepLane = 0, kPrepScattered = 1, kPrepWave = 2 };
+
+template <int DT, int CH, bool TRI, int MODE>
 __global__ void __launch_bounds__(kBlock) k_sample_prep(SampleArgs a)
 {
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if constexpr (!SCATTERED && DT != HTEX_F32) {
+    if constexpr (MODE == kPrepWave) {
         __shared__ Task tasks[kBlock / 64][kTasks];
         if (q - (int64_t)__lane_id() >= a.Q) return;   // the whole wavefront is past the end
         sample_wave_prepared<DT, CH, TRI>(a, q, q < a.Q, tasks[threadIdx.x >> 6]);
     } else {
         if (q >= a.Q) return;
-        sample_one_prepared<DT, CH, TRI, SCATTERED>(a, q);
+        sample_one_prepared<DT, CH, TRI, MODE == kPrepScattered>(a, q);
     }
 }
 
@@ -344,11 +350,11 @@ hipError_t launch_fwd(const SampleArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int DT, int CH, bool TRI, bool SCATTERED>
+template <int DT, int CH, bool TRI, int MODE>
 hipError_t launch_fwd_prep(const SampleArgs &a, hipStream_t s)
 {
     const uint32_t G = (uint32_t)ceil_div(a.Q, kBlock);
-    hipLaunchKernelGGL((k_sample_prep<DT, CH, TRI, SCATTERED>), dim3(G), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_sample_prep<DT, CH, TRI, MODE>), dim3(G), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
@@ -376,13 +382,19 @@ template <int DT, int CH, bool TRI> struct Fwd {
 template <int DT, int CH, bool TRI> struct FwdPrep {
     static hipError_t run(const SampleArgs &a, hipStream_t s)
     {
-        return launch_fwd_prep<DT, CH, TRI, false>(a, s);
+        return launch_fwd_prep<DT, CH, TRI, kPrepLane>(a, s);
     }
 };
 template <int DT, int CH, bool TRI> struct FwdPrepScattered {
     static hipError_t run(const SampleArgs &a, hipStream_t s)
     {
-        return launch_fwd_prep<DT, CH, TRI, true>(a, s);
+        return launch_fwd_prep<DT, CH, TRI, kPrepScattered>(a, s);
+    }
+};
+template <int DT, int CH, bool TRI> struct FwdPrepWave {
+    static hipError_t run(const SampleArgs &a, hipStream_t s)
+    {
+        return launch_fwd_prep<DT, CH, TRI, kPrepWave>(a, s);
     }
 };
 
@@ -423,11 +435,13 @@ hipError_t launch_prepare(const SampleArgs &a, void *prep, hipStream_t s)
 }
 
 hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, bool scattered,
-                                  hipStream_t s)
+                                  bool cache_resident, hipStream_t s)
 {
     if (a.Q == 0) return hipSuccess;
-    return scattered ? dispatch<FwdPrepScattered>(a, dtype, filter, s)
-                     : dispatch<FwdPrep>(a, dtype, filter, s);
+    if (scattered) return dispatch<FwdPrepScattered>(a, dtype, filter, s);
+    // VALU-bound: quantized texels, or a pool that stays in the caches
+    if (dtype != HTEX_F32 || cache_resident) return dispatch<FwdPrepWave>(a, dtype, filter, s);
+    return dispatch<FwdPrep>(a, dtype, filter, s);
 }
 
 hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t s)

@@ -365,13 +365,19 @@ def test_backward_adjoint_on_gpu():
     assert abs(lhs - rhs) <= 1e-5 * scale
 
 
-def test_autograd_function():
+@pytest.mark.parametrize("with_prep", [False, True])
+def test_autograd_function(with_prep):
+    """HtexSample: the forward pass (plain, or from prepared records, which
+    gives the same bits) and the gradient of a loss through it."""
     m = cube_mesh()
     s = Setup(m, np.full(m.E, 3), has_mips=False, kind=0)
     q = uniform_queries(m.H, 5000, 3)
+    prep = htex.Prepared(s.dmesh, s.pool) if with_prep else None
+    plain, _ = s.gpu(q)
     tex = s.pool.texels.requires_grad_(True)
     out = htex.HtexSample.apply(tex, s.dmesh, s.pool, t(q.h), t(q.u), t(q.v), None,
-                                htex.HTEX_BILINEAR)
+                                htex.HTEX_BILINEAR, 0, False, prep)
+    np.testing.assert_array_equal(out.detach().cpu().numpy(), plain)
     (out * out).sum().backward()
     g = 2 * out.detach()
     ref = htex.htex_sample_backward(s.dmesh, s.pool, t(q.h), t(q.u), t(q.v), g.contiguous())
