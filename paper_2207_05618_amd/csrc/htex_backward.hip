@@ -259,29 +259,33 @@ __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, co
     fetch_specs(h, tp.n1, tp.p1, u, v, fs);
     const int32_t *es = tp.es, *ks = tp.ks;
     const bool *flips = tp.flips;
+    // every fetch's level plans, planned once: for the normalization W
+    // first, then for the scatter
     float W = 0.0f;
+    int nl[3], lvs[3][2];
+    LevelPlan pl[3][2];
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-        int lv[2];
         float om[2];
-        const int nlev = fetch_levels(L, ks[s], lv, om);
-        for (int sl = 0; sl < nlev; ++sl) {
-            const LevelPlan p = plan_level(ks[s], lv[sl], om[sl], fs[s], flips[s]);
-            W += (p.wx0 + p.wx1) * (p.wy0 + p.wy1);
+        nl[s] = fetch_levels(L, ks[s], lvs[s], om);
+#pragma unroll
+        for (int sl = 0; sl < (TRI ? 2 : 1); ++sl) {
+            pl[s][sl] = plan_level(ks[s], sl < nl[s] ? lvs[s][sl] : lvs[s][0], om[sl], fs[s],
+                                   flips[s]);
+            if (sl < nl[s]) W += (pl[s][sl].wx0 + pl[s][sl].wx1) * (pl[s][sl].wy0 + pl[s][sl].wy1);
         }
     }
     const float4 g4 = load_row<CH>(a.dout, q);
     const float rW = 1.0f / W;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-        int lv[2];
-        float om[2];
-        const int nlev = fetch_levels(L, ks[s], lv, om);
+        const int nlev = nl[s];
+        const int *lv = lvs[s];
         const int64_t eb = tp.ebs[s];
 #pragma unroll
-        for (int sl = 0; sl < 2; ++sl) {
+        for (int sl = 0; sl < (TRI ? 2 : 1); ++sl) {
             if (sl >= nlev) break;
-            const LevelPlan p = plan_level(ks[s], lv[sl], om[sl], fs[s], flips[s]);
+            const LevelPlan &p = pl[s][sl];
             if (own_run && s == 0) {
                 own.nlev = nlev;
                 own.lv[sl] = lv[sl];
