@@ -139,3 +139,42 @@ def test_aniso_invalid_queries_and_arguments():
     s0 = Setup(m, np.full(m.E, 3), has_mips=False)
     with pytest.raises(htex.HtexError):
         htex.htex_sample_aniso(s0.dmesh, s0.pool, t(q.h), t(q.u), t(q.v), t(J))
+
+
+def test_aniso_corner_queries_and_batch_order():
+    """Queries near the face-centroid corner (u, v < 0.02), where most probes
+    reach both the Next and the Prev quad, so the wavefront deals out more
+    than 64 neighbour fetches per round; probe counts from 1 to 16 mixed
+    with invalid queries in a ragged batch.  Against the oracle, and bit for
+    bit under a permutation of the batch: a query's result does not depend
+    on the other queries of its wavefront."""
+    m = tiny_meshes()[2]
+    s = Setup(m, np.random.default_rng(87).integers(2, 7, m.E), has_mips=True, kind=1, seed=88)
+    Q = 64 * 37 + 29
+    rng = np.random.default_rng(89)
+    q = uniform_queries(m.H, Q, 90)
+    q.u = rng.uniform(0.0, 0.02, Q).astype(np.float32)
+    q.v = rng.uniform(0.0, 0.02, Q).astype(np.float32)
+    J = aniso_jacobians(Q, 91, np.exp2(rng.uniform(-8, -3, Q)), ratio=(1.0, 20.0))
+    iso = rng.choice(Q, 100, replace=False)
+    J[iso] = np.float32(2.0 ** -6) * np.array([1, 0, 0, 1], np.float32)
+    bad = rng.choice(Q, 40, replace=False)
+    q.h[bad[:20]] = m.H
+    J[bad[20:], 1] = np.nan
+    got, n, ref, nref, errs = _run(s, q, J)
+    assert errs == 40
+    np.testing.assert_array_equal(n, nref)
+    assert set(np.unique(n)) >= set(range(1, 17))
+    assert np.isnan(got[bad]).all()
+    ok = np.isfinite(ref).all(1)
+    assert ok.sum() > Q - 60
+    assert not np.isfinite(got[~ok]).all(1).any()
+    assert_rel(got[ok], ref[ok], TOL)
+    perm = rng.permutation(Q)
+    q2 = uniform_queries(m.H, Q, 90)
+    q2.h, q2.u, q2.v = q.h[perm], q.u[perm], q.v[perm]
+    out2, n2 = htex.htex_sample_aniso(s.dmesh, s.pool, t(q2.h), t(q2.u), t(q2.v),
+                                      t(np.ascontiguousarray(J[perm])), nprobe=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out2.cpu().numpy(), got[perm])
+    np.testing.assert_array_equal(n2.cpu().numpy(), n[perm])
