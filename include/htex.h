@@ -336,7 +336,9 @@ htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *p
  * N and the probe coordinates are computed in float32 with one rounding
  * per operation (squares, sums, square roots, quotients, offset, product
  * and sum; no fused multiply-add), so they are reproducible.  N = 1 is
- * exactly htex_sample's trilinear result at footprint f = pmax.
+ * exactly htex_sample's trilinear result at footprint f = pmax.  Each
+ * probe's three fetches are added in Alg. 3's order, then the probes in
+ * order, so a query's result does not depend on the rest of the batch.
  * Requires a pool with mips; footprint arrays in `queries` are ignored.
  * jac: device float32 [Q][4], 16-byte aligned.  A query with a non-finite
  * derivative is invalid (NaN row, *err_count incremented). */
