@@ -138,7 +138,11 @@ __device__ __forceinline__ int word_k(uint64_t w) { return (int)((w >> 40) & 31u
 // the spread of N within the wave, instead of all running the wave's
 // largest N.  Each probe sums its three fetches in Alg. 3's order; the
 // query's lane adds its probes' sums in probe order, so a query's result
-// does not depend on the other queries of its wavefront.
+// does not depend on the other queries of its wavefront.  Within a round a
+// lane runs its probe's own-quad fetch itself; the Next and Prev fetches
+// that can reach a texel (a long major axis carries most probes' neighbour
+// fetches off their quads) are dealt out over the wavefront once more, and
+// each probe pulls their results back by ds_bpermute in Alg. 3's order.
 template <int DT, int CH, bool PREP>
 __global__ void __launch_bounds__(kBlock) k_aniso(SampleArgs a, const float4 *jac, int max_aniso,
                                                   int32_t *nprobe)
