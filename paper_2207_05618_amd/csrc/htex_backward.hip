@@ -204,14 +204,13 @@ __device__ __forceinline__ void add_tap(float *arena, int32_t base_f, uint32_t r
 }
 
 // The transpose of Alg. 3 for query q: every in-bounds tap of every fetch
-// and level receives (om w / W) dL/dout.  With `own_run`, the own fetch's
-// taps are not added but handed back (its levels and their plans, 1 / W and
-// dL/dout) for the caller to accumulate.  Returns false for an invalid
-// query.
-struct OwnFetch {
-    int nlev;
-    int lv[2];
-    LevelPlan p[2];
+// and level receives (om w / W) dL/dout.  With `runs`, no tap is added:
+// the plans of all fetches and levels, 1 / W and dL/dout are handed back
+// for the caller to accumulate.  Returns false for an invalid query.
+struct QueryPlans {
+    int nlev[3];
+    int lv[3][2];
+    LevelPlan p[3][2];
     float rw;      // 1 / W
     float4 g;      // dL/dout
 };
@@ -246,7 +245,7 @@ __device__ __forceinline__ Topo topo_of(const SampleArgs &a, int32_t h)
 template <int CH, bool TRI>
 __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, const TileTable &T,
                                               int32_t (&memo_key)[3][2], int32_t (&memo_base)[3][2],
-                                              bool own_run, OwnFetch &own, int32_t hk,
+                                              bool runs, QueryPlans &qp, int32_t hk,
                                               const Topo *known)
 {
     const int32_t h = known ? hk : a.qh[q];
@@ -286,10 +285,10 @@ __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, co
         for (int sl = 0; sl < (TRI ? 2 : 1); ++sl) {
             if (sl >= nlev) break;
             const LevelPlan &p = pl[s][sl];
-            if (own_run && s == 0) {
-                own.nlev = nlev;
-                own.lv[sl] = lv[sl];
-                own.p[sl] = p;
+            if (runs) {
+                qp.nlev[s] = nlev;
+                qp.lv[s][sl] = lv[sl];
+                qp.p[s][sl] = p;
                 continue;
             }
             if (!p.act) continue;
@@ -316,8 +315,8 @@ __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, co
             }
         }
     }
-    own.rw = rW;
-    own.g = g4;
+    qp.rw = rW;
+    qp.g = g4;
     return true;
 }
 
@@ -356,13 +355,13 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
 #pragma unroll
     for (int s = 0; s < 3; ++s)
         for (int sl = 0; sl < 2; ++sl) memo_key[s][sl] = -1;
-    OwnFetch own;
+    QueryPlans qp;
     const int32_t hb = dense_h;
     if (hb < 0) {
         for (int r = 0; r < kBwdPerThread; ++r) {
             const int64_t q = q0 + (int64_t)r * kBlock + threadIdx.x;
             if (q >= a.Q) break;
-            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, false, own, 0, nullptr);
+            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, false, qp, 0, nullptr);
         }
     } else {
         // 1. the tap cell of each query's own fetch on its finer level
@@ -441,76 +440,108 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
                                   (uint16_t)(r * kBlock + threadIdx.x);
         __syncthreads();
         // 4. runs of binned queries, kBwdPerThread consecutive entries per
-        // thread.  Queries of one cell share the four texels of their finer
-        // level, so those contributions are summed over the run; the coarser
-        // level's cell changes less often than the query does and gets a
-        // run of its own.
+        // thread.  Queries of one cell share the four texels of their own
+        // fetch's finer level, so those contributions are summed over the
+        // run; the coarser level's cell changes less often than the query
+        // does and gets a run of its own.  Every binned query has the
+        // block's halfedge, so its Next and Prev fetches go to the same two
+        // textures; their coarser level, where their taps crowd onto few
+        // texels, keeps runs too.  (Runs on every level of every fetch need
+        // more registers than two wavefronts per SIMD leave.)  A run is
+        // added to its tile when its tap cell changes.
+        constexpr int NL = TRI ? 2 : 1;
+        auto run_slot = [](int s, int sl) { return s == 0 || sl == 1; };
         const int i0 = threadIdx.x * kBwdPerThread;
         const int i1 = i0 + kBwdPerThread < nbinned ? i0 + kBwdPerThread : nbinned;
-        const int64_t eb0 = a.base[e0];
-        int32_t cur[2] = {-1, -1};
-        int curl[2] = {0, 0};
-        LevelPlan cp[2];
-        float4 acc[2][4];
-        auto flush = [&](int j) {
-            if (cur[j] < 0) return;
-            const uint32_t off[4] = {cp[j].o00, cp[j].o01, cp[j].o10, cp[j].o11};
-            const uint32_t lo = level_offset32(k0, curl[j]);
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                if ((cp[j].mask >> t) & 1)
-                    add_tap<CH>(arena, own_base[curl[j]], off[t] - lo,
-                                a.dtex + CH * (eb0 + off[t]), acc[j][t]);
-        };
         const Topo tb = topo_of(a, hb);
+        int32_t rkey[3][NL], rbase[3][NL];
+        float4 acc[3][NL][4];
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+#pragma unroll
+            for (int sl = 0; sl < NL; ++sl) rkey[s][sl] = -1;
+        // the tile of fetch s's level l (the own fetch's were claimed above)
+        auto tile = [&](int s, int sl, int l) -> int32_t {
+            if (s == 0) return own_base[l];
+            const int32_t key = tb.es[s] * 16 + l;
+            if (memo_key[s][sl] == key) return memo_base[s][sl];
+            const int32_t bf = find_tile(T, key, (int64_t)CH << (2 * (tb.ks[s] - l)));
+            if (bf >= 0) {
+                memo_key[s][sl] = key;
+                memo_base[s][sl] = bf;
+            }
+            return bf;
+        };
+        auto flush = [&](int s, int sl) {
+            const int32_t key = rkey[s][sl];
+            if (key < 0) return;
+            const int l = key >> 20, k = tb.ks[s], m = k - l, n = 1 << m;
+            const int32_t ti = (key & 1023) - 1, tj = ((key >> 10) & 1023) - 1;
+            const uint32_t lo = level_offset32(k, l);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int32_t x = ti + (t & 1), y = tj + (t >> 1);
+                if ((uint32_t)x >= (uint32_t)n || (uint32_t)y >= (uint32_t)n) continue;
+                const uint32_t rel = ((uint32_t)y << m) + (uint32_t)x;
+                add_tap<CH>(arena, rbase[s][sl], rel, a.dtex + CH * (tb.ebs[s] + lo + rel),
+                            acc[s][sl][t]);
+            }
+        };
         for (int i = i0; i < i1; ++i) {
             const int64_t q = q0 + order[i];
-            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, true, own, hb, &tb);
-            for (int j = 0; j < 2; ++j) {
-                if (j >= own.nlev || !own.p[j].act) continue;
-                const int32_t c = dense_cell(k0, own.lv[j], own.p[j]);
-                if (c < 0) {
-                    // a coarser level's taps outside the cell range (only
-                    // when the finer level's cell sits at its range's edge):
-                    // added directly
-                    const LevelPlan &p = own.p[j];
+            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, true, qp, hb, &tb);
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+#pragma unroll
+                for (int sl = 0; sl < NL; ++sl) {
+                    if (sl >= qp.nlev[s] || !qp.p[s][sl].act) continue;
+                    const LevelPlan &p = qp.p[s][sl];
+                    const int l = qp.lv[s][sl], k = tb.ks[s];
+                    const int32_t n = 1 << (k - l);
                     const float w[4] = {p.wx0 * p.wy0, p.wx1 * p.wy0, p.wx0 * p.wy1,
                                         p.wx1 * p.wy1};
-                    const uint32_t off[4] = {p.o00, p.o01, p.o10, p.o11};
-                    const uint32_t lo = level_offset32(k0, own.lv[j]);
+                    // the run key: level and tap bases, while the bases lie
+                    // in -1 .. n - 1 of a texture of at most 2^9 texels a side
+                    const bool keyed = run_slot(s, sl) && k <= 9 && p.i0 >= -1 && p.i0 <= n - 1 &&
+                                       p.j0 >= -1 && p.j0 <= n - 1;
+                    if (!keyed) {
+                        const uint32_t off[4] = {p.o00, p.o01, p.o10, p.o11};
+                        const uint32_t lo = level_offset32(k, l);
+                        const int32_t bf = tile(s, sl, l);
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            if (!((p.mask >> t) & 1)) continue;
+                            const float wt = w[t] * qp.rw;
+                            add_tap<CH>(arena, bf, off[t] - lo, a.dtex + CH * (tb.ebs[s] + off[t]),
+                                        make_float4(wt * qp.g.x, wt * qp.g.y, wt * qp.g.z,
+                                                    wt * qp.g.w));
+                        }
+                        continue;
+                    }
+                    const int32_t key = l << 20 | (p.j0 + 1) << 10 | (p.i0 + 1);
+                    if (key != rkey[s][sl]) {
+                        flush(s, sl);
+                        rkey[s][sl] = key;
+                        rbase[s][sl] = tile(s, sl, l);
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) acc[s][sl][t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
-                        if (!((p.mask >> t) & 1)) continue;
-                        const float wt = w[t] * own.rw;
-                        add_tap<CH>(arena, own_base[own.lv[j]], off[t] - lo,
-                                    a.dtex + CH * (eb0 + off[t]),
-                                    make_float4(wt * own.g.x, wt * own.g.y, wt * own.g.z,
-                                                wt * own.g.w));
+                        const float wt = w[t] * qp.rw;
+                        acc[s][sl][t].x += wt * qp.g.x;
+                        acc[s][sl][t].y += wt * qp.g.y;
+                        acc[s][sl][t].z += wt * qp.g.z;
+                        acc[s][sl][t].w += wt * qp.g.w;
                     }
-                    continue;
-                }
-                if (c != cur[j]) {
-                    flush(j);
-                    cur[j] = c;
-                    curl[j] = own.lv[j];
-                    cp[j] = own.p[j];
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) acc[j][t] = make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-                const LevelPlan &p = own.p[j];
-                const float w[4] = {p.wx0 * p.wy0, p.wx1 * p.wy0, p.wx0 * p.wy1, p.wx1 * p.wy1};
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const float wt = w[t] * own.rw;
-                    acc[j][t].x += wt * own.g.x;
-                    acc[j][t].y += wt * own.g.y;
-                    acc[j][t].z += wt * own.g.z;
-                    acc[j][t].w += wt * own.g.w;
                 }
             }
         }
-        flush(0);
-        flush(1);
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+#pragma unroll
+            for (int sl = 0; sl < NL; ++sl)
+                if (run_slot(s, sl)) flush(s, sl);
         // the queries left to the per-query path
         uint32_t rest = 0;
 #pragma unroll
@@ -518,7 +549,7 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
             if (cell[r] == -1) rest |= 1u << r;
         for (; rest; rest &= rest - 1)
             scatter_query<CH, TRI>(a, q0 + (int64_t)__builtin_ctz(rest) * kBlock + threadIdx.x, T,
-                                   memo_key, memo_base, false, own, 0, nullptr);
+                                   memo_key, memo_base, false, qp, 0, nullptr);
     }
     __syncthreads();
     // flush the tiles
