@@ -524,8 +524,10 @@ def test_backward_sorted_flag_is_only_a_hint():
 def test_backward_dense_blocks(channels, k, tri):
     """Blocks of 4096 queries on one halfedge take the binned scatter (runs of
     queries with one tap cell summed before they are added; trilinear
-    fetches keep a second run for their coarser level) when the texture has
-    at most 32 x 32 texels (k <= 5), the per-query scatter otherwise.  The batch mixes in what must leave the binned path: queries
+    fetches keep runs for their coarser level and for the neighbour
+    fetches' coarser level) when the texture has at most 32 x 32 texels
+    (k <= 5), the per-query scatter otherwise.  The batch mixes in what
+    must leave the binned path: queries
     on other halfedges, invalid h, NaN u, coordinates outside the quad
     (tap cells outside the binned range), and one block whose first half
     shares a halfedge while its second half does not (a batch wrongly
@@ -640,3 +642,45 @@ def test_largest_resolution_k15():
             np.testing.assert_allclose(acc.cpu().numpy(), share[e], rtol=1e-4, atol=1e-3)
     del dtex, pool
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("tri", [False, True])
+def test_backward_dense_blocks_mixed_neighbours(tri):
+    """Dense blocks (own textures of 32 x 32 texels) whose Next textures have
+    128 x 128 texels and whose Prev textures have 1024 x 1024: the
+    neighbour fetches' coarser level is summed in runs on the former and
+    added tap by tap on the latter (too large for the run key).  Queries are
+    drawn close to the spokes, so the neighbour fetches are active.  Against
+    the oracle within 1e-4 of sum |contributions|."""
+    m = cube_mesh()
+    hs = np.array([3, 17, 40], np.int32)
+    lr = np.full(m.E, 7)
+    lr[m.edge[m.prev[hs]]] = 10
+    lr[m.edge[hs]] = 5
+    s = Setup(m, lr, has_mips=tri, kind=1, seed=94, channels=4)
+    rng = np.random.default_rng(95)
+    Q = 4096 * 4 + 123
+    q = uniform_queries(m.H, Q, 96, log2f=(-9.0, 1.0) if tri else None)
+    q.h[:] = np.repeat(hs, Q // 3 + 1)[:Q]
+    near = rng.random(Q) < 0.6
+    q.u[near] = (q.u[near] * 0.05).astype(np.float32)
+    q.v[near[::-1]] = (q.v[near[::-1]] * 0.05).astype(np.float32)
+    g = rng.standard_normal((Q, 4)).astype(np.float32)
+    filt, ofilt = ((htex.HTEX_TRILINEAR, oracle.TRILINEAR) if tri
+                   else (htex.HTEX_BILINEAR, oracle.BILINEAR))
+    ref, dabs = oracle.backward(s.omesh, s.opool, q.h, q.u, q.v, g.astype(np.float64), q.f,
+                                filter=ofilt, with_abs=True)
+    d = htex.htex_sample_backward(s.dmesh, s.pool, t(q.h), t(q.u), t(q.v), t(g),
+                                  t(q.f) if tri else None, filter=filt,
+                                  flags=htex.HTEX_QUERIES_SORTED)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy().astype(np.float64).reshape(ref.shape)
+    err = np.abs(got - ref)
+    assert (err <= 1e-4 * dabs + 1e-12).all(), float((err / np.maximum(dabs, 1e-30)).max())
+    # the neighbour textures (all their levels) did receive gradient
+    def texels(x):
+        k = int(lr[x])
+        return sum(4 ** (k - l) for l in range(k + 1)) if tri else 4 ** k
+    for e in (m.edge[m.next[hs]], m.edge[m.prev[hs]]):
+        b = s.pool.base_host
+        assert all(np.abs(ref[b[x]:b[x] + texels(x)]).sum() > 0 for x in e)
