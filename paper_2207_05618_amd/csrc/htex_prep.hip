@@ -97,10 +97,27 @@ __device__ __forceinline__ uint16_t to_bf16(float x)
     return (uint16_t)(b >> 16);
 }
 
-__global__ void k_quant_bf16(const float *src, uint16_t *dst, int64_t count)
+// With `vec` (both arrays 16-byte aligned), eight values per thread and
+// step: two 16-byte loads, one 16-byte store; the last count % 8 values,
+// or all of them without `vec`, one at a time.
+__global__ void k_quant_bf16(const float *src, uint16_t *dst, int64_t count, bool vec)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    const int64_t n8 = vec ? count >> 3 : 0;
+    const float4 *s4 = reinterpret_cast<const float4 *>(src);
+    uint4 *d8 = reinterpret_cast<uint4 *>(dst);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n8; i += stride) {
+        const float4 a = s4[2 * i];
+        const float4 b = s4[2 * i + 1];
+        uint4 o;
+        o.x = (uint32_t)to_bf16(a.x) | (uint32_t)to_bf16(a.y) << 16;
+        o.y = (uint32_t)to_bf16(a.z) | (uint32_t)to_bf16(a.w) << 16;
+        o.z = (uint32_t)to_bf16(b.x) | (uint32_t)to_bf16(b.y) << 16;
+        o.w = (uint32_t)to_bf16(b.z) | (uint32_t)to_bf16(b.w) << 16;
+        d8[i] = o;
+    }
+    for (int64_t i = (n8 << 3) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += stride)
         dst[i] = to_bf16(src[i]);
 }
 
@@ -145,7 +162,16 @@ __global__ void __launch_bounds__(256) k_quant_fp8(const float *src, uint8_t *ds
             channels * (has_mips ? ((int64_t(4) << (2 * k)) - 1) / 3 : (int64_t(1) << (2 * k)));
         const float *t = src + channels * base[e];
         float mx = 0.0f;
-        for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) mx = fmaxf(mx, fabsf(t[i]));
+        if (channels == 4) {
+            // RGBA texels: one 16-byte load per texel
+            const float4 *t4 = reinterpret_cast<const float4 *>(t);
+            for (int64_t i = threadIdx.x; i < (cnt >> 2); i += blockDim.x) {
+                const float4 x = t4[i];
+                mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x.x), fabsf(x.y)), fmaxf(fabsf(x.z), fabsf(x.w))));
+            }
+        } else {
+            for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) mx = fmaxf(mx, fabsf(t[i]));
+        }
         red[threadIdx.x] = mx;
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
@@ -156,8 +182,25 @@ __global__ void __launch_bounds__(256) k_quant_fp8(const float *src, uint8_t *ds
         __syncthreads();
         if (threadIdx.x == 0) scale[e] = s;
         uint8_t *o = dst + channels * base[e];
-        for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x)
-            o[i] = (s == 0.0f) ? (uint8_t)0 : to_e4m3(t[i] / s);
+        if (channels == 4) {
+            // last texels first: the lines the max pass read most recently
+            // are the likeliest still in the L2
+            const float4 *t4 = reinterpret_cast<const float4 *>(t);
+            uint32_t *o4 = reinterpret_cast<uint32_t *>(o);
+            const int64_t n4 = cnt >> 2;
+            for (int64_t i = n4 - 1 - threadIdx.x; i >= 0; i -= blockDim.x) {
+                uint32_t c = 0;
+                if (s != 0.0f) {
+                    const float4 x = t4[i];
+                    c = (uint32_t)to_e4m3(x.x / s) | (uint32_t)to_e4m3(x.y / s) << 8 |
+                        (uint32_t)to_e4m3(x.z / s) << 16 | (uint32_t)to_e4m3(x.w / s) << 24;
+                }
+                o4[i] = c;
+            }
+        } else {
+            for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x)
+                o[i] = (s == 0.0f) ? (uint8_t)0 : to_e4m3(t[i] / s);
+        }
     }
 }
 
@@ -237,7 +280,9 @@ hipError_t launch_quantize_bf16(const float *src, uint16_t *dst, int64_t count, 
     if (count == 0) return hipSuccess;
     const int64_t want = (count + 255) / 256;
     const uint32_t grid = (uint32_t)(want < 65536 ? want : 65536);
-    hipLaunchKernelGGL(k_quant_bf16, dim3(grid), dim3(256), 0, s, src, dst, count);
+    const bool vec = reinterpret_cast<uintptr_t>(src) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(dst) % 16 == 0;
+    hipLaunchKernelGGL(k_quant_bf16, dim3(grid), dim3(256), 0, s, src, dst, count, vec);
     return hipGetLastError();
 }
 
