@@ -241,6 +241,38 @@ def test_quantize_codes_bit_exact(cfg3):
     np.testing.assert_array_equal(q8.texels.cpu().numpy(), codes)
 
 
+@pytest.mark.parametrize("channels", [4, 1])
+def test_quantize_bf16_tails_and_alignment(channels):
+    """BF16 conversion in eight-value steps with a tail (a value count that
+    is not a multiple of 8) when both arrays are 16-byte aligned, and one
+    value at a time when the destination is not: the same bits either way,
+    and nothing written outside the destination."""
+    import ctypes
+    from paper_2207_05618_amd import _lib
+    lr = np.array([1, 0, 2, 0, 0], np.uint8)
+    base, total = gpool.layout(lr, True)
+    rng = np.random.default_rng(5)
+    T = (rng.standard_normal((total, channels)) *
+         np.exp2(rng.integers(-20, 20, (total, 1)))).astype(np.float32)
+    pool = htex.Pool(lr, True, texels=t(T), channels=channels)
+    # the library's layouts come in multiples of 16 texels; a caller's pool
+    # record may name any count (here 3 fewer): 4 or 5 values of tail
+    pc = _lib.htex_pool.from_buffer_copy(pool.c)
+    pc.total_texels = total - 3
+    n = (total - 3) * channels
+    assert n % 8 in (4, 5)
+    want = oracle.f32_to_bf16(T).reshape(-1)[:n]
+    for shift in (0, 4):                            # 16-byte aligned, then 8 bytes off
+        buf = torch.full((n + 32,), 0x7777, dtype=torch.int16, device="cuda")
+        st = _lib.load().htex_quantize(ctypes.byref(pc), htex.HTEX_BF16,
+                                       buf.data_ptr() + 2 * shift, None, None)
+        assert st == 0
+        torch.cuda.synchronize()
+        got = buf.cpu().numpy().view(np.uint16)
+        np.testing.assert_array_equal(got[shift:shift + n], want)
+        assert (got[:shift] == 0x7777).all() and (got[shift + n:] == 0x7777).all()
+
+
 def test_quantize_fp8_edge_cases():
     """Zero edges, values near the subnormal/normal boundary and ties."""
     m = cube_mesh(n=2, seed=7, n_split=3, n_merge=1)
