@@ -108,8 +108,10 @@ __global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
 // binned queries: consecutive queries of one cell share their four target
 // texels, so their contributions are summed in registers and added to the
 // tile once per run (the coarser level of a trilinear fetch keeps a run of
-// its own).  Queries on other halfedges, or whose taps fall outside the
-// cell range, take the per-query path.
+// its own, and so does the Next and Prev fetches' coarser level; trilinear
+// runs read each query's inputs one query ahead).  Queries on other
+// halfedges, or whose taps fall outside the cell range, take the per-query
+// path.
 constexpr int kTiles = 32;
 constexpr int kArenaFloats = 16384;   // 64 KB
 // Bilinear batches whose textures have at most 32 x 32 texels need one
@@ -215,6 +217,23 @@ struct QueryPlans {
     float4 g;      // dL/dout
 };
 
+// A query's inputs, read ahead of its scatter.
+struct QIn {
+    float u, v, f;
+    float4 g;
+};
+
+template <int CH, bool TRI>
+__device__ __forceinline__ QIn load_qin(const SampleArgs &a, int64_t q)
+{
+    QIn x;
+    x.u = a.qu[q];
+    x.v = a.qv[q];
+    x.f = TRI ? a.qf[q] : 0.0f;
+    x.g = load_row<CH>(a.dout, q);
+    return x;
+}
+
 // The navigation of one halfedge's three fetches: their edges, log2
 // resolutions, reflections and texel bases.
 struct Topo {
@@ -246,14 +265,14 @@ template <int CH, bool TRI>
 __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, const TileTable &T,
                                               int32_t (&memo_key)[3][2], int32_t (&memo_base)[3][2],
                                               bool runs, QueryPlans &qp, int32_t hk,
-                                              const Topo *known)
+                                              const Topo *known, const QIn *pre = nullptr)
 {
     const int32_t h = known ? hk : a.qh[q];
-    const float u = a.qu[q], v = a.qv[q];
+    const float u = pre ? pre->u : a.qu[q], v = pre ? pre->v : a.qv[q];
     if (!((uint32_t)h < (uint32_t)a.H) || !isfinite(u) || !isfinite(v)) return false;
     const Topo tp = known ? *known : topo_of(a, h);
     Lod L{0, 0, 0.0f, 1.0f};
-    if constexpr (TRI) L = lod_of(a.qf[q]);
+    if constexpr (TRI) L = lod_of(pre ? pre->f : a.qf[q]);
     FetchSpec fs[3];
     fetch_specs(h, tp.n1, tp.p1, u, v, fs);
     const int32_t *es = tp.es, *ks = tp.ks;
@@ -274,7 +293,7 @@ __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, co
             if (sl < nl[s]) W += (pl[s][sl].wx0 + pl[s][sl].wx1) * (pl[s][sl].wy0 + pl[s][sl].wy1);
         }
     }
-    const float4 g4 = load_row<CH>(a.dout, q);
+    const float4 g4 = pre ? pre->g : load_row<CH>(a.dout, q);
     const float rW = 1.0f / W;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
@@ -487,9 +506,22 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
                             acc[s][sl][t]);
             }
         };
+        // each query's inputs are read one query ahead
+        int64_t qn = 0;
+        QIn nxt{};
+        if (TRI && i0 < i1) {
+            qn = q0 + order[i0];
+            nxt = load_qin<CH, TRI>(a, qn);
+        }
         for (int i = i0; i < i1; ++i) {
-            const int64_t q = q0 + order[i];
-            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, true, qp, hb, &tb);
+            const int64_t q = TRI ? qn : q0 + order[i];
+            const QIn cur = nxt;
+            if (TRI && i + 1 < i1) {
+                qn = q0 + order[i + 1];
+                nxt = load_qin<CH, TRI>(a, qn);
+            }
+            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, true, qp, hb, &tb,
+                                   TRI ? &cur : nullptr);
 #pragma unroll
             for (int s = 0; s < 3; ++s) {
 #pragma unroll
