@@ -5,7 +5,7 @@ Workload (default, "frame4k"): a seeded closed-sphere polygon mesh of about
 194k faces (70% quads, 20% triangles, 10% 5-8-gons, 1% of the faces removed
 as holes so 2% of the edges are boundary edges), one 64x64 RGBA float32
 texture per edge with its full mip chain (34.8 GB resident in HBM), texels
-from seeded smooth lattice noise; 3840 x 2160 = 8,294,400 queries per step
+from seeded Perlin gradient noise; 3840 x 2160 = 8,294,400 queries per step
 (uniform halfedge, uniform barycentric point, log2 footprint ~ U[-3.2, -1.2])
 sorted by halfedge, trilinear filtering.  A step is one htex_sample call over
 one frame batch; eight distinct seeded batches rotate, so each batch comes
@@ -77,7 +77,7 @@ def build_workload(name):
     from htexgen.queries import uniform_queries
     if name == "frame4k":
         mesh = sphere_mesh(n=183, seed=201)
-        k, Q, log2f, kind, tex_seed = 6, 3840 * 2160, (-3.2, -1.2), 1, 202
+        k, Q, log2f, kind, tex_seed = 6, 3840 * 2160, (-3.2, -1.2), 2, 202
         qseeds = [203 + 10 * i for i in range(8)]
     else:
         mesh = cube_mesh()
@@ -143,10 +143,48 @@ def algorithmic_bytes(dbg, h, log2res, base, total, Q, qbytes=16, obytes=16, tby
     io = (qbytes + obytes) * Q
     total_bytes = io + topo + tbytes * texels
     return {"bytes": int(total_bytes), "bytes_per_query": total_bytes / Q,
+            "io_bytes": int(io), "topo_bytes": int(topo), "distinct_edges": int(n_e),
             "texel_bytes_per_query": tbytes * texels / Q, "unique_texels": texels,
             "unique_64B_segments": segments, "unique_128B_lines": lines128,
             "segment_bytes_per_query": (io + topo + 64 * segments) / Q,
             "line128_bytes_per_query": (io + topo + 128 * lines128) / Q}
+
+
+def storage_bytes(alg, Q, tbytes, scaled):
+    """Algorithmic bytes of the same launch with texels stored in `tbytes`
+    bytes each (BF16: 8, FP8: 4 for RGBA), plus one float32 scale per
+    distinct edge for FP8."""
+    b = alg["io_bytes"] + alg["topo_bytes"] + tbytes * alg["unique_texels"]
+    if scaled:
+        b += 4 * alg["distinct_edges"]
+    return {"bytes": int(b), "bytes_per_query": b / Q,
+            "texel_bytes_per_query": tbytes * alg["unique_texels"] / Q}
+
+
+def kernel_seconds(fn, n=10, warm=3):
+    """Average time of one call of fn(i) (one kernel launch) from HIP events
+    recorded around each call on the launch stream."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for i in range(warm):
+        fn(i)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(n)]
+    t0 = time.perf_counter()
+    for i in range(n):
+        evs[i][0].record(stream)
+        fn(i)
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / n
+    return sum(a.elapsed_time(b) for a, b in evs) / n / 1e3, wall
+
+
+def roofline_entry(kernel, nbytes, seconds, bound="hbm"):
+    achieved = nbytes / seconds / 1e9
+    return {"bound": bound, "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "avg_kernel_us": seconds * 1e6}
 
 
 # ----------------------------------------------------------- CPU oracle --
@@ -205,6 +243,53 @@ def cpu_baseline(mesh, log2res, base, pool_dev, batch, has_mips=True, want_s=10.
             "single_core_value": q1.Q / statistics.median(one_times)}
 
 
+# ------------------------------------------------------------ precision --
+
+def precision_config3(n_iter=20):
+    """Config 3: the tiny cube's 16x16 RGBA float32 pool (no mips) stored as
+    float32, BF16 and FP8-E4M3 (per-edge scale), 2^20 seeded queries,
+    bilinear, blended in float32.  Per storage type: kernel time from HIP
+    events, samples/s and the algorithmic bytes per launch (the 0.2-0.8 MB
+    pool stays in the caches, so HBM is not what bounds these launches;
+    the roofline entry is reported for completeness)."""
+    import numpy as np
+    import torch
+
+    import paper_2207_05618_amd as htex
+    from htexgen import pool as gpool
+    from htexgen.mesh import cube_mesh
+    from htexgen.queries import uniform_queries
+
+    m = cube_mesh()
+    lr = np.full(m.E, 4, np.uint8)
+    base, total = gpool.layout(lr, False)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    pool = htex.Pool(lr, False, texels=T(gpool.fill_level0_host(0, 102, lr, base, total,
+                                                                m.boundary_edges(), False)))
+    q = uniform_queries(m.H, 1 << 20, 301)
+    dm = htex.Mesh.of(m)
+    prep = htex.Prepared(dm, pool)
+    h, u, v = T(q.h), T(q.u), T(q.v)
+    _, dbg = htex.htex_sample(dm, pool, h, u, v, debug=True)
+    alg = algorithmic_bytes(dbg.cpu().numpy(), q.h, lr, base, total, q.Q, qbytes=12)
+    del dbg
+    out = torch.empty((q.Q, 4), dtype=torch.float32, device="cuda")
+    res = {"queries": q.Q, "pool_texels": int(total), "filter": "bilinear"}
+    for name, dt, tb in (("f32", htex.HTEX_F32, 16), ("bf16", htex.HTEX_BF16, 8),
+                         ("fp8_e4m3", htex.HTEX_FP8_E4M3, 4)):
+        p = pool if dt == htex.HTEX_F32 else htex.htex_quantize(pool, dt)
+        ks, wall = kernel_seconds(lambda i: htex.htex_sample_prepared(prep, p, h, u, v, out=out),
+                                  n=n_iter)
+        b = storage_bytes(alg, q.Q, tb, dt == htex.HTEX_FP8_E4M3)
+        res[name] = {"samples_per_s": q.Q / ks, "kernel_us": ks * 1e6, "wall_us": wall * 1e6,
+                     "pool_bytes": p.nbytes(), "alg_bytes_per_query": b["bytes_per_query"],
+                     "roofline": roofline_entry(f"htex::k_sample_prep<{name},bilinear>",
+                                                b["bytes"], ks)}
+    for name in ("bf16", "fp8_e4m3"):
+        res[name]["speedup_vs_f32"] = res[name]["samples_per_s"] / res["f32"]["samples_per_s"]
+    return res
+
+
 # ------------------------------------------------------- differentiation --
 
 def grad_benchmark(steps=200):
@@ -225,7 +310,7 @@ def grad_benchmark(steps=200):
     dm = htex.Mesh.of(m)
     base, total = gpool.layout(lr, False)
     target = htex.Pool(lr, False, texels=torch.from_numpy(
-        gpool.fill_level0_host(1, 401, lr, base, total, m.boundary_edges(), False)).cuda())
+        gpool.fill_level0_host(2, 401, lr, base, total, m.boundary_edges(), False)).cuda())
     q = uniform_queries(m.H, 3840 * 2160, 405, sort=True)
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     h, u, v = T(q.h), T(q.u), T(q.v)
@@ -297,7 +382,7 @@ def grad_trilinear(m, dm, q, timed, steps):
     lr = np.full(m.E, 5, np.uint8)
     base, total = gpool.layout(lr, True)
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    target = htex.Pool(lr, True, texels=T(gpool.fill_level0_host(1, 401, lr, base, total,
+    target = htex.Pool(lr, True, texels=T(gpool.fill_level0_host(2, 401, lr, base, total,
                                                                   m.boundary_edges(), True)))
     htex.htex_build_mips(target)
     f = T(np.exp2(np.random.default_rng(406).uniform(-8, 0, q.Q)).astype(np.float32))
@@ -614,8 +699,9 @@ def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9),
 
     t0 = time.perf_counter()
     rng = np.random.default_rng(seed + 1)
-    # per-mesh resolution, downgraded on the largest meshes to reach the budget
-    ks = rng.choice([5, 6, 7], 16)
+    # per-mesh resolution from 16^2 .. 128^2, downgraded on the largest
+    # meshes to reach the budget
+    ks = rng.choice([4, 5, 6, 7], 16)
 
     def bytes_of(i, k):
         return htex.htex_pool_layout(np.full(meshes[i][4], k, np.uint8), True)[1] * 8
@@ -654,22 +740,41 @@ def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9),
     mean_q = float(np.mean([p[1] for p in payloads]))
     log(f"serve: 48 payloads, mean {mean_q:.0f} queries ({time.perf_counter() - t0:.1f}s)")
 
-    # one request at a time: copy in, sample, copy out, wait (no batching)
-    seq_lat = []
-    alone = {}
-    for j in range(16):
-        mid, Q, h, u, v, f, _ = payloads[j]
-        _, pool, prep, _ = resident[mid]
-        ts = time.perf_counter()
-        dh, du, dv, df = (x.to("cuda", non_blocking=True) for x in (h, u, v, f))
-        o = htex.htex_sample_prepared(prep, pool, dh, du, dv, df, filter=htex.HTEX_TRILINEAR,
-                                      flags=htex.HTEX_QUERIES_SORTED)
-        oh = torch.empty((Q, 4), dtype=torch.float32, pin_memory=True)
-        oh.copy_(o, non_blocking=True)
-        torch.cuda.synchronize()
-        seq_lat.append(time.perf_counter() - ts)
-        alone[j] = oh
-    seq_rate = sum(payloads[j][1] for j in range(16)) / sum(seq_lat)
+    def sequential(js, res):
+        """One request at a time: copy in, sample, copy out, wait (no
+        batching).  Returns (samples/s, latencies, results)."""
+        lat, outs = [], {}
+        for j in js:
+            mid, Q, h, u, v, f, _ = payloads[j]
+            _, pool, prep, _ = res[mid]
+            ts = time.perf_counter()
+            dh, du, dv, df = (x.to("cuda", non_blocking=True) for x in (h, u, v, f))
+            o = htex.htex_sample_prepared(prep, pool, dh, du, dv, df, filter=htex.HTEX_TRILINEAR,
+                                          flags=htex.HTEX_QUERIES_SORTED)
+            oh = torch.empty((Q, 4), dtype=torch.float32, pin_memory=True)
+            oh.copy_(o, non_blocking=True)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - ts)
+            outs[j] = oh
+        return sum(payloads[j][1] for j in js) / sum(lat), lat, outs
+
+    seq_rate, seq_lat, alone = sequential(range(16), resident)
+
+    # Against plain FP32 on the same GPU: the same meshes and resolutions
+    # with float32 texels take twice the bytes, so the comparison runs on
+    # the meshes whose float32 pools fit the same budget (smallest first),
+    # with the payloads that name them: BF16 served (capacity) and one at a
+    # time, then float32 served and one at a time.
+    f32_bytes = [2 * r[1].nbytes() for r in resident]
+    subset, acc = [], 0
+    for i in np.argsort(f32_bytes):
+        if acc + f32_bytes[i] <= target_bytes:
+            subset.append(int(i))
+            acc += f32_bytes[i]
+    js = [j for j in range(48) if payloads[j][0] in subset]
+    cmp = {"meshes": subset, "f32_resident_bytes": acc, "requests": len(js)}
+    if js:
+        cmp["bf16_sequential_samples_per_s"] = sequential(js[:16], resident)[0]
 
     srv = Server(htex.HTEX_BF16, htex.HTEX_TRILINEAR, arena_bytes=4 << 30, max_inflight=64,
                  compute_streams=1, copy_streams=1, max_batch_queries=1 << 22, max_meshes=16,
@@ -677,59 +782,82 @@ def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9),
     for dm, pool, prep, _ in resident:
         srv.add_mesh(prep, pool)
 
-    def submit(j):
+    def submit(j, server=None):
         mid, Q, h, u, v, f, out = payloads[j]
-        return srv.submit(mid, h, u, v, f, out)
+        return (server or srv).submit(mid, h, u, v, f, out)
 
-    # saturation: bursts of 3 x 48 requests, after one untimed burst that
-    # warms the server (events, arena pages, copy queues)
-    for j in range(48):
-        submit(j)
-    srv.drain(300)
-    for rid, _ in srv.poll(1 << 16):
-        srv.release(rid)
-    # the faster of two timed bursts (the first burst on a fresh box can run
-    # slow while the host and link settle)
-    sat_rate = 0.0
-    for rep in range(2):
-        tb = time.perf_counter()
-        for r in range(3):
-            for j in range(48):
-                submit(j)
-        srv.drain(300)
-        sat_rate = max(sat_rate, 3 * sum(p[1] for p in payloads) / (time.perf_counter() - tb))
-        for rid, _ in srv.poll(1 << 16):
-            srv.release(rid)
+    def burst(server, js, reps=2):
+        """Saturation: the faster of `reps` timed bursts of 3 x js requests,
+        after one untimed burst that warms the server (events, arena pages,
+        copy queues; the first burst on a fresh box can run slow while the
+        host and link settle)."""
+        for j in js:
+            submit(j, server)
+        server.drain(300)
+        for rid, _ in server.poll(1 << 16):
+            server.release(rid)
+        best = 0.0
+        for rep in range(reps):
+            tb = time.perf_counter()
+            for r in range(3):
+                for j in js:
+                    submit(j, server)
+            server.drain(300)
+            best = max(best, 3 * sum(payloads[j][1] for j in js) / (time.perf_counter() - tb))
+            for rid, _ in server.poll(1 << 16):
+                server.release(rid)
+        return best
+
+    sat_rate = burst(srv, range(48))
     same = all(np.array_equal(payloads[j][6].numpy(), alone[j].numpy()) for j in range(16))
     log(f"serve: burst {sat_rate:.3e} samples/s; sequential {seq_rate:.3e}; "
         f"mix==alone {same}")
 
     def poisson(lam):
         """Poisson arrivals at lam requests/s for run_s seconds; returns the
-        achieved samples/s (until the last result) and the latencies."""
+        achieved samples/s (until the last result), the latencies and the
+        request sizes (in completion order)."""
         arr = np.cumsum(rng.exponential(1.0 / lam, size=int(lam * run_s) + 1))
         arr = arr[arr < run_s]
         picks = rng.integers(0, 48, size=len(arr))
         start = time.perf_counter()
         nq = 0
+        size_of = {}
         for a, j in zip(arr, picks):
             while time.perf_counter() - start < a:
                 pass
-            submit(int(j))
+            size_of[submit(int(j))] = payloads[int(j)][1]
             nq += payloads[int(j)][1]
         srv.drain(300)
         wall = time.perf_counter() - start
         done = srv.poll(1 << 20)
         lat = np.array([l for _, l in done])
+        sizes = np.array([size_of[rid] for rid, _ in done])
         for rid, _ in done:
             srv.release(rid)
-        return nq / wall, lat, len(arr)
+        return nq / wall, lat, len(arr), sizes
+
+    # request-size classes: deciles of the payloads' sizes (log-uniform
+    # over 4k-2M queries)
+    size_edges = np.quantile([p[1] for p in payloads], np.linspace(0, 1, 11))
+
+    def by_size(lat, sizes):
+        rows = []
+        for d in range(10):
+            lo, hi = size_edges[d], size_edges[d + 1]
+            sel = (sizes >= lo) & ((sizes <= hi) if d == 9 else (sizes < hi))
+            if sel.any():
+                rows.append({"decile": d + 1, "queries_lo": int(lo), "queries_hi": int(hi),
+                             "requests": int(sel.sum()),
+                             "p50_ms": float(np.percentile(lat[sel], 50) * 1e3),
+                             "p99_ms": float(np.percentile(lat[sel], 99) * 1e3)})
+        return rows
 
     # sustained capacity: arrivals offered 25% above the burst rate keep the
     # server busy for the whole run; a burst of queued requests batches more
     # than a stream of arrivals does, so the loads below are set against the
     # smaller of the two
-    sustained, _, _ = poisson(1.25 * sat_rate / mean_q)
+    sustained, _, _, _ = poisson(1.25 * sat_rate / mean_q)
     capacity = min(sat_rate, sustained)
     log(f"serve: sustained {sustained:.3e} samples/s under overload; capacity {capacity:.3e}")
     out = {"resident_bytes": pool_bytes, "meshes": 16,
@@ -743,20 +871,64 @@ def serve_benchmark(meshes, seed=501, target_bytes=200e9, rates=(0.3, 0.6, 0.9),
     lam_sat = capacity / mean_q
     for frac in rates:
         lam = frac * lam_sat
-        achieved, lat, nreq = poisson(lam)
+        achieved, lat, nreq, sizes = poisson(lam)
         rec = {"load": frac, "requests": int(nreq), "offered_req_per_s": lam,
                "achieved_samples_per_s": achieved,
                "p50_ms": float(np.percentile(lat, 50) * 1e3),
-               "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+               "p99_ms": float(np.percentile(lat, 99) * 1e3),
+               "by_request_size": by_size(lat, sizes)}
         out["rates"].append(rec)
         log(f"serve: load {frac}: {nreq} requests, p50 {rec['p50_ms']:.2f} ms, "
             f"p99 {rec['p99_ms']:.2f} ms, {rec['achieved_samples_per_s']:.3e} samples/s")
     st = srv.stats()
-    srv.close()
     out["batches"] = st["batches"]
     out["arena_peak_bytes"] = st["arena_peak_bytes"]
     out["copy_chunk_queries"] = chunk
-    del resident, payloads, alone
+
+    if js:
+        cmp["bf16_served_samples_per_s"] = burst(srv, js)
+    srv.close()
+    srv = None      # the server object kept its meshes' pools alive
+    del alone
+    for i in range(16):
+        if i not in subset:
+            resident[i] = None
+    torch.cuda.empty_cache()
+    for i in subset:
+        dm, pool, prep, H = resident[i]
+        resident[i] = None
+        del pool, prep
+        torch.cuda.empty_cache()
+        E = meshes[i][4]
+        p32 = htex.Pool(np.full(E, ks[i], np.uint8), True, htex.HTEX_F32)
+        gdev.fill_level0(p32.texels, 1, seed * 100 + i, p32.log2res, p32.base, meshes[i][6])
+        htex.htex_build_mips(p32)
+        resident[i] = (dm, p32, htex.Prepared(dm, p32), H)
+    torch.cuda.synchronize()
+    if js:
+        srv32 = Server(htex.HTEX_F32, htex.HTEX_TRILINEAR, arena_bytes=4 << 30, max_inflight=64,
+                       compute_streams=1, copy_streams=1, max_batch_queries=1 << 22,
+                       max_meshes=16, copy_chunk_queries=chunk)
+        ids = {}
+        for i in subset:
+            ids[i] = srv32.add_mesh(resident[i][2], resident[i][1])
+        # the server numbers meshes in registration order: remap the payloads
+        remapped = {j: (ids[payloads[j][0]],) + payloads[j][1:] for j in js}
+        saved = {j: payloads[j] for j in js}
+        for j in js:
+            payloads[j] = remapped[j]
+        cmp["f32_served_samples_per_s"] = burst(srv32, js)
+        srv32.close()
+        for j in js:
+            payloads[j] = saved[j]
+        cmp["f32_sequential_samples_per_s"] = sequential(js[:16], resident)[0]
+        cmp["served_bf16_over_sequential_f32"] = (cmp["bf16_served_samples_per_s"] /
+                                                   cmp["f32_sequential_samples_per_s"])
+        cmp["served_f32_over_sequential_f32"] = (cmp["f32_served_samples_per_s"] /
+                                                  cmp["f32_sequential_samples_per_s"])
+        log(f"serve vs plain f32: {json.dumps(cmp)}")
+    out["vs_plain_f32"] = cmp
+    del resident, payloads
     torch.cuda.empty_cache()
     return out
 
@@ -832,12 +1004,14 @@ def main():
         copy_gbs = None
     else:
         ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ce0.record(stream)
         for _ in range(5):
+            y.copy_(x)
+        ce0.record(stream)
+        for _ in range(30):
             y.copy_(x)
         ce1.record(stream)
         torch.cuda.synchronize()
-        copy_gbs = 5 * 2 * x.numel() * 4 / (ce0.elapsed_time(ce1) / 1e3) / 1e9
+        copy_gbs = 30 * 2 * x.numel() * 4 / (ce0.elapsed_time(ce1) / 1e3) / 1e9
     del x, y
 
     def step(i, p=pool, bs=dev_batches, flags=htex.HTEX_QUERIES_SORTED):
@@ -863,6 +1037,17 @@ def main():
     median_kernel_s = statistics.median(kern_ms) / 1e3
     value = args.steps * Q / elapsed
     log(f"{args.steps} steps in {elapsed * 1e3:.2f} ms; kernel avg {avg_kernel_s * 1e6:.1f} us")
+
+    alg = None
+    if not args.no_bytes:
+        h, u, v, f = dev_batches[0]
+        _, dbg = htex.htex_sample(dmesh, pool, h, u, v, f, filter=htex.HTEX_TRILINEAR,
+                                  debug=True)
+        dbg_host = dbg.cpu().numpy()
+        del dbg
+        alg = algorithmic_bytes(dbg_host, batches[0].h, log2res, pool.base_host, pool.total, Q)
+        del dbg_host
+        torch.cuda.empty_cache()
 
     def rate(p, bs, n=10, flags=htex.HTEX_QUERIES_SORTED):
         for i in range(3):
@@ -909,17 +1094,28 @@ def main():
             extra["one_of_eight_share"] = {"queries": Q // 8, "us": t_share * 1e6,
                                            "samples_per_s": (Q // 8) / t_share}
             del share, out8
-        # unsorted batch put in halfedge order first (sort, permute, sample,
-        # results back to input order), timed as a whole
+        # unsorted batch put in halfedge order first (one call sorts the
+        # batch with its queries), sampled sorted, results back in input
+        # order; timed as a whole, then step by step
         hu, uu, vu, fu = to_dev(unsorted)
         sorted_out = torch.empty_like(out)
+        keep = {}
 
-        def sorted_step():
-            perm = htex.htex_sort_queries(mesh.H, hu)
-            h2, u2, v2, f2 = htex.htex_permute_queries(perm, hu, uu, vu, fu)
+        def sort_step(i=0):
+            keep["b"] = htex.htex_sort_batch(mesh.H, hu, uu, vu, fu)
+
+        def sample_sorted(i=0):
+            perm, h2, u2, v2, f2 = keep["b"]
             htex.htex_sample_prepared(prep, pool, h2, u2, v2, f2, filter=htex.HTEX_TRILINEAR,
                                       flags=htex.HTEX_QUERIES_SORTED, out=sorted_out)
-            htex.htex_unpermute_results(perm, sorted_out, out=out)
+
+        def unpermute(i=0):
+            htex.htex_unpermute_results(keep["b"][0], sorted_out, out=out)
+
+        def sorted_step():
+            sort_step()
+            sample_sorted()
+            unpermute()
 
         for _ in range(2):
             sorted_step()
@@ -929,14 +1125,30 @@ def main():
             sorted_step()
         torch.cuda.synchronize()
         extra["unsorted_via_sort_samples_per_s"] = 5 * Q / (time.perf_counter() - t1)
-        del hu, uu, vu, fu, sorted_out
-        qb = htex.htex_quantize(pool, htex.HTEX_BF16)
-        extra["bf16_samples_per_s"] = rate(qb, dev_batches)
-        del qb
-        q8 = htex.htex_quantize(pool, htex.HTEX_FP8_E4M3)
-        extra["fp8_e4m3_samples_per_s"] = rate(q8, dev_batches)
-        del q8
-        torch.cuda.empty_cache()
+        extra["sort_path_us"] = {"sort_batch": kernel_seconds(sort_step, n=5)[0] * 1e6,
+                                 "sample_sorted": kernel_seconds(sample_sorted, n=5)[0] * 1e6,
+                                 "unpermute": kernel_seconds(unpermute, n=5)[0] * 1e6}
+        del hu, uu, vu, fu, sorted_out, keep
+        # the frame with its pool stored as BF16 and FP8-E4M3: kernel time
+        # from HIP events per launch, and the roofline against the bytes the
+        # launch needs at 8 and 4 bytes per texel
+        for name, dt, tb in (("bf16", htex.HTEX_BF16, 8), ("fp8_e4m3", htex.HTEX_FP8_E4M3, 4)):
+            qp = htex.htex_quantize(pool, dt)
+            extra[f"{name}_samples_per_s"] = rate(qp, dev_batches)
+            ks, _ = kernel_seconds(lambda i: step(i, qp, dev_batches), n=20)
+            rec = {"kernel_us": ks * 1e6, "samples_per_s_kernel": Q / ks,
+                   "pool_bytes": qp.nbytes()}
+            if alg is not None:
+                b = storage_bytes(alg, Q, tb, dt == htex.HTEX_FP8_E4M3)
+                rec["alg_bytes_per_query"] = b["bytes_per_query"]
+                rec["alg_texel_bytes_per_query"] = b["texel_bytes_per_query"]
+                rec["roofline"] = roofline_entry(f"htex::k_sample_prep<{name},trilinear>",
+                                                 b["bytes"], ks)
+            extra[f"{name}_frame"] = rec
+            del qp
+            torch.cuda.empty_cache()
+        extra["config3_precision"] = precision_config3()
+        log(f"config3 {json.dumps(extra['config3_precision'])}")
         for kk in list(extra):
             if kk.endswith("samples_per_s"):
                 extra[kk.replace("samples_per_s", "speedup_vs_f32")] = extra[kk] / value
@@ -953,15 +1165,7 @@ def main():
             log(f"rgb+disp {json.dumps(extra['rgb_plus_displacement'])}")
 
     roofline = None
-    alg = None
-    if not args.no_bytes:
-        h, u, v, f = dev_batches[0]
-        _, dbg = htex.htex_sample(dmesh, pool, h, u, v, f, filter=htex.HTEX_TRILINEAR,
-                                  debug=True)
-        dbg_host = dbg.cpu().numpy()
-        del dbg
-        alg = algorithmic_bytes(dbg_host, batches[0].h, log2res, pool.base_host, pool.total, Q)
-        del dbg_host
+    if alg is not None:
         achieved = alg["bytes"] / avg_kernel_s / 1e9
         traffic = recorded_traffic()
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,

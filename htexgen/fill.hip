@@ -1,8 +1,8 @@
 // fill.hip -- device-side texel fill of the seeded input generator.
 //
 // Writes level 0 of every edge texture with the same values as
-// htexgen/texels.py (splitmix64-based counter hash; uniform or smooth lattice
-// noise; mirrored content on boundary edges).  Input generation only: no part
+// htexgen/texels.py (splitmix64-based counter hash; uniform, smooth lattice
+// noise or Perlin gradient noise; mirrored content on boundary edges).  Input generation only: no part
 // of the sampling arithmetic lives here.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -29,6 +29,34 @@ __device__ __forceinline__ uint64_t hash5(uint64_t seed, uint64_t a, uint64_t b,
 
 __constant__ int32_t kRamp[8] = {1, 6, 14, 25, 39, 50, 58, 63};
 
+// Perlin's quintic fade at t = (2f + 1) / 16, times 2^20, and the eight
+// lattice gradients (see htexgen/texels.py)
+__constant__ int64_t kFade[8] = {2326, 51138, 188750, 402682, 645894, 859826, 997438, 1046250};
+__constant__ int32_t kGrad[8][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1},
+                                    {1, 1}, {-1, 1}, {1, -1}, {-1, -1}};
+
+// Perlin gradient noise texel of edge e, channel c, at source texel (si, sj),
+// in exact integer arithmetic: (2^18 + 31 M) 2^-24 with
+// M = clamp(floor(N / 2^26) + 2^18, 0, 2^19) and N / 2^44 the noise.
+__device__ __forceinline__ float perlin_texel(uint64_t seed, int64_t e, int c, int64_t si,
+                                              int64_t sj)
+{
+    const int64_t a = si >> 3, b = sj >> 3;
+    const int64_t x = 2 * (si & 7) + 1, y = 2 * (sj & 7) + 1;
+    const int64_t wx1 = kFade[si & 7], wy1 = kFade[sj & 7];
+    const int64_t wx0 = (int64_t(1) << 20) - wx1, wy0 = (int64_t(1) << 20) - wy1;
+    auto corner = [&](int64_t da, int64_t db) -> int64_t {
+        const int g = (int)(hash5(seed, (uint64_t)e, (uint64_t)c, (uint64_t)(a + da),
+                                  (uint64_t)(b + db)) & 7u);
+        return kGrad[g][0] * (x - 16 * da) + kGrad[g][1] * (y - 16 * db);
+    };
+    const int64_t N = wx0 * wy0 * corner(0, 0) + wx1 * wy0 * corner(1, 0) +
+                      wx0 * wy1 * corner(0, 1) + wx1 * wy1 * corner(1, 1);
+    int64_t M = (N >> 26) + (int64_t(1) << 18);
+    M = M < 0 ? 0 : (M > (int64_t(1) << 19) ? (int64_t(1) << 19) : M);
+    return (float)(int32_t)((int64_t(1) << 18) + 31 * M) * 0x1p-24f;
+}
+
 __global__ void k_fill(int kind, uint64_t seed, int32_t E, const uint8_t *log2res,
                        const int64_t *base, const uint8_t *boundary, float *tex, int channels)
 {
@@ -48,6 +76,8 @@ __global__ void k_fill(int kind, uint64_t seed, int32_t E, const uint8_t *log2re
                 if (kind == 0) {
                     const uint64_t hv = hash5(seed, (uint64_t)e, (uint64_t)(sj * n + si), (uint64_t)c, 0);
                     vals[c] = (float)(int32_t)(hv >> 40) * 0x1p-24f;
+                } else if (kind == 2) {
+                    vals[c] = perlin_texel(seed, e, c, si, sj);
                 } else {
                     const int64_t a = si >> 3, b = sj >> 3;
                     const int32_t rx1 = kRamp[si & 7], ry1 = kRamp[sj & 7];
@@ -74,7 +104,7 @@ extern "C" int htexgen_fill_level0(int kind, uint64_t seed, int32_t E, const uin
                                    int channels, void *stream)
 {
     if (E <= 0) return 0;
-    if (kind != 0 && kind != 1) return -1;
+    if (kind < 0 || kind > 2) return -1;
     if (channels != 1 && channels != 4) return -1;
     const uint32_t grid = (uint32_t)(E < (1 << 20) ? E : (1 << 20));
     hipLaunchKernelGGL(k_fill, dim3(grid), dim3(256), 0, static_cast<hipStream_t>(stream), kind,

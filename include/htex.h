@@ -265,25 +265,39 @@ htex_status htex_sample_backward(const htex_mesh *mesh, const htex_pool *pool,
  * other order can be put in halfedge order so that neighbouring queries read
  * the same textures.  Sampling results do not depend on the order. */
 
-/* Bytes of device workspace htex_sort_queries needs for Q queries. */
-size_t htex_sort_workspace_bytes(int64_t Q);
+/* Bytes of device workspace htex_sort_queries and htex_sort_batch need for
+ * Q queries on a mesh of H halfedges. */
+size_t htex_sort_workspace_bytes(int32_t H, int64_t Q);
 
 /* perm[0..Q) = the stable ordering of the queries by h (queries with h
  * outside [0, H) last, in input order).  h: device int32 [Q]; perm: device
- * int32 [Q]; ws: device workspace of at least htex_sort_workspace_bytes(Q)
- * bytes, 256-byte aligned.  Q < 2^31. */
+ * int32 [Q]; ws: device workspace of at least htex_sort_workspace_bytes(H, Q)
+ * bytes, 256-byte aligned, not overlapping perm; its contents on entry do
+ * not matter.  Q < 2^31. */
 htex_status htex_sort_queries(int32_t H, int64_t Q, const int32_t *h, int32_t *perm, void *ws,
                               size_t ws_bytes, void *stream);
+
+/* The sorted batch itself in one call: perm as htex_sort_queries, and
+ * h_out[i] = h[perm[i]], likewise u_out, v_out and f_out (f_out only when
+ * `in` has footprints; it may be NULL otherwise).  The radix passes carry
+ * the queries with their keys, so no gather through perm follows.  Every
+ * output is device int32/float32 [Q], 4-byte aligned, and must not overlap
+ * the input arrays, each other or the workspace (HTEX_E_ARG otherwise).
+ * ws as for htex_sort_queries.  Q < 2^31. */
+htex_status htex_sort_batch(int32_t H, const htex_queries *in, int32_t *perm, int32_t *h_out,
+                            float *u_out, float *v_out, float *f_out, void *ws, size_t ws_bytes,
+                            void *stream);
 
 /* Sorted copy of a batch: h_out[i] = h[perm[i]], same for u, v and the
  * footprint (f_out may be NULL when the batch has none). */
 htex_status htex_permute_queries(const htex_queries *in, const int32_t *perm, int32_t *h_out,
                                  float *u_out, float *v_out, float *f_out, void *stream);
 
-/* Results back to input order: out[perm[i]] = in[i] (float32 Q x 4, both
- * 16-byte aligned, not overlapping). */
-htex_status htex_unpermute_results(int64_t Q, const int32_t *perm, const float *in, float *out,
-                                   void *stream);
+/* Results back to input order: row perm[i] of out = row i of in (float32,
+ * Q rows of `channels` (1 or 4) floats, both aligned to 4 channels bytes,
+ * not overlapping).  perm must be a permutation of [0, Q). */
+htex_status htex_unpermute_results(int64_t Q, int32_t channels, const int32_t *perm,
+                                   const float *in, float *out, void *stream);
 
 /* Prepared fetch descriptors: the halfedge navigation of Alg. 3 resolved
  * once per (mesh, pool) so that a query reads one record instead of walking
@@ -305,7 +319,10 @@ htex_status htex_prepare(const htex_mesh *mesh, const htex_pool *pool, void *pre
 /* Same result as htex_sample (bit for bit) from prepared descriptors: the
  * fast path for repeated sampling of one mesh.  `H` is the number of
  * halfedges the records cover (queries with h outside [0, H) are invalid as
- * in htex_sample).  No debug trace.  The HTEX_QUERIES_SCATTERED hint picks
+ * in htex_sample); the records buffer must hold H records.  A record whose
+ * fetches would read past pool->total_texels (records prepared for another
+ * pool layout) makes its query invalid (NaN row, *err_count incremented)
+ * instead of reading outside the pool.  No debug trace.  The HTEX_QUERIES_SCATTERED hint picks
  * the kernel: by default every tap of a sampled level is read, which suits
  * coherent batches (ordered by halfedge, or rasterized, where neighbouring
  * queries share the cache lines); with the hint only in-bounds taps are
@@ -350,7 +367,9 @@ htex_status htex_sample_aniso(const htex_mesh *mesh, const htex_pool *pool,
                               uint32_t flags, float *out, int32_t *nprobe, int32_t *err_count,
                               void *stream);
 
-/* The same from prepared records (htex_prepare), bit for bit. */
+/* The same from prepared records (htex_prepare), bit for bit; records that
+ * do not fit the pool make their queries invalid, as in
+ * htex_sample_prepared. */
 htex_status htex_sample_aniso_prepared(int32_t H, const void *prep, const htex_pool *pool,
                                        const htex_queries *queries, const float *jac,
                                        int32_t max_aniso, uint32_t flags, float *out,

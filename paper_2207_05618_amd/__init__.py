@@ -9,6 +9,7 @@ is no CPU path.
 from __future__ import annotations
 
 import ctypes as C
+import hashlib
 
 import numpy as np
 import torch
@@ -23,7 +24,8 @@ __all__ = ["Mesh", "Pool", "htex_pool_layout", "htex_mesh_validate", "htex_build
            "htex_quantize", "htex_sample", "htex_sample_backward", "HtexSample",
            "htex_prepare", "htex_sample_prepared", "Prepared",
            "htex_sample_aniso", "htex_sample_aniso_prepared",
-           "htex_sort_queries", "htex_permute_queries", "htex_unpermute_results",
+           "htex_sort_queries", "htex_sort_batch", "htex_permute_queries",
+           "htex_unpermute_results",
            "debug_records", "HtexError"]
 
 DEBUG_DTYPE = np.dtype(DEBUG_FIELDS)
@@ -73,6 +75,14 @@ def htex_pool_layout(log2res, has_mips: bool):
     return base[:E], int(total[0])
 
 
+def layout_key(log2res, has_mips: bool, total: int):
+    """What prepared records depend on: the pool's texel layout (edge count,
+    size, mips, per-edge resolutions) -- not the texels, their storage type
+    or their channel count."""
+    lr = np.ascontiguousarray(log2res, dtype=np.uint8)
+    return (len(lr), int(total), bool(has_mips), hashlib.sha256(lr.tobytes()).hexdigest())
+
+
 class Pool:
     """Per-edge texel pool on the device (layout of htex.h).
 
@@ -103,6 +113,7 @@ class Pool:
         if self.texels.shape != (total, self.channels):
             raise ValueError(f"texels must have shape ({total}, {self.channels})")
         self.scale = scale
+        self.layout_key = layout_key(lr, self.has_mips, total)
         if self.dtype == HTEX_FP8_E4M3:
             self.scale = _dev(scale, torch.float32, "scale") if scale is not None else \
                 torch.zeros(self.E, dtype=torch.float32, device=device)
@@ -193,13 +204,26 @@ def _queries(h, u, v, footprint):
     return q, Q
 
 
+def _rows(t, name, n, C_):
+    """Checks a float32 [n, C_] device tensor (a [n] vector when C_ == 1 is
+    accepted too)."""
+    _dev(t, torch.float32, name)
+    if t.numel() != n * C_ or (t.dim() == 2 and tuple(t.shape) != (n, C_)) or t.dim() > 2:
+        raise ValueError(f"{name} must have shape ({n}, {C_}), got {tuple(t.shape)}")
+    return t
+
+
+def _out(out, Q, pool, device):
+    if out is None:
+        return torch.empty((Q, pool.channels), dtype=torch.float32, device=device)
+    return _rows(out, "out", Q, pool.channels)
+
+
 def htex_sample(mesh: Mesh, pool: Pool, h, u, v, footprint=None, filter=HTEX_BILINEAR,
                 flags=0, out=None, debug=False, err_count=None, stream=None):
     """Alg. 3 for every query -> (out float32 [Q, C], debug int32 [Q, 40] or None)."""
     q, Q = _queries(h, u, v, footprint)
-    if out is None:
-        out = torch.empty((Q, pool.channels), dtype=torch.float32, device=h.device)
-    _dev(out, torch.float32, "out")
+    out = _out(out, Q, pool, h.device)
     dbg = torch.zeros((Q, 40), dtype=torch.int32, device=h.device) if debug else None
     if err_count is not None:
         _dev(err_count, torch.int32, "err_count")
@@ -212,7 +236,9 @@ def htex_sample(mesh: Mesh, pool: Pool, h, u, v, footprint=None, filter=HTEX_BIL
 
 
 class Prepared:
-    """Per-halfedge fetch records of one (mesh, pool layout) pair (device)."""
+    """Per-halfedge fetch records of one (mesh, pool layout) pair (device).
+    Keeps the layout it was built for (edge count, pool size, mips, the
+    per-edge resolutions): a pool of another layout is refused."""
 
     def __init__(self, mesh: Mesh, pool: Pool, stream=None):
         self.H = mesh.H
@@ -220,20 +246,26 @@ class Prepared:
         self.buf = torch.empty((n, 4), dtype=torch.int32, device=mesh.twin.device)
         htex_prepare(mesh, pool, self, stream)
 
+    def check_pool(self, pool: Pool):
+        if pool.layout_key != self.layout_key:
+            raise ValueError("prepared records were built for another pool layout "
+                             f"(E, texels, mips = {self.layout_key[:3]}; the pool has "
+                             f"{pool.layout_key[:3]}); rebuild them with Prepared(mesh, pool)")
+
 
 def htex_prepare(mesh: Mesh, pool: Pool, prep: "Prepared", stream=None):
     check(load().htex_prepare(C.byref(mesh.c), C.byref(pool.c), prep.buf.data_ptr(),
                               _stream(stream)))
+    prep.layout_key = pool.layout_key
 
 
 def htex_sample_prepared(prep: "Prepared", pool: Pool, h, u, v, footprint=None,
                          filter=HTEX_BILINEAR, flags=0, out=None, err_count=None,
                          stream=None):
     """htex_sample from prepared records (bit-identical results) -> out [Q, C]."""
+    prep.check_pool(pool)
     q, Q = _queries(h, u, v, footprint)
-    if out is None:
-        out = torch.empty((Q, pool.channels), dtype=torch.float32, device=h.device)
-    _dev(out, torch.float32, "out")
+    out = _out(out, Q, pool, h.device)
     if err_count is not None:
         _dev(err_count, torch.int32, "err_count")
     check(load().htex_sample_prepared(prep.H, prep.buf.data_ptr(), C.byref(pool.c), C.byref(q),
@@ -252,9 +284,7 @@ def htex_sample_aniso(mesh: Mesh, pool: Pool, h, u, v, jac, max_aniso: int = 16,
     _dev(jac, torch.float32, "jac")
     if jac.numel() != 4 * Q:
         raise ValueError("jac must hold 4 floats per query")
-    if out is None:
-        out = torch.empty((Q, pool.channels), dtype=torch.float32, device=h.device)
-    _dev(out, torch.float32, "out")
+    out = _out(out, Q, pool, h.device)
     n = torch.zeros(Q, dtype=torch.int32, device=h.device) if nprobe else None
     if err_count is not None:
         _dev(err_count, torch.int32, "err_count")
@@ -269,13 +299,12 @@ def htex_sample_aniso(mesh: Mesh, pool: Pool, h, u, v, jac, max_aniso: int = 16,
 def htex_sample_aniso_prepared(prep: "Prepared", pool: Pool, h, u, v, jac, max_aniso: int = 16,
                                flags=0, out=None, err_count=None, stream=None):
     """htex_sample_aniso from prepared records (bit-identical) -> out [Q, C]."""
+    prep.check_pool(pool)
     q, Q = _queries(h, u, v, None)
     _dev(jac, torch.float32, "jac")
     if jac.numel() != 4 * Q:
         raise ValueError("jac must hold 4 floats per query")
-    if out is None:
-        out = torch.empty((Q, pool.channels), dtype=torch.float32, device=h.device)
-    _dev(out, torch.float32, "out")
+    out = _out(out, Q, pool, h.device)
     if err_count is not None:
         _dev(err_count, torch.int32, "err_count")
     check(load().htex_sample_aniso_prepared(prep.H, prep.buf.data_ptr(), C.byref(pool.c),
@@ -286,22 +315,43 @@ def htex_sample_aniso_prepared(prep: "Prepared", pool: Pool, h, u, v, jac, max_a
     return out
 
 
+def _sort_ws(H, Q, device):
+    nbytes = int(load().htex_sort_workspace_bytes(int(H), Q))
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device), nbytes
+
+
 def htex_sort_queries(H: int, h, stream=None):
     """perm (int32 [Q], device): the stable order of the queries by halfedge."""
     h = _dev(h, torch.int32, "h")
     Q = h.numel()
     perm = torch.empty(Q, dtype=torch.int32, device=h.device)
-    nbytes = int(load().htex_sort_workspace_bytes(Q))
-    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=h.device)
+    ws, nbytes = _sort_ws(H, Q, h.device)
     check(load().htex_sort_queries(int(H), Q, h.data_ptr(), perm.data_ptr(), ws.data_ptr(),
                                    nbytes, _stream(stream)))
     return perm
+
+
+def htex_sort_batch(H: int, h, u, v, footprint=None, stream=None):
+    """(perm, h, u, v, footprint) of the batch in halfedge order, in one call:
+    the radix passes carry the queries with their keys."""
+    q, Q = _queries(h, u, v, footprint)
+    perm = torch.empty(Q, dtype=torch.int32, device=h.device)
+    ho, uo, vo = torch.empty_like(h), torch.empty_like(u), torch.empty_like(v)
+    fo = torch.empty_like(footprint) if footprint is not None else None
+    ws, nbytes = _sort_ws(H, Q, h.device)
+    check(load().htex_sort_batch(int(H), C.byref(q), perm.data_ptr(), ho.data_ptr(),
+                                 uo.data_ptr(), vo.data_ptr(),
+                                 fo.data_ptr() if fo is not None else None, ws.data_ptr(),
+                                 nbytes, _stream(stream)))
+    return perm, ho, uo, vo, fo
 
 
 def htex_permute_queries(perm, h, u, v, footprint=None, stream=None):
     """(h, u, v, footprint) gathered into the order `perm`."""
     q, Q = _queries(h, u, v, footprint)
     _dev(perm, torch.int32, "perm")
+    if perm.numel() != Q:
+        raise ValueError("perm must hold one index per query")
     ho = torch.empty_like(h)
     uo = torch.empty_like(u)
     vo = torch.empty_like(v)
@@ -313,12 +363,18 @@ def htex_permute_queries(perm, h, u, v, footprint=None, stream=None):
 
 
 def htex_unpermute_results(perm, out_sorted, out=None, stream=None):
-    """Results of a permuted batch back in input order."""
+    """Results of a permuted batch back in input order (rows of 1 or 4
+    floats)."""
     _dev(perm, torch.int32, "perm")
     _dev(out_sorted, torch.float32, "out_sorted")
+    Q = perm.numel()
+    if out_sorted.dim() != 2 or out_sorted.shape[0] != Q or out_sorted.shape[1] not in (1, 4):
+        raise ValueError(f"out_sorted must have shape ({Q}, 1) or ({Q}, 4)")
+    ch = int(out_sorted.shape[1])
     if out is None:
         out = torch.empty_like(out_sorted)
-    check(load().htex_unpermute_results(perm.numel(), perm.data_ptr(), out_sorted.data_ptr(),
+    _rows(out, "out", Q, ch)
+    check(load().htex_unpermute_results(Q, ch, perm.data_ptr(), out_sorted.data_ptr(),
                                         out.data_ptr(), _stream(stream)))
     return out
 
@@ -333,10 +389,10 @@ def htex_sample_backward(mesh: Mesh, pool: Pool, h, u, v, dout, footprint=None,
                          filter=HTEX_BILINEAR, flags=0, dtexels=None, stream=None):
     """dtexels (float32, pool-shaped) += transpose of htex_sample applied to dout."""
     q, Q = _queries(h, u, v, footprint)
-    _dev(dout, torch.float32, "dout")
+    _rows(dout, "dout", Q, pool.channels)
     if dtexels is None:
         dtexels = torch.zeros_like(pool.texels, dtype=torch.float32)
-    _dev(dtexels, torch.float32, "dtexels")
+    _rows(dtexels, "dtexels", pool.total, pool.channels)
     check(load().htex_sample_backward(C.byref(mesh.c), C.byref(pool.c), C.byref(q),
                                       int(filter), int(flags), dout.data_ptr(),
                                       dtexels.data_ptr(), _stream(stream)))

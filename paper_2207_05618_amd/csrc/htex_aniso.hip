@@ -165,8 +165,15 @@ __global__ void __launch_bounds__(kBlock) k_aniso(SampleArgs a, const float4 *ja
         v = __builtin_nontemporal_load(a.qv + q);
         J = jac[q];
     }
-    const bool valid = live && (uint32_t)h < (uint32_t)a.H && isfinite(u) && isfinite(v) &&
-                       isfinite(J.x) && isfinite(J.y) && isfinite(J.z) && isfinite(J.w);
+    bool valid = live && (uint32_t)h < (uint32_t)a.H && isfinite(u) && isfinite(v) &&
+                 isfinite(J.x) && isfinite(J.y) && isfinite(J.z) && isfinite(J.w);
+    PrepRec rec = PrepRec{};
+    if constexpr (PREP) {
+        if (valid) {
+            rec = static_cast<const PrepRec *>(a.prep)[h];
+            valid = record_in_pool(rec, a.total_texels, a.has_mips != 0);
+        }
+    }
     if (live && !valid) {
         const float nan = __uint_as_float(0x7fc00000u);
         store_row<CH>(a.out, q, nan, nan, nan, nan);
@@ -179,7 +186,6 @@ __global__ void __launch_bounds__(kBlock) k_aniso(SampleArgs a, const float4 *ja
         uint64_t w[3];
         int32_t e[3];
         if constexpr (PREP) {
-            const PrepRec rec = static_cast<const PrepRec *>(a.prep)[h];
 #pragma unroll
             for (int f = 0; f < 3; ++f) {
                 w[f] = rec.w[f];

@@ -353,20 +353,91 @@ htex_status htex_sample_backward(const htex_mesh *mesh, const htex_pool *pool,
                     "backward launch");
 }
 
-size_t htex_sort_workspace_bytes(int64_t Q) { return htex::sort_workspace_bytes(Q < 0 ? 0 : Q); }
+size_t htex_sort_workspace_bytes(int32_t H, int64_t Q)
+{
+    return htex::sort_workspace_bytes(H < 0 ? 0 : H, Q < 0 ? 0 : Q);
+}
+
+namespace {
+
+// Whether [a, a + an) and [b, b + bn) (bytes) overlap; NULL ranges never do.
+bool overlap(const void *a, size_t an, const void *b, size_t bn)
+{
+    if (!a || !b) return false;
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bn && y < x + an;
+}
+
+htex_status check_sort(int32_t H, int64_t Q, const void *ws, size_t ws_bytes)
+{
+    if (H < 0 || Q < 0) return fail(HTEX_E_ARG, "negative size");
+    if (Q >= (int64_t(1) << 31)) return fail(HTEX_E_RANGE, "sorting needs Q < 2^31");
+    if (Q > 0) {
+        if (!ws) return fail(HTEX_E_ARG, "workspace is NULL");
+        if (!aligned(ws, 256)) return fail(HTEX_E_ARG, "workspace must be 256-byte aligned");
+        const size_t need = htex::sort_workspace_bytes(H, Q);
+        if (ws_bytes < need)
+            return fail(HTEX_E_ARG, "workspace of %zu bytes is smaller than the %zu needed",
+                        ws_bytes, need);
+    }
+    return HTEX_OK;
+}
+
+// The sorted batch must not overlap the batch it comes from or the
+// workspace (the radix passes scatter; they cannot run in place).
+htex_status check_sort_batch(const htex_queries *in, const int32_t *perm, const int32_t *h_out,
+                             const float *u_out, const float *v_out, const float *f_out,
+                             const void *ws, size_t ws_bytes)
+{
+    if (!in) return fail(HTEX_E_ARG, "queries is NULL");
+    if (in->Q == 0) return HTEX_OK;
+    if (!in->h || !in->u || !in->v || !perm || !h_out || !u_out || !v_out)
+        return fail(HTEX_E_ARG, "NULL argument");
+    if (in->footprint && !f_out) return fail(HTEX_E_ARG, "f_out is NULL");
+    const size_t n = 4 * (size_t)in->Q;
+    const void *outs[5] = {perm, h_out, u_out, v_out, in->footprint ? f_out : nullptr};
+    const void *ins[4] = {in->h, in->u, in->v, in->footprint};
+    for (int i = 0; i < 5; ++i) {
+        if (outs[i] && !aligned(outs[i], 4)) return fail(HTEX_E_ARG, "outputs must be 4-byte aligned");
+        for (int j = 0; j < 4; ++j)
+            if (overlap(outs[i], n, ins[j], n))
+                return fail(HTEX_E_ARG, "sorted outputs must not overlap the input batch");
+        for (int j = i + 1; j < 5; ++j)
+            if (overlap(outs[i], n, outs[j], n))
+                return fail(HTEX_E_ARG, "sorted outputs must not overlap each other");
+        if (overlap(outs[i], n, ws, ws_bytes))
+            return fail(HTEX_E_ARG, "sorted outputs must not overlap the workspace");
+    }
+    return HTEX_OK;
+}
+
+}  // namespace
 
 htex_status htex_sort_queries(int32_t H, int64_t Q, const int32_t *h, int32_t *perm, void *ws,
                               size_t ws_bytes, void *stream)
 {
-    if (H < 0 || Q < 0) return fail(HTEX_E_ARG, "negative size");
-    if (Q >= (int64_t(1) << 31)) return fail(HTEX_E_RANGE, "sorting needs Q < 2^31");
+    if (htex_status st = check_sort(H, Q, ws, ws_bytes)) return st;
     if (Q == 0) return ok();
-    if (!h || !perm || !ws) return fail(HTEX_E_ARG, "NULL argument");
-    if (!aligned(ws, 256)) return fail(HTEX_E_ARG, "workspace must be 256-byte aligned");
-    if (ws_bytes < htex::sort_workspace_bytes(Q))
-        return fail(HTEX_E_ARG, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
-                    htex::sort_workspace_bytes(Q));
-    return from_hip(htex::launch_sort(h, H, Q, perm, ws, static_cast<hipStream_t>(stream)),
+    if (!h || !perm) return fail(HTEX_E_ARG, "NULL argument");
+    if (overlap(perm, 4 * (size_t)Q, ws, ws_bytes))
+        return fail(HTEX_E_ARG, "perm must not overlap the workspace");
+    return from_hip(htex::launch_sort(H, Q, h, nullptr, nullptr, nullptr, perm, nullptr, nullptr,
+                                      nullptr, nullptr, ws, static_cast<hipStream_t>(stream)),
+                    "sort launch");
+}
+
+htex_status htex_sort_batch(int32_t H, const htex_queries *in, int32_t *perm, int32_t *h_out,
+                            float *u_out, float *v_out, float *f_out, void *ws, size_t ws_bytes,
+                            void *stream)
+{
+    if (!in) return fail(HTEX_E_ARG, "queries is NULL");
+    if (htex_status st = check_sort(H, in->Q, ws, ws_bytes)) return st;
+    if (htex_status st = check_sort_batch(in, perm, h_out, u_out, v_out, f_out, ws, ws_bytes))
+        return st;
+    if (in->Q == 0) return ok();
+    return from_hip(htex::launch_sort(H, in->Q, in->h, in->u, in->v, in->footprint, perm, h_out,
+                                      u_out, v_out, in->footprint ? f_out : nullptr, ws,
+                                      static_cast<hipStream_t>(stream)),
                     "sort launch");
 }
 
@@ -385,15 +456,19 @@ htex_status htex_permute_queries(const htex_queries *in, const int32_t *perm, in
                     "permute launch");
 }
 
-htex_status htex_unpermute_results(int64_t Q, const int32_t *perm, const float *in, float *out,
-                                   void *stream)
+htex_status htex_unpermute_results(int64_t Q, int32_t channels, const int32_t *perm,
+                                   const float *in, float *out, void *stream)
 {
     if (Q < 0) return fail(HTEX_E_ARG, "negative Q");
+    if (channels != 1 && channels != 4) return fail(HTEX_E_ARG, "channels must be 1 or 4");
     if (Q == 0) return ok();
-    if (!perm || !in || !out || !aligned(in, 16) || !aligned(out, 16))
-        return fail(HTEX_E_ARG, "in/out must be non-NULL and 16-byte aligned");
-    if (in == out) return fail(HTEX_E_ARG, "in and out must not overlap");
-    return from_hip(htex::launch_unpermute(perm, Q, in, out, static_cast<hipStream_t>(stream)),
+    const size_t row = 4 * (size_t)channels;
+    if (!perm || !in || !out || !aligned(in, row) || !aligned(out, row))
+        return fail(HTEX_E_ARG, "in/out must be non-NULL and %zu-byte aligned", row);
+    if (overlap(in, row * (size_t)Q, out, row * (size_t)Q))
+        return fail(HTEX_E_ARG, "in and out must not overlap");
+    return from_hip(htex::launch_unpermute(perm, Q, channels, in, out,
+                                           static_cast<hipStream_t>(stream)),
                     "unpermute launch");
 }
 
@@ -411,9 +486,12 @@ htex_status htex_prepare(const htex_mesh *mesh, const htex_pool *pool, void *pre
     return from_hip(htex::launch_prepare(a, prep, static_cast<hipStream_t>(stream)), "prepare launch");
 }
 
-htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *pool,
-                                 const htex_queries *queries, int32_t filter, uint32_t flags,
-                                 float *out, int32_t *err_count, void *stream)
+namespace {
+
+// Checks and launch arguments shared by the prepared sampling entry points.
+htex_status prepared_args(int32_t H, const void *prep, const htex_pool *pool,
+                          const htex_queries *queries, int32_t filter, uint32_t flags,
+                          float *out, int32_t *err_count, htex::SampleArgs *a)
 {
     htex_status st = check_pool(pool, nullptr);
     if (!st) st = check_queries(queries, filter);
@@ -428,19 +506,27 @@ htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *p
         if (!out || !aligned(out, 4 * (size_t)pool->channels))
             return fail(HTEX_E_ARG, "out must be %d-byte aligned", 4 * pool->channels);
     }
-    htex::SampleArgs a{};
-    a.H = H;
-    a.channels = pool->channels;
-    a.texels = pool->texels;
-    a.scale = pool->scale;
-    a.Q = queries->Q;
-    a.qh = queries->h;
-    a.qu = queries->u;
-    a.qv = queries->v;
-    a.qf = queries->footprint;
-    a.out = out;
-    a.err = err_count;
-    a.prep = prep;
+    *a = htex::SampleArgs{};
+    a->H = H;
+    a->channels = pool->channels;
+    a->texels = pool->texels;
+    a->scale = pool->scale;
+    a->has_mips = pool->has_mips;
+    a->total_texels = pool->total_texels;
+    a->Q = queries->Q;
+    a->qh = queries->h;
+    a->qu = queries->u;
+    a->qv = queries->v;
+    a->qf = queries->footprint;
+    a->out = out;
+    a->err = err_count;
+    a->prep = prep;
+    return HTEX_OK;
+}
+
+htex_status launch_prepared(const htex::SampleArgs &a, const htex_pool *pool, int32_t filter,
+                            uint32_t flags, void *stream)
+{
     // a pool that fits the 256 MB fabric-side cache leaves the sampler
     // bound by the VALU rather than by memory
     const bool resident = pool->total_texels * (int64_t)texel_bytes(pool->dtype, pool->channels) <=
@@ -449,6 +535,18 @@ htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *p
                                                  (flags & HTEX_QUERIES_SCATTERED) != 0, resident,
                                                  static_cast<hipStream_t>(stream)),
                     "prepared sample launch");
+}
+
+}  // namespace
+
+htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *pool,
+                                 const htex_queries *queries, int32_t filter, uint32_t flags,
+                                 float *out, int32_t *err_count, void *stream)
+{
+    htex::SampleArgs a;
+    if (htex_status st = prepared_args(H, prep, pool, queries, filter, flags, out, err_count, &a))
+        return st;
+    return launch_prepared(a, pool, filter, flags, stream);
 }
 
 namespace {
@@ -514,6 +612,8 @@ htex_status htex_sample_aniso_prepared(int32_t H, const void *prep, const htex_p
     a.channels = pool->channels;
     a.texels = pool->texels;
     a.scale = pool->scale;
+    a.has_mips = pool->has_mips;
+    a.total_texels = pool->total_texels;
     a.Q = queries->Q;
     a.qh = queries->h;
     a.qu = queries->u;

@@ -403,6 +403,27 @@ struct alignas(16) PrepRec {
 };
 static_assert(sizeof(PrepRec) == HTEX_PREP_BYTES, "record size");
 
+// Whether the three fetches of record r stay inside a pool of `total`
+// texels laid out with (`mips`) or without mip levels: each fetch's edge,
+// all of its levels, must end at or before `total`.  A record prepared for
+// another pool layout then cannot make a kernel read outside the pool; its
+// query is answered as invalid instead.
+__device__ __forceinline__ bool record_in_pool(const PrepRec &r, int64_t total, bool mips)
+{
+    bool ok = true;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const uint32_t k = (uint32_t)(r.w[s] >> 40) & 31u;
+        const uint32_t kk = k > 15u ? 15u : k;
+        // texels of an edge: (4^(k+1) - 1) / 3 with mips (bit pattern
+        // 0101...01 of k + 1 pairs), 4^k without
+        const uint32_t ext = mips ? (0x55555555u >> (30u - 2u * kk)) : (1u << (2u * kk));
+        const int64_t end = (int64_t)(r.w[s] & 0xffffffffffull) + (int64_t)ext;
+        ok = ok & (k <= 15u) & (end <= total);
+    }
+    return ok;
+}
+
 template <int DT, int CH>
 __device__ __forceinline__ Resolved resolve_prepared(const SampleArgs &a, uint64_t w, int32_t e)
 {

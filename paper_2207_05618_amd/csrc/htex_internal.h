@@ -31,6 +31,8 @@ struct SampleArgs {
     float *dtex;                // backward: pool-shaped float32
     const void *prep;           // prepared descriptors (fast path), nullable
     int32_t channels;           // values per texel and per output row: 4 or 1
+    int32_t has_mips;           // prepared path: the pool's layout has mip levels
+    int64_t total_texels;       // prepared path: size of the pool in texels
 };
 
 // Offset of mip level l inside an edge of log2 resolution k, in texels:
@@ -74,8 +76,9 @@ struct ServeMesh {
     const void *prep;
     const void *texels;
     const float *scale;
+    int64_t total_texels;
     int32_t H;
-    int32_t pad;
+    int32_t has_mips;
 };
 
 struct ServeTile {
@@ -89,14 +92,17 @@ struct ServeTile {
 constexpr int kTileQueries = 256;
 
 hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t s);
-size_t sort_workspace_bytes(int64_t Q);
-hipError_t launch_sort(const int32_t *h, int32_t H, int64_t Q, int32_t *perm, void *ws,
-                       hipStream_t s);
+size_t sort_workspace_bytes(int32_t H, int64_t Q);
+// Sorts by halfedge: perm, and (when u_out is non-NULL) the sorted u, v and
+// (when f_out is non-NULL) footprint; h_out may be NULL.
+hipError_t launch_sort(int32_t H, int64_t Q, const int32_t *h, const float *u, const float *v,
+                       const float *f, int32_t *perm, int32_t *h_out, float *u_out, float *v_out,
+                       float *f_out, void *ws, hipStream_t s);
 hipError_t launch_gather_queries(const int32_t *perm, int64_t Q, const int32_t *h, const float *u,
                                  const float *v, const float *f, int32_t *ho, float *uo, float *vo,
                                  float *fo, hipStream_t s);
-hipError_t launch_unpermute(const int32_t *perm, int64_t Q, const float *in, float *out,
-                            hipStream_t s);
+hipError_t launch_unpermute(const int32_t *perm, int64_t Q, int channels, const float *in,
+                            float *out, hipStream_t s);
 hipError_t launch_serve(const ServeMesh *meshes, const ServeTile *tiles, int32_t ntiles,
                         int32_t grid, int dtype, int channels, int filter, int32_t *err,
                         hipStream_t s);

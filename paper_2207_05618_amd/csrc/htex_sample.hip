@@ -80,20 +80,26 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a)
 // batch kernel and the serving kernel, so a query's result does not depend
 // on which launch, batch or tile computes it.
 // SCATTERED selects the per-tap predicated fetch for batches in random
-// order (same results).
+// order (same results).  A record that does not fit the pool (prepared for
+// another layout) makes its query invalid.
 template <int DT, int CH, bool TRI, bool SCATTERED>
 __device__ __forceinline__ void sample_one_prepared(const SampleArgs &a, int64_t q)
 {
     const int32_t h = __builtin_nontemporal_load(a.qh + q);
     const float u = __builtin_nontemporal_load(a.qu + q);
     const float v = __builtin_nontemporal_load(a.qv + q);
-    if (!((uint32_t)h < (uint32_t)a.H) || !isfinite(u) || !isfinite(v)) {
+    PrepRec rec;
+    bool valid = ((uint32_t)h < (uint32_t)a.H) && isfinite(u) && isfinite(v);
+    if (valid) {
+        rec = static_cast<const PrepRec *>(a.prep)[h];
+        valid = record_in_pool(rec, a.total_texels, a.has_mips != 0);
+    }
+    if (!valid) {
         const float nan = __uint_as_float(0x7fc00000u);
         store_row<CH>(a.out, q, nan, nan, nan, nan);
         if (a.err) atomicAdd(a.err, 1);
         return;
     }
-    const PrepRec rec = static_cast<const PrepRec *>(a.prep)[h];
     Lod L{0, 0, 0.0f, 1.0f};
     if constexpr (TRI) L = lod_of(__builtin_nontemporal_load(a.qf + q));
     FetchSpec fs[3];
@@ -175,15 +181,18 @@ __device__ __forceinline__ void sample_wave_prepared(const SampleArgs &a, int64_
         v = __builtin_nontemporal_load(a.qv + q);
         if constexpr (TRI) f = __builtin_nontemporal_load(a.qf + q);
     }
-    const bool valid = live && ((uint32_t)h < (uint32_t)a.H) && isfinite(u) && isfinite(v);
+    bool valid = live && ((uint32_t)h < (uint32_t)a.H) && isfinite(u) && isfinite(v);
+    PrepRec rec = PrepRec{};
+    if (valid) {
+        rec = static_cast<const PrepRec *>(a.prep)[h];
+        valid = record_in_pool(rec, a.total_texels, a.has_mips != 0);
+        if (!valid) rec = PrepRec{};
+    }
     if (live && !valid) {
         const float nan = __uint_as_float(0x7fc00000u);
         store_row<CH>(a.out, q, nan, nan, nan, nan);
         if (a.err) atomicAdd(a.err, 1);
     }
-    PrepRec rec;
-    if (valid) rec = static_cast<const PrepRec *>(a.prep)[h];
-    else rec = PrepRec{};
     Lod L{0, 0, 0.0f, 1.0f};
     if constexpr (TRI) L = lod_of(f);
     // the Next and Prev fetches this query may need, posted as tasks
@@ -303,6 +312,8 @@ __global__ void __launch_bounds__(kBlock) k_serve(const ServeMesh *meshes, const
             SampleArgs a{};
             a.H = M.H;
             a.prep = M.prep;
+            a.total_texels = M.total_texels;
+            a.has_mips = M.has_mips;
             a.texels = M.texels;
             a.scale = M.scale;
             a.Q = T.q0 + T.count;

@@ -533,7 +533,7 @@ htex_status htex_server_add_mesh(htex_server *S, int32_t H, const void *prep, co
         return fail(HTEX_E_ARG, "pool arrays missing");
     std::lock_guard<std::mutex> lk(S->mu);
     if ((int)S->meshes.size() >= S->cfg.max_meshes) return fail(HTEX_E_RANGE, "mesh table full");
-    htex::ServeMesh m{prep, pool->texels, pool->scale, H, 0};
+    htex::ServeMesh m{prep, pool->texels, pool->scale, pool->total_texels, H, pool->has_mips};
     const int id = (int)S->meshes.size();
     // the scheduler only reads entries of meshes already registered, and a
     // request can name a mesh only after this call returns

@@ -36,6 +36,7 @@ class Server:
         self._meshes = []
 
     def add_mesh(self, prep, pool) -> int:
+        prep.check_pool(pool)
         mid = C.c_int32()
         check(load().htex_server_add_mesh(self._h, prep.H, prep.buf.data_ptr(),
                                           C.byref(pool.c), C.byref(mid)))
@@ -51,8 +52,20 @@ class Server:
     def submit(self, mesh_id, h, u, v, f=None, out=None) -> int:
         """h, u, v, f: page-locked CPU tensors; returns the request id."""
         Q = h.numel()
+        want = [(h, torch.int32, "h"), (u, torch.float32, "u"), (v, torch.float32, "v")]
+        if f is not None:
+            want.append((f, torch.float32, "f"))
+        for t, dt, name in want:
+            if not isinstance(t, torch.Tensor) or t.is_cuda or t.dtype != dt:
+                raise TypeError(f"{name} must be a CPU {dt} tensor")
+            if not t.is_contiguous() or t.numel() != Q:
+                raise ValueError(f"{name} must be contiguous with {Q} entries")
         if out is None:
             out = torch.empty((Q, self.channels), dtype=torch.float32, pin_memory=True)
+        if (not isinstance(out, torch.Tensor) or out.is_cuda or out.dtype != torch.float32
+                or not out.is_contiguous() or out.numel() != Q * self.channels):
+            raise ValueError(f"out must be a contiguous CPU float32 tensor of {Q} x "
+                             f"{self.channels} values")
         rid = C.c_int64()
         check(load().htex_server_submit(self._h, int(mesh_id), Q, h.data_ptr(), u.data_ptr(),
                                         v.data_ptr(), f.data_ptr() if f is not None else None,

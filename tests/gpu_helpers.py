@@ -73,8 +73,11 @@ def assert_debug_equal(dg, do, wtol=1e-5):
     valid = dg["next"] >= 0
     np.testing.assert_allclose(dg["W"][valid], do["W"][valid], rtol=wtol, atol=1e-6)
     np.testing.assert_allclose(dg["wf"][valid], do["wf"][valid], rtol=wtol, atol=1e-6)
-    # phi = log2(m) from a float32 series with a hardware reciprocal: a few
-    # float32 ulps near 1 (it enters the colour linearly, far inside 1e-5)
+    # phi = log2(m) from a float32 series on s = (m - 1) rcp(m + 1): the
+    # rounding of m + 1 (2^-24), the hardware reciprocal (1 ulp, 2^-23), the
+    # product (2^-24) and the Horner evaluation (about 2.5 2^-24) bound its
+    # error by ~3.9e-7 relative, and phi < 1 (it enters the colour linearly,
+    # far inside 1e-5)
     np.testing.assert_allclose(dg["phi"][valid], do["phi"][valid], rtol=0, atol=4e-7)
 
 

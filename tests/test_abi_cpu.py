@@ -190,3 +190,61 @@ def test_server_config_is_checked_before_any_device_call(field, value):
     assert L.htex_server_create(C.byref(cfg), C.byref(h)) == -1
     assert not h.value
     assert L.htex_last_error().decode() != ""
+
+
+def test_sort_argument_checks():
+    """Sorting refuses a short or misaligned workspace, outputs that overlap
+    the input batch, and oversized batches, before launching."""
+    L = _lib.load()
+    H, Q = 392, 1000
+    need = L.htex_sort_workspace_bytes(H, Q)
+    assert need > 0
+    # larger H needs more digit passes, hence at least as much workspace
+    assert L.htex_sort_workspace_bytes(1 << 30, Q) >= need
+    ws = 1 << 20
+    assert L.htex_sort_queries(H, Q, 16, 16 << 20, ws, need - 1, None) == -1
+    assert L.htex_sort_queries(H, Q, 16, 16 << 20, ws + 4, need, None) == -1
+    assert L.htex_sort_queries(H, Q, 16, 16 << 20, None, need, None) == -1
+    assert L.htex_sort_queries(H, 1 << 31, 16, 16 << 20, ws, 1 << 40, None) == -3
+    # perm inside the workspace
+    assert L.htex_sort_queries(H, Q, 16, ws + 256, ws, need, None) == -1
+    q = _lib.htex_queries(Q, 1 << 24, 2 << 24, 3 << 24, None)
+    outs = [5 << 24, 6 << 24, 7 << 24, 8 << 24]
+    # an output aliasing an input array is refused
+    assert L.htex_sort_batch(H, C.byref(q), 5 << 24, 1 << 24, 7 << 24, 8 << 24, None, ws, need,
+                             None) == -1
+    # two outputs overlapping each other
+    assert L.htex_sort_batch(H, C.byref(q), 5 << 24, 5 << 24, 7 << 24, 8 << 24, None, ws, need,
+                             None) == -1
+    # a footprint without f_out
+    qf = _lib.htex_queries(Q, 1 << 24, 2 << 24, 3 << 24, 4 << 24)
+    assert L.htex_sort_batch(H, C.byref(qf), *outs, None, ws, need, None) == -1
+    assert L.htex_last_error().decode() != ""
+
+
+def test_unpermute_checks():
+    L = _lib.load()
+    # channels must be 1 or 4; rows aligned to their width; no overlap
+    assert L.htex_unpermute_results(10, 2, 16, 1 << 20, 2 << 20, None) == -1
+    assert L.htex_unpermute_results(10, 4, 16, (1 << 20) + 4, 2 << 20, None) == -1
+    assert L.htex_unpermute_results(10, 1, 16, 1 << 20, (1 << 20) + 8, None) == -1
+    assert L.htex_last_error().decode() != ""
+
+
+def test_prepared_records_remember_their_layout():
+    """Prepared records are refused for a pool of another layout: the key
+    changes with the per-edge resolutions, the mips and the size, but not
+    with the storage type."""
+    import types
+    lr = np.array([4, 5, 4], np.uint8)
+    base, total = htex.htex_pool_layout(lr, True)
+    k = htex.layout_key(lr, True, total)
+    assert k == htex.layout_key(lr.copy(), True, total)
+    lr2 = np.array([5, 4, 4], np.uint8)
+    assert htex.layout_key(lr2, True, htex.htex_pool_layout(lr2, True)[1]) != k
+    assert htex.layout_key(lr, False, htex.htex_pool_layout(lr, False)[1]) != k
+    prep = htex.Prepared.__new__(htex.Prepared)
+    prep.layout_key = k
+    prep.check_pool(types.SimpleNamespace(layout_key=k))
+    with pytest.raises(ValueError, match="another pool layout"):
+        prep.check_pool(types.SimpleNamespace(layout_key=htex.layout_key(lr2, True, total)))

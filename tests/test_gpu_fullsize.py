@@ -16,6 +16,7 @@ from htexgen import device as gdev
 from htexgen import pool as gpool
 from htexgen.mesh import sphere_mesh
 from htexgen.queries import uniform_queries
+from htexgen.texels import PERLIN
 from tests.gpu_helpers import assert_debug_equal, assert_rel, t
 
 pytestmark = pytest.mark.gpu
@@ -26,7 +27,7 @@ def frame():
     mesh = sphere_mesh(n=183, seed=201)
     lr = np.full(mesh.E, 6, np.uint8)
     pool = htex.Pool(lr, True, htex.HTEX_F32)
-    gdev.fill_level0(pool.texels, 1, 202, pool.log2res, pool.base, mesh.boundary_edges())
+    gdev.fill_level0(pool.texels, PERLIN, 202, pool.log2res, pool.base, mesh.boundary_edges())
     htex.htex_build_mips(pool)
     q = uniform_queries(mesh.H, 3840 * 2160, 203, log2f=(-3.2, -1.2), sort=True)
     dm = htex.Mesh.of(mesh)
@@ -54,7 +55,7 @@ def _oracle_for(mesh, lr, qs):
     n = 1 << int(sub[0])
     jj, ii = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
     for chunk in np.array_split(np.arange(len(edges)), max(1, len(edges) // 256)):
-        vals = texel_values(1, 202, edges[chunk][:, None, None], n, bnd[chunk][:, None, None],
+        vals = texel_values(PERLIN, 202, edges[chunk][:, None, None], n, bnd[chunk][:, None, None],
                             ii.reshape(-1)[None, :, None], jj.reshape(-1)[None, :, None],
                             np.arange(4)[None, None, :])
         rows = base[chunk][:, None] + np.arange(n * n)[None, :]
@@ -118,6 +119,17 @@ def test_frame_prepared_equals_plain(frame):
                                    flags=htex.HTEX_QUERIES_SCATTERED)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(o3.cpu().numpy(), out[perm])
+    # the sort path the benchmark times on the shuffled frame: sort the batch
+    # in one call, sample it sorted, results back to the shuffled order
+    hu, uu, vu, fu = t(qu.h), t(qu.u), t(qu.v), t(qu.f)
+    del o2, o3
+    p4, h4, u4, v4, f4 = htex.htex_sort_batch(mesh.H, hu, uu, vu, fu)
+    o4s = htex.htex_sample_prepared(prep, pool, h4, u4, v4, f4, filter=htex.HTEX_TRILINEAR,
+                                    flags=htex.HTEX_QUERIES_SORTED)
+    o4 = htex.htex_unpermute_results(p4, o4s)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(p4.cpu().numpy(), np.argsort(qu.h, kind="stable"))
+    np.testing.assert_array_equal(o4.cpu().numpy(), out[perm])
 
 
 def test_frame_quantized_error_bounds(frame):

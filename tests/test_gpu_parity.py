@@ -424,7 +424,7 @@ def test_device_fill_matches_host_generator():
     m = cube_mesh(n=3, seed=5, n_split=4, n_merge=2)
     rng = np.random.default_rng(1)
     lr = rng.integers(0, 7, m.E).astype(np.uint8)
-    for kind in (0, 1):
+    for kind in (0, 1, 2):
         base, total = gpool.layout(lr, True)
         ref = gpool.fill_level0_host(kind, 77, lr, base, total, m.boundary_edges(), True)
         dev = torch.zeros((total, 4), dtype=torch.float32, device="cuda")
