@@ -288,6 +288,25 @@ htex_status htex_sort_batch(int32_t H, const htex_queries *in, int32_t *perm, in
                             float *u_out, float *v_out, float *f_out, void *ws, size_t ws_bytes,
                             void *stream);
 
+/* htex_sort_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no workspace argument; the radix passes use a scratch array
+ * compiled into the library instead.  Same outputs as htex_sort_batch, bit
+ * for bit.  Calls no hipMalloc, hipFree or allocating library routine.
+ * Limits: at most HTEX_SORT_NOALLOC_MAX_Q queries (HTEX_E_RANGE above); the
+ * array takes HTEX_SORT_NOALLOC_SCRATCH_MIB MiB of device memory on every
+ * GPU where the library's sort kernels are loaded, until the process ends.
+ * Every call on one GPU uses that GPU's one array: calls that overlap in
+ * time on one GPU (other streams, other threads) race and corrupt each
+ * other's results, so serialize them (calls on one stream are ordered).
+ * Nothing in the array needs clearing between calls (each call writes all
+ * it reads).  Arguments as for htex_sort_batch. */
+#define HTEX_SORT_NOALLOC_MAX_Q (1 << 20)
+#define HTEX_SORT_NOALLOC_SCRATCH_MIB 33
+htex_status htex_sort_batch_noalloc(int32_t H, const htex_queries *in, int32_t *perm,
+                                    int32_t *h_out, float *u_out, float *v_out, float *f_out,
+                                    void *stream);
+
 /* Sorted copy of a batch: h_out[i] = h[perm[i]], same for u, v and the
  * footprint (f_out may be NULL when the batch has none). */
 htex_status htex_permute_queries(const htex_queries *in, const int32_t *perm, int32_t *h_out,

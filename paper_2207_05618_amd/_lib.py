@@ -68,6 +68,7 @@ SIGNATURES = {
     "htex_sort_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int64]),
     "htex_sort_queries": (C.c_int32, [C.c_int32, C.c_int64, _P, _P, _P, C.c_size_t, _P]),
     "htex_sort_batch": (C.c_int32, [C.c_int32, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "htex_sort_batch_noalloc": (C.c_int32, [C.c_int32, _P, _P, _P, _P, _P, _P, _P]),
     "htex_permute_queries": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P]),
     "htex_unpermute_results": (C.c_int32, [C.c_int64, C.c_int32, _P, _P, _P, _P]),
     "htex_sample_prepared": (C.c_int32, [C.c_int32, _P, _P, _P, C.c_int32, C.c_uint32, _P, _P,
@@ -77,6 +78,7 @@ SIGNATURES = {
                                                _P, _P, _P]),
 }
 HTEX_PREP_BYTES = 48
+HTEX_SORT_NOALLOC_MAX_Q = 1 << 20
 HTEX_MAX_ANISO = 16
 
 

@@ -441,6 +441,33 @@ htex_status htex_sort_batch(int32_t H, const htex_queries *in, int32_t *perm, in
                     "sort launch");
 }
 
+htex_status htex_sort_batch_noalloc(int32_t H, const htex_queries *in, int32_t *perm,
+                                    int32_t *h_out, float *u_out, float *v_out, float *f_out,
+                                    void *stream)
+{
+    if (!in) return fail(HTEX_E_ARG, "queries is NULL");
+    if (H < 0 || in->Q < 0) return fail(HTEX_E_ARG, "negative size");
+    if (in->Q > htex::kStaticSortMaxQ)
+        return fail(HTEX_E_RANGE, "the allocation-free sort takes at most %lld queries, got %lld",
+                    (long long)htex::kStaticSortMaxQ, (long long)in->Q);
+    if (htex_status st = check_sort_batch(in, perm, h_out, u_out, v_out, f_out, nullptr, 0))
+        return st;
+    if (in->Q == 0) return ok();
+    void *ws = nullptr;
+    hipError_t e = htex::static_sort_scratch(&ws);
+    if (e != hipSuccess) return from_hip(e, "sort scratch lookup");
+    const size_t need = htex::sort_workspace_bytes(H, in->Q);
+    if (need > htex::static_sort_scratch_bytes())
+        return fail(HTEX_E_RANGE, "sort scratch of %zu bytes is smaller than the %zu needed",
+                    htex::static_sort_scratch_bytes(), need);
+    if (htex_status st = check_sort_batch(in, perm, h_out, u_out, v_out, f_out, ws, need))
+        return st;
+    return from_hip(htex::launch_sort(H, in->Q, in->h, in->u, in->v, in->footprint, perm, h_out,
+                                      u_out, v_out, in->footprint ? f_out : nullptr, ws,
+                                      static_cast<hipStream_t>(stream)),
+                    "sort launch");
+}
+
 htex_status htex_permute_queries(const htex_queries *in, const int32_t *perm, int32_t *h_out,
                                  float *u_out, float *v_out, float *f_out, void *stream)
 {

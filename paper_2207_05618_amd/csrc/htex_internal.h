@@ -91,8 +91,15 @@ struct ServeTile {
 };
 constexpr int kTileQueries = 256;
 
+// Largest batch of the allocation-free sort, and the most devices whose
+// scratch addresses are kept.
+constexpr int64_t kStaticSortMaxQ = HTEX_SORT_NOALLOC_MAX_Q;
+constexpr int kMaxDevices = 64;
+
 hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t s);
 size_t sort_workspace_bytes(int32_t H, int64_t Q);
+size_t static_sort_scratch_bytes();
+hipError_t static_sort_scratch(void **ptr);
 // Sorts by halfedge: perm, and (when u_out is non-NULL) the sorted u, v and
 // (when f_out is non-NULL) footprint; h_out may be NULL.
 hipError_t launch_sort(int32_t H, int64_t Q, const int32_t *h, const float *u, const float *v,

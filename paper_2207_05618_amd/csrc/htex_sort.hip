@@ -18,6 +18,8 @@
 // array.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "htex_internal.h"
 
 namespace htex {
@@ -329,9 +331,40 @@ constexpr size_t sort_ws_bytes(int32_t H, int64_t Q)
            align256(sizeof(int32_t) * (size_t)nhist) + scan_ws_bytes(nhist);
 }
 
+// Device scratch of the allocation-free sort: the workspace of the largest
+// batch it takes (kStaticSortMaxQ queries, any H < 2^31), per GPU.
+constexpr size_t kStaticSortBytes = sort_ws_bytes(INT32_MAX, kStaticSortMaxQ);
+static_assert(kStaticSortBytes <= (size_t)HTEX_SORT_NOALLOC_SCRATCH_MIB << 20,
+              "the scratch size stated in htex.h");
+static __device__ __align__(256) char scratch[kStaticSortBytes];
+
 }  // namespace
 
 size_t sort_workspace_bytes(int32_t H, int64_t Q) { return sort_ws_bytes(H, Q); }
+
+size_t static_sort_scratch_bytes() { return kStaticSortBytes; }
+
+// The device address of this GPU's `scratch`, looked up once per device with
+// that device current (each GPU holds its own copy of the array; in host code
+// the array's name is not a device address).
+hipError_t static_sort_scratch(void **ptr)
+{
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_sort(int32_t H, int64_t Q, const int32_t *h, const float *u, const float *v,
                        const float *f, int32_t *perm, int32_t *h_out, float *u_out, float *v_out,

@@ -248,3 +248,14 @@ def test_prepared_records_remember_their_layout():
     prep.check_pool(types.SimpleNamespace(layout_key=k))
     with pytest.raises(ValueError, match="another pool layout"):
         prep.check_pool(types.SimpleNamespace(layout_key=htex.layout_key(lr2, True, total)))
+
+
+def test_noalloc_sort_refuses_oversized_batches_on_the_host():
+    """The allocation-free sort rejects batches above its scratch limit
+    before touching the device."""
+    L = _lib.load()
+    q = _lib.htex_queries(_lib.HTEX_SORT_NOALLOC_MAX_Q + 1, 1 << 24, 2 << 24, 3 << 24, None)
+    assert L.htex_sort_batch_noalloc(392, C.byref(q), 5 << 24, 6 << 24, 7 << 24, 8 << 24, None,
+                                     None) == -3
+    assert "at most" in L.htex_last_error().decode()
+    assert L.htex_sort_batch_noalloc(392, None, 16, 16, 16, 16, None, None) == -1
