@@ -66,6 +66,10 @@ def parse():
                          "(0: whole requests in arrival order)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "fp8_e4m3"],
+                    help="texel storage of the timed frame's pool (bf16 and fp8_e4m3 "
+                         "quantize the float32 pool before timing; the extra legs, whose "
+                         "ratios are taken against the float32 frame, are then left out)")
     return ap.parse_args()
 
 
@@ -962,6 +966,8 @@ def recorded_traffic():
 
 def main():
     args = parse()
+    if args.storage != "f32":
+        args.no_extra = True
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path; "
               "run with --gpus 1", file=sys.stderr)
@@ -988,6 +994,10 @@ def main():
     torch.cuda.synchronize()
     log(f"pool {pool.nbytes() / 1e9:.2f} GB filled + mips ({time.perf_counter() - t_start:.1f}s)")
     prep = htex.Prepared(dmesh, pool)       # per (mesh, pool layout), like the mips
+    STORAGE = {"f32": (htex.HTEX_F32, 16), "bf16": (htex.HTEX_BF16, 8),
+               "fp8_e4m3": (htex.HTEX_FP8_E4M3, 4)}
+    st_dtype, st_texel_bytes = STORAGE[args.storage]
+    tpool = pool if args.storage == "f32" else htex.htex_quantize(pool, st_dtype)
     torch.cuda.synchronize()
     dev_batches = [to_dev(b) for b in batches]
     Q = batches[0].Q
@@ -1014,7 +1024,7 @@ def main():
         copy_gbs = 30 * 2 * x.numel() * 4 / (ce0.elapsed_time(ce1) / 1e3) / 1e9
     del x, y
 
-    def step(i, p=pool, bs=dev_batches, flags=htex.HTEX_QUERIES_SORTED):
+    def step(i, p=tpool, bs=dev_batches, flags=htex.HTEX_QUERIES_SORTED):
         h, u, v, f = bs[i % len(bs)]
         htex.htex_sample_prepared(prep, p, h, u, v, f, filter=htex.HTEX_TRILINEAR,
                                   flags=flags, out=out)
@@ -1166,11 +1176,16 @@ def main():
 
     roofline = None
     if alg is not None:
+        if args.storage != "f32":
+            # the line and segment figures below count float32 texels
+            alg = dict(alg, segment_bytes_per_query=float("nan"),
+                       line128_bytes_per_query=None, unique_128B_lines=None,
+                       **storage_bytes(alg, Q, st_texel_bytes, st_dtype == htex.HTEX_FP8_E4M3))
         achieved = alg["bytes"] / avg_kernel_s / 1e9
-        traffic = recorded_traffic()
+        traffic = recorded_traffic() if args.storage == "f32" else None
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                    "kernel": "htex::k_sample_prep<f32,trilinear>",
+                    "kernel": f"htex::k_sample_prep<{args.storage},trilinear>",
                     "avg_kernel_us": avg_kernel_s * 1e6,
                     "median_kernel_us": median_kernel_s * 1e6,
                     "copy_GBs": copy_gbs,
@@ -1183,11 +1198,12 @@ def main():
                                        if traffic else None),
                     "l2_fabric_vs_copy": (traffic / avg_kernel_s / 1e9 / copy_gbs
                                           if traffic and copy_gbs else None),
-                    "segment64_frac": alg["segment_bytes_per_query"] * Q / avg_kernel_s / 1e9
-                    / HBM_PEAK_GBS,
+                    "segment64_frac": (alg["segment_bytes_per_query"] * Q / avg_kernel_s / 1e9
+                                       / HBM_PEAK_GBS if args.storage == "f32" else None),
                     "alg_bytes_per_query": alg["bytes_per_query"],
                     "alg_texel_bytes_per_query": alg["texel_bytes_per_query"],
-                    "segment64_bytes_per_query": alg["segment_bytes_per_query"],
+                    "segment64_bytes_per_query": (alg["segment_bytes_per_query"]
+                                                  if args.storage == "f32" else None),
                     "line128_bytes_per_query": alg["line128_bytes_per_query"],
                     "unique_128B_texel_lines": alg["unique_128B_lines"]}
         log(f"algorithmic bytes/query {alg['bytes_per_query']:.1f} "
@@ -1204,10 +1220,10 @@ def main():
         cpu = cpu_baseline(mesh, log2res, pool.base_host, pool.texels, batches[0])
         log(f"cpu oracle {cpu['value']:.3e} samples/s on {cpu['cores']} cores")
 
-    pool_bytes = pool.nbytes()
+    pool_bytes = tpool.nbytes()
     serving = None
     if not args.no_serve and args.workload == "frame4k":
-        del prep, out, dev_batches, pool
+        del prep, out, dev_batches, pool, tpool
         torch.cuda.empty_cache()
         serving = serve_benchmark(smeshes, chunk=args.serve_chunk)
 
@@ -1227,6 +1243,7 @@ def main():
                          "5to8": float((fs >= 5).mean())},
             "boundary_edge_frac": float(mesh.boundary_edges().mean()),
             "queries_per_step": Q, "pool_bytes": pool_bytes, "filter": "trilinear",
+            "texel_storage": args.storage,
             "log2_footprint": [-3.2, -1.2] if args.workload == "frame4k" else [-6, 0],
             "sorted": True, "batches_rotated": len(batches)},
         "roofline": roofline, "cpu_baseline": cpu, "extra": extra, "serving": serving,

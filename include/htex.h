@@ -302,7 +302,7 @@ htex_status htex_sort_batch(int32_t H, const htex_queries *in, int32_t *perm, in
  * Nothing in the array needs clearing between calls (each call writes all
  * it reads).  Arguments as for htex_sort_batch. */
 #define HTEX_SORT_NOALLOC_MAX_Q (1 << 20)
-#define HTEX_SORT_NOALLOC_SCRATCH_MIB 33
+#define HTEX_SORT_NOALLOC_SCRATCH_MIB 35
 htex_status htex_sort_batch_noalloc(int32_t H, const htex_queries *in, int32_t *perm,
                                     int32_t *h_out, float *u_out, float *v_out, float *f_out,
                                     void *stream);

@@ -3,19 +3,23 @@
 //
 // Stable LSD radix sort of (key, input index) pairs; the key of a query is h,
 // or H for an invalid h (outside [0, H)), which sorts last.  Digits are as
-// wide as needed to cover keys 0..H in the fewest passes of at most 10 bits
-// (two passes for a million halfedges).  Each pass: a digit histogram per
-// tile of kTile keys, an exclusive scan of the histograms in digit-major
-// order (so tile t's digit d starts after every smaller digit and after
-// digit d of tiles < t), then the scatter.  The scatter first sorts its tile
-// in LDS, stably (a key's rank among equal digits comes from wave ballots
-// within a wave and per-wave counts across the waves of a round), and then
-// writes the tile out in that order, so consecutive lanes store consecutive
-// addresses of a digit's run instead of one scattered word each.
-// A sorted batch: the first histogram pass also copies the queries into
-// 16-byte records (h, u, v, footprint), which are gathered through the
-// final permutation -- one 16-byte read per query instead of one read per
-// array.
+// wide as needed to cover keys 0..H in the fewest passes of at most 8 bits
+// (three passes for a million halfedges).  The passes follow the one-sweep
+// scheme of Adinets and Merrill (2022): one read of the keys counts every
+// pass's digits up front, so each pass knows where each digit's run begins,
+// and each pass is then a single launch over tiles of kTile keys in which
+// tile t learns, for each digit, how many keys of the tiles before it share
+// that digit from the tiles before it (decoupled look-back over published
+// per-tile counts) instead of from a separate histogram and scan.
+//
+// Inside a tile the keys are ranked stably: each wavefront ranks its quarter
+// on its own (ballots within a round of 64 keys and the wavefront's running
+// digit counts in LDS), one scan per digit across the four wavefronts places
+// the quarters, and the tile is written from LDS in sorted order, so
+// consecutive lanes store consecutive addresses of a digit's run.  A sorted
+// batch: the counting read also copies the queries into 16-byte records
+// (h, u, v, footprint), and the last pass gathers each output row's record
+// -- one 16-byte read per query instead of one per array.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -29,8 +33,22 @@ constexpr int kThreads = 256;
 constexpr int kPerThread = 16;
 constexpr int kTile = kThreads * kPerThread;   // 4096 keys per tile
 constexpr int kWaves = kThreads / 64;
-constexpr int kMaxDigitBits = 10;
+constexpr int kMaxDigitBits = 8;
 constexpr int kMaxBins = 1 << kMaxDigitBits;
+constexpr int kDigitsPerThread = kMaxBins / kThreads;   // consecutive digits of one thread
+constexpr int kMaxPasses = 4;                  // keys below 2^32
+constexpr int kCountBlocks = 1024;             // blocks of the counting read (at most)
+constexpr int kLookWindow = 4;                 // predecessors read at once in the look-back
+static_assert(kMaxBins % kThreads == 0, "whole digits per thread");
+
+// Published per-tile digit counts: the top two bits say what the low 32 hold.
+constexpr uint64_t kAggregate = uint64_t(1) << 62;   // this tile's count alone
+constexpr uint64_t kPrefix = uint64_t(2) << 62;      // this tile's and all before it
+// Polls of a predecessor's count before a tile gives up waiting.  Every tile
+// publishes its own count before it waits, and tile numbers are handed out
+// in the order blocks start, so a wait only ever depends on blocks already
+// running; the limit only keeps the kernel finite.
+constexpr int kSpinLimit = 1 << 22;
 
 __device__ __forceinline__ uint32_t sort_key(int32_t h, int32_t H)
 {
@@ -50,203 +68,264 @@ struct KeySrc {
     }
 };
 
-// hist[d * ntiles + t] = number of keys of tile t whose digit is d;
-// hist[nb * ntiles] = 0, so that the exclusive scan leaves Q there.  With
-// `rec`, the first pass also writes every query as one 16-byte record.
-__global__ void __launch_bounds__(kThreads) k_hist(KeySrc ks, int64_t Q, int shift, int bits,
-                                                   int32_t ntiles, int32_t *hist,
-                                                   const float *u, const float *v,
-                                                   const float *f, float4 *rec)
+// Zeroes n 16-byte words (the digit counts, tile tickets and published
+// counts of every pass).
+__global__ void __launch_bounds__(kThreads) k_clear(uint4 *p, int64_t n)
 {
-    __shared__ int32_t cnt[kMaxBins];
-    const int nb = 1 << bits;
-    for (int d = threadIdx.x; d < nb; d += kThreads) cnt[d] = 0;
-    __syncthreads();
-    const int64_t t0 = (int64_t)blockIdx.x * kTile;
-    const uint32_t mask = (uint32_t)nb - 1u;
-    for (int r = 0; r < kPerThread; ++r) {
-        const int64_t i = t0 + (int64_t)r * kThreads + threadIdx.x;
-        if (i < Q) {
-            atomicAdd(&cnt[(ks(i) >> shift) & mask], 1);
-            if (rec)
-                rec[i] = make_float4(__int_as_float(ks.h[i]), u[i], v[i], f ? f[i] : 0.0f);
-        }
-    }
-    __syncthreads();
-    for (int d = threadIdx.x; d < nb; d += kThreads)
-        hist[(int64_t)d * ntiles + blockIdx.x] = cnt[d];
-    if (blockIdx.x == 0 && threadIdx.x == 0) hist[(int64_t)nb * ntiles] = 0;
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// Exclusive scan of int32 data in place, one level: each block scans 1024
-// values and writes its total to sums[block].
-__global__ void __launch_bounds__(kThreads) k_scan_block(int32_t *data, int64_t n, int32_t *sums)
+// count[pass * kMaxBins + d] += the keys whose digit of that pass is d,
+// over the tiles blockIdx.x, blockIdx.x + gridDim.x, ...  With `rec`, also
+// rec[i] = (h, u, v, f).
+__global__ void __launch_bounds__(kThreads) k_count(const int32_t *h, int32_t H, int64_t Q,
+                                                    int passes, int bits, uint32_t *count,
+                                                    const float *u, const float *v,
+                                                    const float *f, float4 *rec)
 {
-    __shared__ int32_t s[kThreads];
-    const int64_t b0 = (int64_t)blockIdx.x * kThreads * 4;
-    int32_t v[4];
-    int32_t local = 0;
-    for (int j = 0; j < 4; ++j) {
-        const int64_t i = b0 + (int64_t)threadIdx.x * 4 + j;
-        v[j] = i < n ? data[i] : 0;
-        local += v[j];
-    }
-    s[threadIdx.x] = local;
+    __shared__ uint32_t cnt[kMaxPasses][kMaxBins];
+    for (int p = 0; p < kMaxPasses; ++p)
+        for (int d = threadIdx.x; d < kMaxBins; d += kThreads) cnt[p][d] = 0u;
+    const uint32_t mask = (1u << bits) - 1u;
     __syncthreads();
-    for (int off = 1; off < kThreads; off <<= 1) {
-        const int32_t add = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0;
-        __syncthreads();
-        s[threadIdx.x] += add;
-        __syncthreads();
-    }
-    int32_t run = s[threadIdx.x] - local;   // exclusive prefix of this thread
-    for (int j = 0; j < 4; ++j) {
-        const int64_t i = b0 + (int64_t)threadIdx.x * 4 + j;
-        if (i < n) data[i] = run;
-        run += v[j];
-    }
-    if (threadIdx.x == kThreads - 1 && sums) sums[blockIdx.x] = s[kThreads - 1];
-}
-
-__global__ void __launch_bounds__(kThreads) k_scan_add(int32_t *data, int64_t n, const int32_t *sums)
-{
-    const int64_t b0 = (int64_t)blockIdx.x * kThreads * 4;
-    const int32_t add = sums[blockIdx.x];
-    for (int j = 0; j < 4; ++j) {
-        const int64_t i = b0 + (int64_t)threadIdx.x * 4 + j;
-        if (i < n) data[i] += add;
-    }
-}
-
-// One pass of the scatter.  offs: the scanned histograms (nb * ntiles + 1
-// entries).  idx_in NULL stands for the identity; kout NULL on the last pass
-// (the keys are no longer needed).
-__global__ void __launch_bounds__(kThreads) k_scatter(KeySrc ks, const int32_t *idx_in,
-                                                      uint32_t *kout, int32_t *iout, int64_t Q,
-                                                      int shift, int bits, int32_t ntiles,
-                                                      const int32_t *offs)
-{
-    __shared__ int32_t gstart[kMaxBins];        // global start of each digit's run of this tile
-    __shared__ int32_t lstart[kMaxBins];        // its start inside the tile
-    __shared__ int32_t lrun[kMaxBins];          // next free local slot of each digit
-    __shared__ int32_t wcnt[kWaves][kMaxBins];  // per-wave digit counts of a round
-    __shared__ int32_t part[kThreads];
-    __shared__ uint32_t lkey[kTile];
-    __shared__ int32_t lidx[kTile];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nb = 1 << bits;
-    const uint32_t mask = (uint32_t)nb - 1u;
-    const int64_t t0 = (int64_t)blockIdx.x * kTile;
-    const int tcount = (int)(Q - t0 < kTile ? Q - t0 : kTile);
-    // digit runs of this tile: global starts, counts, and a local exclusive
-    // scan of the counts (each thread scans a chunk of nb / 256 digits)
-    const int per = (nb + kThreads - 1) / kThreads;
-    int32_t csum = 0;
-    for (int j = 0; j < per; ++j) {
-        const int d = threadIdx.x * per + j;
-        if (d < nb) {
-            const int64_t at = (int64_t)d * ntiles + blockIdx.x;
-            const int32_t g = offs[at];
-            gstart[d] = g;
-            lstart[d] = offs[at + 1] - g;   // the count, for now
-            csum += offs[at + 1] - g;
-            for (int v = 0; v < kWaves; ++v) wcnt[v][d] = 0;
+    for (int64_t tile = blockIdx.x; tile * kTile < Q; tile += gridDim.x) {
+        const int64_t t0 = tile * kTile + threadIdx.x;
+        int32_t hv[kPerThread];
+#pragma unroll
+        for (int r = 0; r < kPerThread; ++r) {
+            const int64_t i = t0 + (int64_t)r * kThreads;
+            hv[r] = i < Q ? h[i] : 0;
         }
-    }
-    part[threadIdx.x] = csum;
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const int l = threadIdx.x;
-        const int32_t v0 = part[4 * l], v1 = part[4 * l + 1], v2 = part[4 * l + 2],
-                      v3 = part[4 * l + 3];
-        const int32_t tot = v0 + v1 + v2 + v3;
-        int32_t inc = tot;
-        for (int dd = 1; dd < 64; dd <<= 1) {
-            const int32_t y = __shfl_up(inc, dd);
-            if (l >= dd) inc += y;
-        }
-        const int32_t ex = inc - tot;
-        part[4 * l] = ex;
-        part[4 * l + 1] = ex + v0;
-        part[4 * l + 2] = ex + v0 + v1;
-        part[4 * l + 3] = ex + v0 + v1 + v2;
-    }
-    __syncthreads();
-    {
-        int32_t run = part[threadIdx.x];
-        for (int j = 0; j < per; ++j) {
-            const int d = threadIdx.x * per + j;
-            if (d < nb) {
-                const int32_t c = lstart[d];
-                lstart[d] = run;
-                lrun[d] = run;
-                run += c;
+        if (rec) {
+#pragma unroll 4
+            for (int r = 0; r < kPerThread; ++r) {
+                const int64_t i = t0 + (int64_t)r * kThreads;
+                if (i < Q)
+                    rec[i] = make_float4(__int_as_float(hv[r]), u[i], v[i], f ? f[i] : 0.0f);
             }
         }
+#pragma unroll
+        for (int r = 0; r < kPerThread; ++r) {
+            if (t0 + (int64_t)r * kThreads >= Q) break;
+            const uint32_t key = sort_key(hv[r], H);
+            for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][(key >> (p * bits)) & mask], 1u);
+        }
     }
     __syncthreads();
-    // the tile sorted into LDS, kThreads keys per round
+    const int nb = 1 << bits;
+    for (int p = 0; p < passes; ++p)
+        for (int d = threadIdx.x; d < nb; d += kThreads)
+            if (cnt[p][d]) atomicAdd(&count[p * kMaxBins + d], cnt[p][d]);
+}
+
+// Exclusive scans of a and b over the block's threads (one value each).
+__device__ __forceinline__ void block_scan2(int32_t &a, int32_t &b, int32_t (*wsum)[kWaves])
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int32_t ia = a, ib = b;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t ya = __shfl_up(ia, d), yb = __shfl_up(ib, d);
+        if (lane >= d) ia += ya, ib += yb;
+    }
+    if (lane == 63) wsum[0][w] = ia, wsum[1][w] = ib;
+    __syncthreads();
+    int32_t ba = 0, bb = 0;
+    for (int v = 0; v < w; ++v) ba += wsum[0][v], bb += wsum[1][v];
+    a = ba + ia - a;
+    b = bb + ib - b;
+}
+
+struct PassArgs {
+    KeySrc ks;
+    const int32_t *idx_in;    // input index of each key; NULL: the identity
+    uint32_t *kout;           // sorted keys; NULL on the last pass
+    int32_t *iout;            // their input indices (perm on the last pass)
+    const float4 *rec;        // last pass of a sorted batch: the query records
+    int32_t *ho;
+    float *uo, *vo, *fo;      // ... gathered into the sorted arrays
+    int64_t Q;
+    int shift, bits;
+    const uint32_t *count;    // this pass's digit counts over the batch
+    uint64_t *status;         // this pass's published counts [tile][kMaxBins]
+    uint32_t *ticket;         // this pass's tile counter
+};
+
+// One pass: a block takes the next tile, ranks it, publishes its digit
+// counts, looks back for the counts of the tiles before it and writes the
+// tile to its places.
+__global__ void __launch_bounds__(kThreads) k_pass(PassArgs a)
+{
+    // per-wave digit counts, then each wavefront's first slot for the digit
+    __shared__ int32_t wcnt[kWaves][kMaxBins];
+    __shared__ int32_t delta[kMaxBins];          // a digit's output start minus its tile start
+    __shared__ int32_t wsum[2][kWaves];
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t lkey[kTile];             // the tile in sorted order
+    __shared__ int32_t lidx[kTile];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int d0 = threadIdx.x * kDigitsPerThread;   // this thread's digits: d0 + k
+    const int nb = 1 << a.bits;
+    const uint32_t mask = (uint32_t)nb - 1u;
+    if (threadIdx.x == 0) s_tile = atomicAdd(a.ticket, 1u);
+    for (int v = 0; v < kWaves; ++v)
+        for (int k = 0; k < kDigitsPerThread; ++k) wcnt[v][d0 + k] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const int64_t t0 = (int64_t)tile * kTile;
+    const int tcount = (int)(a.Q - t0 < kTile ? a.Q - t0 : kTile);
+    // 1. each wavefront ranks its quarter of the tile, 64 keys a round, in
+    // input order: a key's rank is the wavefront's count of its digit before
+    // the round plus the equal digits on lower lanes (one wavefront's LDS
+    // accesses are done in program order, so every lane of a group reads the
+    // count before the group's first lane writes the new one)
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int32_t *const cnt = wcnt[w];
+    uint32_t key[kPerThread];
+    int32_t rank_in_wave[kPerThread];
+#pragma unroll
     for (int r = 0; r < kPerThread; ++r) {
-        const int li = r * kThreads + (int)threadIdx.x;
-        const int64_t i = t0 + li;
-        const bool valid = li < tcount;
-        const uint32_t key = valid ? ks(i) : 0u;
-        const int32_t id = valid ? (idx_in ? idx_in[i] : (int32_t)i) : 0;
-        const uint32_t dig = (key >> shift) & mask;
-        // lanes of this wave holding the same digit
+        const int p = w * (kTile / kWaves) + r * 64 + lane;
+        const bool valid = p < tcount;
+        key[r] = valid ? a.ks(t0 + p) : 0u;
+        const uint32_t dig = (key[r] >> a.shift) & mask;
         uint64_t same = __ballot(valid);
-        for (int b = 0; b < bits; ++b) {
+        for (int b = 0; b < a.bits; ++b) {
             const uint64_t ones = __ballot(((dig >> b) & 1u) != 0u);
             same &= ((dig >> b) & 1u) ? ones : ~ones;
         }
         const int rank = __popcll(same & below);
-        const int cnt = __popcll(same);
-        const bool leader = valid && rank == 0;
-        if (leader) wcnt[w][dig] = cnt;
-        __syncthreads();
-        int before = 0, after = 0;
-        if (valid) {
-            for (int v = 0; v < kWaves; ++v) {
-                const int c = wcnt[v][dig];
-                before += v < w ? c : 0;
-                after += v > w ? c : 0;
-            }
-            const int p = lrun[dig] + before + rank;
-            lkey[p] = key;
-            lidx[p] = id;
-        }
-        __syncthreads();
-        if (leader) {
-            if (after == 0) lrun[dig] += before + cnt;
-            wcnt[w][dig] = 0;
-        }
-        __syncthreads();
+        const int32_t before = valid ? cnt[dig] : 0;
+        if (valid && rank == 0) cnt[dig] = before + __popcll(same);
+        rank_in_wave[r] = before + rank;
     }
-    // the tile written out in sorted order: consecutive lanes, consecutive
+    __syncthreads();
+    // 2. this thread's digits: the tile's counts, published at once; the
+    // wavefronts' offsets; each digit's start in the tile and in the batch
+    int32_t c[kDigitsPerThread];
+    int32_t csum = 0, gsum = 0;
+    uint64_t *const st = a.status + (size_t)tile * kMaxBins + d0;
+#pragma unroll
+    for (int k = 0; k < kDigitsPerThread; ++k) {
+        c[k] = 0;
+        if (d0 + k < nb) {
+            for (int v = 0; v < kWaves; ++v) c[k] += wcnt[v][d0 + k];
+            __hip_atomic_store(st + k, (tile == 0 ? kPrefix : kAggregate) | (uint32_t)c[k],
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            gsum += (int32_t)a.count[d0 + k];
+        }
+        csum += c[k];
+    }
+    // the keys and their ranks wait in LDS (in input order) during the
+    // look-back, which then has the registers for its window
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+        const int p = w * (kTile / kWaves) + r * 64 + lane;
+        lkey[p] = key[r];
+        lidx[p] = rank_in_wave[r];
+    }
+    int32_t lbase = csum, gbase = gsum;
+    block_scan2(lbase, gbase, wsum);
+    // 3. look-back: the keys of each digit in the tiles before this one,
+    // kLookWindow predecessors at a time, nearest first; the counts are
+    // added up to the first inclusive one, and the walk resumes at the first
+    // tile not yet published, polling it
+    uint32_t before[kDigitsPerThread];
+    bool done[kDigitsPerThread];
+    int64_t j[kDigitsPerThread];
+#pragma unroll
+    for (int k = 0; k < kDigitsPerThread; ++k) {
+        before[k] = 0;
+        done[k] = tile == 0 || d0 + k >= nb;
+        j[k] = (int64_t)tile - 1;
+    }
+    for (int polls = 0;;) {
+        uint64_t x[kDigitsPerThread][kLookWindow];
+#pragma unroll
+        for (int k = 0; k < kDigitsPerThread; ++k)
+#pragma unroll
+            for (int i = 0; i < kLookWindow; ++i)
+                x[k][i] = !done[k] && j[k] - i >= 0
+                              ? __hip_atomic_load(a.status + (size_t)(j[k] - i) * kMaxBins + d0 + k,
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                              : kPrefix;
+        bool all = true, progress = false;
+#pragma unroll
+        for (int k = 0; k < kDigitsPerThread; ++k) {
+            if (done[k]) continue;
+            int taken = 0;
+#pragma unroll
+            for (int i = 0; i < kLookWindow; ++i) {
+                if (done[k] || taken < i || !(x[k][i] >> 62)) continue;
+                before[k] += (uint32_t)x[k][i];
+                taken = i + 1;
+                done[k] = (x[k][i] & kPrefix) != 0;
+            }
+            j[k] -= taken;
+            progress |= taken > 0;
+            all &= done[k];
+        }
+        if (all) break;
+        if (!progress) {
+            if (++polls >= kSpinLimit) break;   // never expected; keeps the kernel finite
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    int32_t lrun = lbase, grun = gbase;
+#pragma unroll
+    for (int k = 0; k < kDigitsPerThread; ++k) {
+        const int d = d0 + k;
+        if (d < nb) {
+            if (tile > 0)
+                __hip_atomic_store(st + k, kPrefix | (uint32_t)(before[k] + c[k]),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int v = 0, o = lrun; v < kWaves; ++v) {
+                const int32_t x = wcnt[v][d];
+                wcnt[v][d] = o;
+                o += x;
+            }
+            delta[d] = grun + (int32_t)before[k] - lrun;
+            lrun += c[k];
+            grun += (int32_t)a.count[d];
+        }
+    }
+    __syncthreads();
+    // 4. the tile's sorted order in LDS
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+        const int p = w * (kTile / kWaves) + r * 64 + lane;
+        key[r] = lkey[p];
+        rank_in_wave[r] = lidx[p];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+        const int p = w * (kTile / kWaves) + r * 64 + lane;
+        if (p < tcount) {
+            const uint32_t dig = (key[r] >> a.shift) & mask;
+            const int slot = cnt[dig] + rank_in_wave[r];
+            lkey[slot] = key[r];
+            lidx[slot] = a.idx_in ? a.idx_in[t0 + p] : (int32_t)(t0 + p);
+        }
+    }
+    __syncthreads();
+    // 5. the tile written out in sorted order: consecutive lanes, consecutive
     // addresses within each digit's run
     for (int o = threadIdx.x; o < tcount; o += kThreads) {
-        const uint32_t key = lkey[o];
-        const uint32_t d = (key >> shift) & mask;
-        const int32_t dst = gstart[d] + (o - lstart[d]);
-        if (kout) kout[dst] = key;
-        iout[dst] = lidx[o];
+        const uint32_t k = lkey[o];
+        const uint32_t dg = (k >> a.shift) & mask;
+        const int32_t to = delta[dg] + o;
+        const int32_t src = lidx[o];
+        if (a.kout) a.kout[to] = k;
+        a.iout[to] = src;
+        if (a.rec) {
+            const float4 r = a.rec[src];
+            a.ho[to] = __float_as_int(r.x);
+            a.uo[to] = r.y;
+            a.vo[to] = r.z;
+            if (a.fo) a.fo[to] = r.w;
+        }
     }
-}
-
-// The sorted batch: query perm[i] of the 16-byte records into row i of the
-// sorted arrays.
-__global__ void __launch_bounds__(kThreads) k_gather_records(const int32_t *perm, int64_t Q,
-                                                             const float4 *rec, int32_t *ho,
-                                                             float *uo, float *vo, float *fo)
-{
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= Q) return;
-    const float4 r = rec[perm[i]];
-    ho[i] = __float_as_int(r.x);
-    uo[i] = r.y;
-    vo[i] = r.z;
-    if (fo) fo[i] = r.w;
 }
 
 __global__ void __launch_bounds__(kThreads) k_gather(const int32_t *perm, int64_t Q,
@@ -276,32 +355,6 @@ constexpr int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Scan workspace: one partial-sum array per level.
-constexpr size_t scan_ws_bytes(int64_t n)
-{
-    size_t b = 0;
-    while (n > 1) {
-        n = cdiv(n, kThreads * 4);
-        b += align256(sizeof(int32_t) * (size_t)n);
-    }
-    return b;
-}
-
-hipError_t scan_exclusive(int32_t *data, int64_t n, int32_t *ws, hipStream_t s)
-{
-    const int64_t nb = cdiv(n, kThreads * 4);
-    int32_t *sums = ws;
-    hipLaunchKernelGGL(k_scan_block, dim3((uint32_t)nb), dim3(kThreads), 0, s, data, n,
-                       nb > 1 ? sums : nullptr);
-    hipError_t e = hipGetLastError();
-    if (e || nb == 1) return e;
-    int32_t *next_ws = ws + align256(sizeof(int32_t) * nb) / sizeof(int32_t);
-    e = scan_exclusive(sums, nb, next_ws, s);
-    if (e) return e;
-    hipLaunchKernelGGL(k_scan_add, dim3((uint32_t)nb), dim3(kThreads), 0, s, data, n, sums);
-    return hipGetLastError();
-}
-
 // Passes and digit width for keys 0..H: the fewest passes of at most
 // kMaxDigitBits bits, digits split evenly.
 struct SortPlan {
@@ -317,18 +370,25 @@ constexpr SortPlan sort_plan(int32_t H)
     return {passes, (kb + passes - 1) / passes};
 }
 
-// Workspace layout: the 16-byte query records, the (key, index) sets the
+// Workspace layout: the 16-byte query records; the (key, index) sets the
 // passes between the first and the last write (one set for two passes, two
-// for more), the histograms and the scan partials.
+// for more); then the region cleared before every sort -- the digit counts
+// and tile tickets of every pass, and the published counts of every tile
+// of every pass.
+constexpr size_t kControlBytes = align256(sizeof(uint32_t) * kMaxPasses * (kMaxBins + 1));
+
+constexpr size_t sort_status_bytes(int passes, int64_t ntiles)
+{
+    return align256(sizeof(uint64_t) * (size_t)passes * (size_t)ntiles * kMaxBins);
+}
+
 constexpr size_t sort_ws_bytes(int32_t H, int64_t Q)
 {
     const SortPlan p = sort_plan(H);
     const int64_t q = Q > 0 ? Q : 1;
-    const int64_t ntiles = cdiv(q, kTile);
-    const int64_t nhist = ((int64_t)1 << p.bits) * ntiles + 1;
     const int sets = p.passes >= 3 ? 2 : p.passes - 1;
     return align256(16 * (size_t)q) + (size_t)sets * 2 * align256(sizeof(int32_t) * (size_t)q) +
-           align256(sizeof(int32_t) * (size_t)nhist) + scan_ws_bytes(nhist);
+           kControlBytes + sort_status_bytes(p.passes, cdiv(q, kTile));
 }
 
 // Device scratch of the allocation-free sort: the workspace of the largest
@@ -373,50 +433,57 @@ hipError_t launch_sort(int32_t H, int64_t Q, const int32_t *h, const float *u, c
     if (Q == 0) return hipSuccess;
     const SortPlan plan = sort_plan(H);
     const bool batch = u_out != nullptr;
+    const int64_t ntiles = cdiv(Q, kTile);
     char *p = static_cast<char *>(ws);
     float4 *rec = reinterpret_cast<float4 *>(p);
     p += align256(16 * (size_t)Q);
     const size_t arr = align256(sizeof(int32_t) * (size_t)Q);
-    uint32_t *keys[2];
-    int32_t *idx[2];
+    uint32_t *keys[2] = {};
+    int32_t *idx[2] = {};
     const int nsets = plan.passes >= 3 ? 2 : plan.passes - 1;
     for (int k = 0; k < nsets; ++k) {
         keys[k] = reinterpret_cast<uint32_t *>(p);
         idx[k] = reinterpret_cast<int32_t *>(p + arr);
         p += 2 * arr;
     }
-    const int64_t ntiles = cdiv(Q, kTile);
-    const int64_t nhist = ((int64_t)1 << plan.bits) * ntiles + 1;
-    int32_t *hist = reinterpret_cast<int32_t *>(p);
-    p += align256(sizeof(int32_t) * (size_t)nhist);
-    int32_t *scan_ws = reinterpret_cast<int32_t *>(p);
+    uint32_t *count = reinterpret_cast<uint32_t *>(p);   // [kMaxPasses][kMaxBins]
+    uint32_t *ticket = count + kMaxPasses * kMaxBins;    // [kMaxPasses]
+    uint64_t *status = reinterpret_cast<uint64_t *>(p + kControlBytes);
+    const int64_t nclear = (int64_t)(kControlBytes + sort_status_bytes(plan.passes, ntiles)) / 16;
+    const dim3 block(kThreads);
+    hipLaunchKernelGGL(k_clear, dim3((uint32_t)cdiv(nclear, kThreads)), block, 0, s,
+                       reinterpret_cast<uint4 *>(p), nclear);
+    hipError_t e = hipGetLastError();
+    if (!e) {
+        hipLaunchKernelGGL(k_count, dim3((uint32_t)(ntiles < kCountBlocks ? ntiles : kCountBlocks)),
+                           block,
+                           0, s, h, H, Q, plan.passes, plan.bits, count, batch ? u : nullptr,
+                           batch ? v : nullptr, batch ? f : nullptr, batch ? rec : nullptr);
+        e = hipGetLastError();
+    }
     KeySrc ks{h, nullptr, H};
     const int32_t *idx_in = nullptr;
-    hipError_t e = hipSuccess;
-    const dim3 grid((uint32_t)ntiles), block(kThreads);
     for (int pass = 0; pass < plan.passes && !e; ++pass) {
-        const int shift = plan.bits * pass;
         const bool last = pass == plan.passes - 1;
-        uint32_t *kout = last ? nullptr : keys[pass & 1];
-        int32_t *iout = last ? perm : idx[pass & 1];
-        const bool copy = batch && pass == 0;
-        hipLaunchKernelGGL(k_hist, grid, block, 0, s, ks, Q, shift, plan.bits, (int32_t)ntiles,
-                           hist, copy ? u : nullptr, copy ? v : nullptr, copy ? f : nullptr,
-                           copy ? rec : nullptr);
-        e = hipGetLastError();
-        if (!e) e = scan_exclusive(hist, nhist, scan_ws, s);
-        if (!e) {
-            hipLaunchKernelGGL(k_scatter, grid, block, 0, s, ks, idx_in, kout, iout, Q, shift,
-                               plan.bits, (int32_t)ntiles, hist);
-            e = hipGetLastError();
+        PassArgs a{};
+        a.ks = ks;
+        a.idx_in = idx_in;
+        a.kout = last ? nullptr : keys[pass & 1];
+        a.iout = last ? perm : idx[pass & 1];
+        if (last && batch) {
+            a.rec = rec;
+            a.ho = h_out, a.uo = u_out, a.vo = v_out, a.fo = f_out;
         }
-        ks = KeySrc{nullptr, kout, H};
-        idx_in = iout;
-    }
-    if (!e && batch) {
-        hipLaunchKernelGGL(k_gather_records, dim3((uint32_t)cdiv(Q, kThreads)), block, 0, s, perm,
-                           Q, rec, h_out, u_out, v_out, f_out);
+        a.Q = Q;
+        a.shift = plan.bits * pass;
+        a.bits = plan.bits;
+        a.count = count + pass * kMaxBins;
+        a.status = status + (size_t)pass * (size_t)ntiles * kMaxBins;
+        a.ticket = ticket + pass;
+        hipLaunchKernelGGL(k_pass, dim3((uint32_t)ntiles), block, 0, s, a);
         e = hipGetLastError();
+        ks = KeySrc{nullptr, a.kout, H};
+        idx_in = a.iout;
     }
     return e;
 }
