@@ -363,6 +363,7 @@ def grad_benchmark(steps=200):
     tex.requires_grad_(False)
     tri = grad_trilinear(m, dm, q, timed, steps)
     return {"queries": q.Q, "edges": int(m.E), "texels": int(total),
+            "backward_roofline": backward_roofline(q.Q, total, t_bwd, trilinear=False),
             "forward_samples_per_s": q.Q / t_fwd, "backward_samples_per_s": q.Q / t_bwd,
             "forward_us": t_fwd * 1e6, "forward_plain_us": t_fwd_plain * 1e6,
             "backward_us": t_bwd * 1e6,
@@ -370,6 +371,19 @@ def grad_benchmark(steps=200):
             "adam_steps": steps, "adam_seconds": fit_s, "loss_first": losses[0],
             "loss_last": losses[-1], "loss_reduction": losses[0] / max(losses[-1], 1e-30),
             "loss_curve_every_20": losses, "trilinear_level0": tri}
+
+
+def backward_roofline(Q, texels, seconds, trilinear):
+    """The backward launch against HBM: per query it reads h, u, v (and the
+    footprint) and dL/dout (16 B); the gradient pool is read and written
+    once (every texel of these small pools is touched).  The launch is
+    bound by LDS float atomics, not by these bytes."""
+    per_query = (16 if trilinear else 12) + 16
+    b = Q * per_query + 2 * 16 * texels
+    achieved = b / seconds / 1e9
+    return {"bound": "lds_atomics", "alg_bytes_per_query": b / Q, "alg_bytes": int(b),
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "avg_kernel_us": seconds * 1e6}
 
 
 def grad_trilinear(m, dm, q, timed, steps):
@@ -429,6 +443,7 @@ def grad_trilinear(m, dm, q, timed, steps):
     tex.requires_grad_(False)
     return {"texels": int(total), "forward_us": t_fwd * 1e6,
             "forward_plain_us": t_fwd_plain * 1e6, "backward_us": t_bwd * 1e6,
+            "backward_roofline": backward_roofline(q.Q, total, t_bwd, trilinear=True),
             "mip_backward_us": t_mip * 1e6, "build_mips_us": t_mips * 1e6,
             "adam_steps": steps, "adam_seconds": fit_s, "loss_first": losses[0],
             "loss_last": losses[-1], "loss_reduction": losses[0] / max(losses[-1], 1e-30),
