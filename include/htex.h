@@ -279,8 +279,10 @@ htex_status htex_sort_queries(int32_t H, int64_t Q, const int32_t *h, int32_t *p
 
 /* The sorted batch itself in one call: perm as htex_sort_queries, and
  * h_out[i] = h[perm[i]], likewise u_out, v_out and f_out (f_out only when
- * `in` has footprints; it may be NULL otherwise).  The radix passes carry
- * the queries with their keys, so no gather through perm follows.  Every
+ * `in` has footprints; it may be NULL otherwise).  The counting read copies
+ * each query into a 16-byte record and the last radix pass gathers each
+ * sorted row's record (one 16-byte read per query), so no separate gather
+ * through perm follows.  Every
  * output is device int32/float32 [Q], 4-byte aligned, and must not overlap
  * the input arrays, each other or the workspace (HTEX_E_ARG otherwise).
  * ws as for htex_sort_queries.  Q < 2^31. */
@@ -299,8 +301,8 @@ htex_status htex_sort_batch(int32_t H, const htex_queries *in, int32_t *perm, in
  * Every call on one GPU uses that GPU's one array: calls that overlap in
  * time on one GPU (other streams, other threads) race and corrupt each
  * other's results, so serialize them (calls on one stream are ordered).
- * Nothing in the array needs clearing between calls (each call writes all
- * it reads).  Arguments as for htex_sort_batch. */
+ * Nothing in the array needs clearing between calls (each call clears or
+ * writes all it reads).  Arguments as for htex_sort_batch. */
 #define HTEX_SORT_NOALLOC_MAX_Q (1 << 20)
 #define HTEX_SORT_NOALLOC_SCRATCH_MIB 35
 htex_status htex_sort_batch_noalloc(int32_t H, const htex_queries *in, int32_t *perm,

@@ -333,7 +333,8 @@ def htex_sort_queries(H: int, h, stream=None):
 
 def htex_sort_batch(H: int, h, u, v, footprint=None, stream=None):
     """(perm, h, u, v, footprint) of the batch in halfedge order, in one call:
-    the radix passes carry the queries with their keys."""
+    the last radix pass gathers each sorted row's query as one 16-byte
+    record."""
     q, Q = _queries(h, u, v, footprint)
     perm = torch.empty(Q, dtype=torch.int32, device=h.device)
     ho, uo, vo = torch.empty_like(h), torch.empty_like(u), torch.empty_like(v)
