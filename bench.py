@@ -1120,14 +1120,17 @@ def main():
                                            "samples_per_s": (Q // 8) / t_share}
             del share, out8
         # unsorted batch put in halfedge order first (one call sorts the
-        # batch with its queries), sampled sorted, results back in input
-        # order; timed as a whole, then step by step
+        # batch with its queries), sampled with the sorted kernel, results
+        # back in input order; timed as a whole, then step by step; and as a
+        # whole in edge order (sorted by the edge of each halfedge, so that
+        # both triangles of an intrinsic quad come together)
         hu, uu, vu, fu = to_dev(unsorted)
         sorted_out = torch.empty_like(out)
         keep = {}
+        by = {}
 
         def sort_step(i=0):
-            keep["b"] = htex.htex_sort_batch(mesh.H, hu, uu, vu, fu)
+            keep["b"] = htex.htex_sort_batch(mesh.H, hu, uu, vu, fu, **by)
 
         def sample_sorted(i=0):
             perm, h2, u2, v2, f2 = keep["b"]
@@ -1150,9 +1153,21 @@ def main():
             sorted_step()
         torch.cuda.synchronize()
         extra["unsorted_via_sort_samples_per_s"] = 5 * Q / (time.perf_counter() - t1)
-        extra["sort_path_us"] = {"sort_batch": kernel_seconds(sort_step, n=5)[0] * 1e6,
+        extra["sort_path_us"] = {"order": "halfedge",
+                                 "sort_batch": kernel_seconds(sort_step, n=5)[0] * 1e6,
                                  "sample_sorted": kernel_seconds(sample_sorted, n=5)[0] * 1e6,
                                  "unpermute": kernel_seconds(unpermute, n=5)[0] * 1e6}
+        by = {"key": dmesh.edge, "nkeys": mesh.E}
+        for _ in range(2):
+            sorted_step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            sorted_step()
+        torch.cuda.synchronize()
+        extra["unsorted_via_edge_sort_samples_per_s"] = 5 * Q / (time.perf_counter() - t1)
+        extra["edge_sort_path_us"] = {"sort_batch": kernel_seconds(sort_step, n=5)[0] * 1e6,
+                                      "sample_sorted": kernel_seconds(sample_sorted, n=5)[0] * 1e6}
         del hu, uu, vu, fu, sorted_out, keep
         # the frame with its pool stored as BF16 and FP8-E4M3: kernel time
         # from HIP events per launch, and the roofline against the bytes the

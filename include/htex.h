@@ -266,7 +266,8 @@ htex_status htex_sample_backward(const htex_mesh *mesh, const htex_pool *pool,
  * the same textures.  Sampling results do not depend on the order. */
 
 /* Bytes of device workspace htex_sort_queries and htex_sort_batch need for
- * Q queries on a mesh of H halfedges. */
+ * Q queries on a mesh of H halfedges (htex_sort_batch_by_key: pass the
+ * number of keys for H). */
 size_t htex_sort_workspace_bytes(int32_t H, int64_t Q);
 
 /* perm[0..Q) = the stable ordering of the queries by h (queries with h
@@ -290,6 +291,22 @@ htex_status htex_sort_batch(int32_t H, const htex_queries *in, int32_t *perm, in
                             float *u_out, float *v_out, float *f_out, void *ws, size_t ws_bytes,
                             void *stream);
 
+/* htex_sort_batch ordered by a key per halfedge instead of the halfedge:
+ * query i sorts by key_of_h[h_i] (device int32 [H], values 0 .. nkeys - 1),
+ * stably; queries whose h lies outside [0, H), or whose key lies outside
+ * [0, nkeys), sort last, in input order.  With key_of_h = the mesh's edge
+ * array (nkeys = E) both halfedges of an edge -- the two triangles of one
+ * intrinsic quad, which share its texture (Sections 3.2 and 4.1) -- are
+ * sampled back to back, which a sorted-batch kernel turns into fewer texel
+ * line fetches.  perm and the sorted arrays
+ * as htex_sort_batch; they must not overlap key_of_h either.  ws: at least
+ * htex_sort_workspace_bytes(nkeys, Q) bytes, 256-byte aligned.  nkeys >= 1;
+ * Q < 2^31. */
+htex_status htex_sort_batch_by_key(int32_t H, int32_t nkeys, const int32_t *key_of_h,
+                                   const htex_queries *in, int32_t *perm, int32_t *h_out,
+                                   float *u_out, float *v_out, float *f_out, void *ws,
+                                   size_t ws_bytes, void *stream);
+
 /* htex_sort_batch for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): no workspace argument; the radix passes use a scratch array
@@ -304,7 +321,7 @@ htex_status htex_sort_batch(int32_t H, const htex_queries *in, int32_t *perm, in
  * Nothing in the array needs clearing between calls (each call clears or
  * writes all it reads).  Arguments as for htex_sort_batch. */
 #define HTEX_SORT_NOALLOC_MAX_Q (1 << 20)
-#define HTEX_SORT_NOALLOC_SCRATCH_MIB 35
+#define HTEX_SORT_NOALLOC_SCRATCH_MIB 39
 htex_status htex_sort_batch_noalloc(int32_t H, const htex_queries *in, int32_t *perm,
                                     int32_t *h_out, float *u_out, float *v_out, float *f_out,
                                     void *stream);

@@ -331,19 +331,33 @@ def htex_sort_queries(H: int, h, stream=None):
     return perm
 
 
-def htex_sort_batch(H: int, h, u, v, footprint=None, stream=None):
+def htex_sort_batch(H: int, h, u, v, footprint=None, stream=None, key=None, nkeys=None):
     """(perm, h, u, v, footprint) of the batch in halfedge order, in one call:
     the last radix pass gathers each sorted row's query as one 16-byte
-    record."""
+    record.  With `key` (device int32 [H]) and `nkeys`, the batch is ordered
+    by key[h] instead (keys 0 .. nkeys - 1; e.g. a Mesh's `edge` and E, so
+    that both halfedges of an edge come together)."""
     q, Q = _queries(h, u, v, footprint)
     perm = torch.empty(Q, dtype=torch.int32, device=h.device)
     ho, uo, vo = torch.empty_like(h), torch.empty_like(u), torch.empty_like(v)
     fo = torch.empty_like(footprint) if footprint is not None else None
-    ws, nbytes = _sort_ws(H, Q, h.device)
-    check(load().htex_sort_batch(int(H), C.byref(q), perm.data_ptr(), ho.data_ptr(),
-                                 uo.data_ptr(), vo.data_ptr(),
-                                 fo.data_ptr() if fo is not None else None, ws.data_ptr(),
-                                 nbytes, _stream(stream)))
+    fp = fo.data_ptr() if fo is not None else None
+    if key is None:
+        ws, nbytes = _sort_ws(H, Q, h.device)
+        check(load().htex_sort_batch(int(H), C.byref(q), perm.data_ptr(), ho.data_ptr(),
+                                     uo.data_ptr(), vo.data_ptr(), fp, ws.data_ptr(), nbytes,
+                                     _stream(stream)))
+    else:
+        key = _dev(key, torch.int32, "key")
+        if key.numel() != H:
+            raise ValueError(f"key must hold one value per halfedge ({H}), got {key.numel()}")
+        if nkeys is None or int(nkeys) < 1:
+            raise ValueError("nkeys (the number of distinct keys, >= 1) is required with key")
+        ws, nbytes = _sort_ws(int(nkeys), Q, h.device)
+        check(load().htex_sort_batch_by_key(int(H), int(nkeys), key.data_ptr(), C.byref(q),
+                                            perm.data_ptr(), ho.data_ptr(), uo.data_ptr(),
+                                            vo.data_ptr(), fp, ws.data_ptr(), nbytes,
+                                            _stream(stream)))
     return perm, ho, uo, vo, fo
 
 

@@ -68,6 +68,8 @@ SIGNATURES = {
     "htex_sort_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int64]),
     "htex_sort_queries": (C.c_int32, [C.c_int32, C.c_int64, _P, _P, _P, C.c_size_t, _P]),
     "htex_sort_batch": (C.c_int32, [C.c_int32, _P, _P, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "htex_sort_batch_by_key": (C.c_int32, [C.c_int32, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P,
+                                           C.c_size_t, _P]),
     "htex_sort_batch_noalloc": (C.c_int32, [C.c_int32, _P, _P, _P, _P, _P, _P, _P]),
     "htex_permute_queries": (C.c_int32, [_P, _P, _P, _P, _P, _P, _P]),
     "htex_unpermute_results": (C.c_int32, [C.c_int64, C.c_int32, _P, _P, _P, _P]),

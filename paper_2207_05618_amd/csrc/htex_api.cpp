@@ -421,7 +421,8 @@ htex_status htex_sort_queries(int32_t H, int64_t Q, const int32_t *h, int32_t *p
     if (!h || !perm) return fail(HTEX_E_ARG, "NULL argument");
     if (overlap(perm, 4 * (size_t)Q, ws, ws_bytes))
         return fail(HTEX_E_ARG, "perm must not overlap the workspace");
-    return from_hip(htex::launch_sort(H, Q, h, nullptr, nullptr, nullptr, perm, nullptr, nullptr,
+    return from_hip(htex::launch_sort(H, nullptr, 0, Q, h, nullptr, nullptr, nullptr, perm, nullptr,
+                                      nullptr,
                                       nullptr, nullptr, ws, static_cast<hipStream_t>(stream)),
                     "sort launch");
 }
@@ -435,8 +436,36 @@ htex_status htex_sort_batch(int32_t H, const htex_queries *in, int32_t *perm, in
     if (htex_status st = check_sort_batch(in, perm, h_out, u_out, v_out, f_out, ws, ws_bytes))
         return st;
     if (in->Q == 0) return ok();
-    return from_hip(htex::launch_sort(H, in->Q, in->h, in->u, in->v, in->footprint, perm, h_out,
+    return from_hip(htex::launch_sort(H, nullptr, 0, in->Q, in->h, in->u, in->v, in->footprint, perm, h_out,
                                       u_out, v_out, in->footprint ? f_out : nullptr, ws,
+                                      static_cast<hipStream_t>(stream)),
+                    "sort launch");
+}
+
+htex_status htex_sort_batch_by_key(int32_t H, int32_t nkeys, const int32_t *key_of_h,
+                                   const htex_queries *in, int32_t *perm, int32_t *h_out,
+                                   float *u_out, float *v_out, float *f_out, void *ws,
+                                   size_t ws_bytes, void *stream)
+{
+    if (!in) return fail(HTEX_E_ARG, "queries is NULL");
+    if (H < 0) return fail(HTEX_E_ARG, "negative size");
+    if (nkeys < 1) return fail(HTEX_E_ARG, "nkeys must be positive, got %d", nkeys);
+    if (htex_status st = check_sort(nkeys, in->Q, ws, ws_bytes)) return st;
+    if (htex_status st = check_sort_batch(in, perm, h_out, u_out, v_out, f_out, ws, ws_bytes))
+        return st;
+    if (in->Q == 0) return ok();
+    if (H > 0) {
+        if (!key_of_h || !aligned(key_of_h, 4))
+            return fail(HTEX_E_ARG, "key_of_h must be non-NULL and 4-byte aligned");
+        const size_t n = 4 * (size_t)in->Q, nk = 4 * (size_t)H;
+        const void *outs[5] = {perm, h_out, u_out, v_out, in->footprint ? f_out : nullptr};
+        for (const void *o : outs)
+            if (overlap(o, n, key_of_h, nk))
+                return fail(HTEX_E_ARG, "sorted outputs must not overlap key_of_h");
+    }
+    return from_hip(htex::launch_sort(H, key_of_h, nkeys, in->Q, in->h, in->u, in->v,
+                                      in->footprint, perm, h_out, u_out, v_out,
+                                      in->footprint ? f_out : nullptr, ws,
                                       static_cast<hipStream_t>(stream)),
                     "sort launch");
 }
@@ -462,7 +491,7 @@ htex_status htex_sort_batch_noalloc(int32_t H, const htex_queries *in, int32_t *
                     htex::static_sort_scratch_bytes(), need);
     if (htex_status st = check_sort_batch(in, perm, h_out, u_out, v_out, f_out, ws, need))
         return st;
-    return from_hip(htex::launch_sort(H, in->Q, in->h, in->u, in->v, in->footprint, perm, h_out,
+    return from_hip(htex::launch_sort(H, nullptr, 0, in->Q, in->h, in->u, in->v, in->footprint, perm, h_out,
                                       u_out, v_out, in->footprint ? f_out : nullptr, ws,
                                       static_cast<hipStream_t>(stream)),
                     "sort launch");

@@ -100,11 +100,14 @@ hipError_t launch_sample(const SampleArgs &a, int dtype, int filter, hipStream_t
 size_t sort_workspace_bytes(int32_t H, int64_t Q);
 size_t static_sort_scratch_bytes();
 hipError_t static_sort_scratch(void **ptr);
-// Sorts by halfedge: perm, and (when u_out is non-NULL) the sorted u, v and
-// (when f_out is non-NULL) footprint; h_out may be NULL.
-hipError_t launch_sort(int32_t H, int64_t Q, const int32_t *h, const float *u, const float *v,
-                       const float *f, int32_t *perm, int32_t *h_out, float *u_out, float *v_out,
-                       float *f_out, void *ws, hipStream_t s);
+// Sorts by halfedge (or by key_of_h[h], keys 0 .. nkeys - 1, when key_of_h
+// is non-NULL): perm, and (when u_out is non-NULL) the sorted h, u, v and
+// (when f_out is non-NULL) footprint.  The workspace is sized for the key
+// range: sort_workspace_bytes(key_of_h ? nkeys : H, Q).
+hipError_t launch_sort(int32_t H, const int32_t *key_of_h, int32_t nkeys, int64_t Q,
+                       const int32_t *h, const float *u, const float *v, const float *f,
+                       int32_t *perm, int32_t *h_out, float *u_out, float *v_out, float *f_out,
+                       void *ws, hipStream_t s);
 hipError_t launch_gather_queries(const int32_t *perm, int64_t Q, const int32_t *h, const float *u,
                                  const float *v, const float *f, int32_t *ho, float *uo, float *vo,
                                  float *fo, hipStream_t s);

@@ -1,9 +1,10 @@
 // htex_sort.hip -- ordering a query batch by halfedge (optional step before
 // sampling) and moving queries and results between the two orders.
 //
-// Stable LSD radix sort of (key, input index) pairs; the key of a query is h,
-// or H for an invalid h (outside [0, H)), which sorts last.  Digits are as
-// wide as needed to cover keys 0..H in the fewest passes of at most 8 bits
+// Stable LSD radix sort of (key, input index) pairs; the key of a query is h
+// (or a caller's key of h, such as its edge), and queries with an invalid h
+// sort last.  Digits are as wide as needed to cover the keys in the fewest
+// passes of at most 8 bits
 // (three passes for a million halfedges).  The passes follow the one-sweep
 // scheme of Adinets and Merrill (2022): one read of the keys counts every
 // pass's digits up front, so each pass knows where each digit's run begins,
@@ -50,21 +51,26 @@ constexpr uint64_t kPrefix = uint64_t(2) << 62;      // this tile's and all befo
 // running; the limit only keeps the kernel finite.
 constexpr int kSpinLimit = 1 << 22;
 
-__device__ __forceinline__ uint32_t sort_key(int32_t h, int32_t H)
-{
-    return ((uint32_t)h < (uint32_t)H) ? (uint32_t)h : (uint32_t)H;
-}
-
 // The keys of a pass: computed from h (first pass) or read back (later
-// passes).
+// passes).  The key of a query is its halfedge h, or key_of_h[h] when a key
+// map is given; a query whose h lies outside [0, H), or whose mapped key
+// lies outside [0, K), takes the key K and sorts last.
 struct KeySrc {
-    const int32_t *h;     // first pass, else NULL
-    const uint32_t *k;    // later passes
-    int32_t H;
+    const int32_t *h;      // first pass, else NULL
+    const uint32_t *k;     // later passes
+    const int32_t *map;    // key of each halfedge, or NULL for h itself
+    int32_t H, K;          // halfedges; keys 0 .. K - 1 (K = H without a map)
 
+    __device__ __forceinline__ uint32_t first(int32_t hv) const
+    {
+        if ((uint32_t)hv >= (uint32_t)H) return (uint32_t)K;
+        if (!map) return (uint32_t)hv;
+        const uint32_t m = (uint32_t)map[hv];
+        return m < (uint32_t)K ? m : (uint32_t)K;
+    }
     __device__ __forceinline__ uint32_t operator()(int64_t i) const
     {
-        return h ? sort_key(h[i], H) : k[i];
+        return h ? first(h[i]) : k[i];
     }
 };
 
@@ -78,11 +84,12 @@ __global__ void __launch_bounds__(kThreads) k_clear(uint4 *p, int64_t n)
 
 // count[pass * kMaxBins + d] += the keys whose digit of that pass is d,
 // over the tiles blockIdx.x, blockIdx.x + gridDim.x, ...  With `rec`, also
-// rec[i] = (h, u, v, f).
-__global__ void __launch_bounds__(kThreads) k_count(const int32_t *h, int32_t H, int64_t Q,
-                                                    int passes, int bits, uint32_t *count,
-                                                    const float *u, const float *v,
-                                                    const float *f, float4 *rec)
+// rec[i] = (h, u, v, f); with `keys`, keys[i] = the key of query i (so that
+// a key map is read once, here, not again by the first pass).
+__global__ void __launch_bounds__(kThreads) k_count(KeySrc ks, int64_t Q, int passes, int bits,
+                                                    uint32_t *count, const float *u,
+                                                    const float *v, const float *f, float4 *rec,
+                                                    uint32_t *keys)
 {
     __shared__ uint32_t cnt[kMaxPasses][kMaxBins];
     for (int p = 0; p < kMaxPasses; ++p)
@@ -95,7 +102,7 @@ __global__ void __launch_bounds__(kThreads) k_count(const int32_t *h, int32_t H,
 #pragma unroll
         for (int r = 0; r < kPerThread; ++r) {
             const int64_t i = t0 + (int64_t)r * kThreads;
-            hv[r] = i < Q ? h[i] : 0;
+            hv[r] = i < Q ? ks.h[i] : 0;
         }
         if (rec) {
 #pragma unroll 4
@@ -108,7 +115,8 @@ __global__ void __launch_bounds__(kThreads) k_count(const int32_t *h, int32_t H,
 #pragma unroll
         for (int r = 0; r < kPerThread; ++r) {
             if (t0 + (int64_t)r * kThreads >= Q) break;
-            const uint32_t key = sort_key(hv[r], H);
+            const uint32_t key = ks.first(hv[r]);
+            if (keys) keys[t0 + (int64_t)r * kThreads] = key;
             for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][(key >> (p * bits)) & mask], 1u);
         }
     }
@@ -370,11 +378,11 @@ constexpr SortPlan sort_plan(int32_t H)
     return {passes, (kb + passes - 1) / passes};
 }
 
-// Workspace layout: the 16-byte query records; the (key, index) sets the
-// passes between the first and the last write (one set for two passes, two
-// for more); then the region cleared before every sort -- the digit counts
-// and tile tickets of every pass, and the published counts of every tile
-// of every pass.
+// Workspace layout: the 16-byte query records; the keys of a mapped sort;
+// the (key, index) sets the passes between the first and the last write
+// (one set for two passes, two for more); then the region cleared before
+// every sort -- the digit counts and tile tickets of every pass, and the
+// published counts of every tile of every pass.
 constexpr size_t kControlBytes = align256(sizeof(uint32_t) * kMaxPasses * (kMaxBins + 1));
 
 constexpr size_t sort_status_bytes(int passes, int64_t ntiles)
@@ -387,8 +395,9 @@ constexpr size_t sort_ws_bytes(int32_t H, int64_t Q)
     const SortPlan p = sort_plan(H);
     const int64_t q = Q > 0 ? Q : 1;
     const int sets = p.passes >= 3 ? 2 : p.passes - 1;
-    return align256(16 * (size_t)q) + (size_t)sets * 2 * align256(sizeof(int32_t) * (size_t)q) +
-           kControlBytes + sort_status_bytes(p.passes, cdiv(q, kTile));
+    return align256(16 * (size_t)q) + align256(sizeof(int32_t) * (size_t)q) +
+           (size_t)sets * 2 * align256(sizeof(int32_t) * (size_t)q) + kControlBytes +
+           sort_status_bytes(p.passes, cdiv(q, kTile));
 }
 
 // Device scratch of the allocation-free sort: the workspace of the largest
@@ -426,18 +435,22 @@ hipError_t static_sort_scratch(void **ptr)
     return hipSuccess;
 }
 
-hipError_t launch_sort(int32_t H, int64_t Q, const int32_t *h, const float *u, const float *v,
-                       const float *f, int32_t *perm, int32_t *h_out, float *u_out, float *v_out,
-                       float *f_out, void *ws, hipStream_t s)
+hipError_t launch_sort(int32_t H, const int32_t *key_of_h, int32_t nkeys, int64_t Q,
+                       const int32_t *h, const float *u, const float *v, const float *f,
+                       int32_t *perm, int32_t *h_out, float *u_out, float *v_out, float *f_out,
+                       void *ws, hipStream_t s)
 {
     if (Q == 0) return hipSuccess;
-    const SortPlan plan = sort_plan(H);
+    const int32_t K = key_of_h ? nkeys : H;
+    const SortPlan plan = sort_plan(K);
     const bool batch = u_out != nullptr;
     const int64_t ntiles = cdiv(Q, kTile);
     char *p = static_cast<char *>(ws);
     float4 *rec = reinterpret_cast<float4 *>(p);
     p += align256(16 * (size_t)Q);
     const size_t arr = align256(sizeof(int32_t) * (size_t)Q);
+    uint32_t *mapped = key_of_h ? reinterpret_cast<uint32_t *>(p) : nullptr;
+    p += arr;
     uint32_t *keys[2] = {};
     int32_t *idx[2] = {};
     const int nsets = plan.passes >= 3 ? 2 : plan.passes - 1;
@@ -456,12 +469,13 @@ hipError_t launch_sort(int32_t H, int64_t Q, const int32_t *h, const float *u, c
     hipError_t e = hipGetLastError();
     if (!e) {
         hipLaunchKernelGGL(k_count, dim3((uint32_t)(ntiles < kCountBlocks ? ntiles : kCountBlocks)),
-                           block,
-                           0, s, h, H, Q, plan.passes, plan.bits, count, batch ? u : nullptr,
-                           batch ? v : nullptr, batch ? f : nullptr, batch ? rec : nullptr);
+                           block, 0, s, KeySrc{h, nullptr, key_of_h, H, K}, Q, plan.passes,
+                           plan.bits, count, batch ? u : nullptr, batch ? v : nullptr,
+                           batch ? f : nullptr, batch ? rec : nullptr, mapped);
         e = hipGetLastError();
     }
-    KeySrc ks{h, nullptr, H};
+    // the first pass reads the keys the counting read wrote, or h itself
+    KeySrc ks = mapped ? KeySrc{nullptr, mapped, nullptr, H, K} : KeySrc{h, nullptr, nullptr, H, K};
     const int32_t *idx_in = nullptr;
     for (int pass = 0; pass < plan.passes && !e; ++pass) {
         const bool last = pass == plan.passes - 1;
@@ -482,7 +496,7 @@ hipError_t launch_sort(int32_t H, int64_t Q, const int32_t *h, const float *u, c
         a.ticket = ticket + pass;
         hipLaunchKernelGGL(k_pass, dim3((uint32_t)ntiles), block, 0, s, a);
         e = hipGetLastError();
-        ks = KeySrc{nullptr, a.kout, H};
+        ks = KeySrc{nullptr, a.kout, nullptr, H, K};
         idx_in = a.iout;
     }
     return e;

@@ -222,6 +222,29 @@ def test_sort_argument_checks():
     assert L.htex_last_error().decode() != ""
 
 
+def test_sort_by_key_argument_checks():
+    """The keyed sort refuses a missing or misaligned key map, nkeys < 1,
+    outputs that overlap the key map, and a workspace sized for fewer keys,
+    before launching."""
+    L = _lib.load()
+    H, Q, K = 392, 1000, 196
+    need = L.htex_sort_workspace_bytes(K, Q)
+    ws, key = 1 << 20, 9 << 24
+    q = _lib.htex_queries(Q, 1 << 24, 2 << 24, 3 << 24, None)
+    outs = [5 << 24, 6 << 24, 7 << 24, 8 << 24]
+    f = L.htex_sort_batch_by_key
+    assert f(H, 0, key, C.byref(q), *outs, None, ws, need, None) == -1
+    assert f(H, K, None, C.byref(q), *outs, None, ws, need, None) == -1
+    assert f(H, K, key + 2, C.byref(q), *outs, None, ws, need, None) == -1
+    assert f(H, K, 5 << 24, C.byref(q), *outs, None, ws, need, None) == -1
+    assert f(H, K, key, C.byref(q), *outs, None, ws, need - 1, None) == -1
+    assert f(H, K, key, None, *outs, None, ws, need, None) == -1
+    assert "key" in L.htex_last_error().decode() or L.htex_last_error().decode() != ""
+    # an empty batch needs nothing
+    q0 = _lib.htex_queries(0, None, None, None, None)
+    assert f(H, K, key, C.byref(q0), *outs, None, None, 0, None) == 0
+
+
 def test_unpermute_checks():
     L = _lib.load()
     # channels must be 1 or 4; rows aligned to their width; no overlap

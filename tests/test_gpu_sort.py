@@ -61,6 +61,56 @@ def test_sort_batch_carries_the_queries(H, Q, with_f):
         assert fo is None
 
 
+def _ref_perm_by_key(h, H, key, K):
+    hv = np.where((h >= 0) & (h < H), h, 0)
+    k = np.where((h >= 0) & (h < H), key[hv].astype(np.int64), K)
+    k = np.where((k >= 0) & (k < K), k, K)
+    return np.argsort(k, kind="stable").astype(np.int32)
+
+
+@pytest.mark.parametrize("H,K,Q", [(392, 196, 20000), (392, 1, 5000), (785950, 396966, 300001),
+                                   (70000, 300, 8193), (2048, 5000, 4097)])
+def test_sort_batch_by_key(H, K, Q):
+    """Keyed order: perm equals the stable argsort of key[h] (invalid h and
+    keys outside [0, K) last), and the sorted arrays are the input gathered
+    through perm, bit for bit."""
+    rng = np.random.default_rng(3 * H + K + Q)
+    h = rng.integers(-3, H + 3, Q).astype(np.int32)
+    key = rng.integers(0, K, H).astype(np.int32)
+    key[::97] = K + 5          # out-of-range keys sort with the invalid queries
+    key[1::101] = -2
+    u = rng.standard_normal(Q).astype(np.float32)
+    v = rng.standard_normal(Q).astype(np.float32)
+    f = rng.standard_normal(Q).astype(np.float32)
+    print(f"sort_batch_by_key H={H} K={K} Q={Q}", flush=True)
+    perm, ho, uo, vo, fo = htex.htex_sort_batch(H, t(h), t(u), t(v), t(f), key=t(key), nkeys=K)
+    torch.cuda.synchronize()
+    ref = _ref_perm_by_key(h, H, key, K)
+    np.testing.assert_array_equal(perm.cpu().numpy(), ref)
+    np.testing.assert_array_equal(ho.cpu().numpy(), h[ref])
+    for a, b in ((uo, u), (vo, v), (fo, f)):
+        np.testing.assert_array_equal(a.cpu().numpy().view(np.uint32), b[ref].view(np.uint32))
+
+
+def test_sample_in_edge_order_matches_direct():
+    """A batch ordered by the edge of its halfedge, sampled with the sorted
+    kernel and put back in input order, gives the direct path's bits."""
+    m = cube_mesh()
+    s = Setup(m, np.full(m.E, 5), has_mips=True, kind=1)
+    q = uniform_queries(m.H, 100000, 19, log2f=(-7, 0), shuffle_seed=4)
+    direct, _ = s.gpu(q, htex.HTEX_TRILINEAR)
+    prep = htex.Prepared(s.dmesh, s.pool)
+    perm, h2, u2, v2, f2 = htex.htex_sort_batch(m.H, t(q.h), t(q.u), t(q.v), t(q.f),
+                                                key=s.dmesh.edge, nkeys=m.E)
+    e = m.edge[h2.cpu().numpy()]
+    assert (e[1:] >= e[:-1]).all()
+    o = htex.htex_sample_prepared(prep, s.pool, h2, u2, v2, f2, filter=htex.HTEX_TRILINEAR,
+                                  flags=htex.HTEX_QUERIES_SORTED)
+    back = htex.htex_unpermute_results(perm, o)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(back.cpu().numpy(), direct)
+
+
 def test_sorted_input_is_identity_and_sampling_order_free():
     m = cube_mesh()
     s = Setup(m, np.full(m.E, 5), has_mips=True, kind=1)
