@@ -182,6 +182,10 @@ __global__ void __launch_bounds__(kThreads) k_pass(PassArgs a)
     const uint32_t tile = s_tile;
     const int64_t t0 = (int64_t)tile * kTile;
     const int tcount = (int)(a.Q - t0 < kTile ? a.Q - t0 : kTile);
+    int32_t gcount[kDigitsPerThread];   // this pass's batch-wide count of each of this thread's digits
+#pragma unroll
+    for (int k = 0; k < kDigitsPerThread; ++k)
+        gcount[k] = d0 + k < nb ? (int32_t)a.count[d0 + k] : 0;
     // 1. each wavefront ranks its quarter of the tile, 64 keys a round, in
     // input order: a key's rank is the wavefront's count of its digit before
     // the round plus the equal digits on lower lanes (one wavefront's LDS
@@ -190,7 +194,12 @@ __global__ void __launch_bounds__(kThreads) k_pass(PassArgs a)
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int32_t *const cnt = wcnt[w];
     uint32_t key[kPerThread];
-    int32_t rank_in_wave[kPerThread];
+    int32_t rank_in_wave[kPerThread], src[kPerThread];
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+        const int p = w * (kTile / kWaves) + r * 64 + lane;
+        src[r] = a.idx_in && p < tcount ? a.idx_in[t0 + p] : (int32_t)(t0 + p);
+    }
 #pragma unroll
     for (int r = 0; r < kPerThread; ++r) {
         const int p = w * (kTile / kWaves) + r * 64 + lane;
@@ -220,7 +229,7 @@ __global__ void __launch_bounds__(kThreads) k_pass(PassArgs a)
             for (int v = 0; v < kWaves; ++v) c[k] += wcnt[v][d0 + k];
             __hip_atomic_store(st + k, (tile == 0 ? kPrefix : kAggregate) | (uint32_t)c[k],
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            gsum += (int32_t)a.count[d0 + k];
+            gsum += gcount[k];
         }
         csum += c[k];
     }
@@ -294,7 +303,7 @@ __global__ void __launch_bounds__(kThreads) k_pass(PassArgs a)
             }
             delta[d] = grun + (int32_t)before[k] - lrun;
             lrun += c[k];
-            grun += (int32_t)a.count[d];
+            grun += gcount[k];
         }
     }
     __syncthreads();
@@ -313,7 +322,7 @@ __global__ void __launch_bounds__(kThreads) k_pass(PassArgs a)
             const uint32_t dig = (key[r] >> a.shift) & mask;
             const int slot = cnt[dig] + rank_in_wave[r];
             lkey[slot] = key[r];
-            lidx[slot] = a.idx_in ? a.idx_in[t0 + p] : (int32_t)(t0 + p);
+            lidx[slot] = src[r];
         }
     }
     __syncthreads();
