@@ -195,6 +195,23 @@ __global__ void __launch_bounds__(kThreads) k_pass(PassArgs a)
     int32_t *const cnt = wcnt[w];
     uint32_t key[kPerThread];
     int32_t rank_in_wave[kPerThread], src[kPerThread];
+    // every key and input index of this thread in flight at once
+    if (a.ks.h) {
+        int32_t hv[kPerThread];
+#pragma unroll
+        for (int r = 0; r < kPerThread; ++r) {
+            const int p = w * (kTile / kWaves) + r * 64 + lane;
+            hv[r] = p < tcount ? a.ks.h[t0 + p] : -1;
+        }
+#pragma unroll
+        for (int r = 0; r < kPerThread; ++r) key[r] = a.ks.first(hv[r]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < kPerThread; ++r) {
+            const int p = w * (kTile / kWaves) + r * 64 + lane;
+            key[r] = p < tcount ? a.ks.k[t0 + p] : 0u;
+        }
+    }
 #pragma unroll
     for (int r = 0; r < kPerThread; ++r) {
         const int p = w * (kTile / kWaves) + r * 64 + lane;
@@ -204,7 +221,6 @@ __global__ void __launch_bounds__(kThreads) k_pass(PassArgs a)
     for (int r = 0; r < kPerThread; ++r) {
         const int p = w * (kTile / kWaves) + r * 64 + lane;
         const bool valid = p < tcount;
-        key[r] = valid ? a.ks(t0 + p) : 0u;
         const uint32_t dig = (key[r] >> a.shift) & mask;
         uint64_t same = __ballot(valid);
         for (int b = 0; b < a.bits; ++b) {
