@@ -374,6 +374,23 @@ htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *p
                                  uint32_t flags, float *out, int32_t *err_count,
                                  void *stream);
 
+/* htex_sample_prepared for a batch in any order, sampled in halfedge order:
+ * the library sorts the batch by halfedge (the order a rasterizer delivers,
+ * Section 4.4, "Rendering", in which neighbouring queries read the same
+ * textures), samples it with its sorted-batch kernels, each lane reading its
+ * query as one 16-byte record through the permutation, and writes row i of
+ * out for query i, as htex_sample_prepared would (the same bits).  Flags
+ * are implied (none taken).  ws: device workspace of at least
+ * htex_sample_reordered_workspace_bytes(H, Q, pool->channels) bytes,
+ * 256-byte aligned, overlapping neither out nor the query arrays (its
+ * contents on entry do not matter).  Q < 2^31 (HTEX_E_RANGE otherwise);
+ * other arguments and errors as htex_sample_prepared. */
+size_t htex_sample_reordered_workspace_bytes(int32_t H, int64_t Q, int32_t channels);
+htex_status htex_sample_prepared_reordered(int32_t H, const void *prep, const htex_pool *pool,
+                                           const htex_queries *queries, int32_t filter,
+                                           float *out, void *ws, size_t ws_bytes,
+                                           int32_t *err_count, void *stream);
+
 /* ----------------------------------------------- anisotropic filtering --
  * The paper samples with the GPU's anisotropic filter (Section 5.1, Fig. 7).
  * Here that is the OpenGL anisotropic-filtering extension's filter applied

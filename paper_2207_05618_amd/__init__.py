@@ -275,6 +275,25 @@ def htex_sample_prepared(prep: "Prepared", pool: Pool, h, u, v, footprint=None,
     return out
 
 
+def htex_sample_prepared_reordered(prep: "Prepared", pool: Pool, h, u, v, footprint=None,
+                                   filter=HTEX_BILINEAR, out=None, err_count=None, stream=None):
+    """htex_sample_prepared for a batch in any order: the library puts it in
+    halfedge order, samples it there and writes the results in the batch's
+    own order (the same bits) -> out [Q, C]."""
+    prep.check_pool(pool)
+    q, Q = _queries(h, u, v, footprint)
+    out = _out(out, Q, pool, h.device)
+    if err_count is not None:
+        _dev(err_count, torch.int32, "err_count")
+    nbytes = int(load().htex_sample_reordered_workspace_bytes(prep.H, Q, pool.channels))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=h.device)
+    check(load().htex_sample_prepared_reordered(
+        prep.H, prep.buf.data_ptr(), C.byref(pool.c), C.byref(q), int(filter), out.data_ptr(),
+        ws.data_ptr(), nbytes, err_count.data_ptr() if err_count is not None else None,
+        _stream(stream)))
+    return out
+
+
 def htex_sample_aniso(mesh: Mesh, pool: Pool, h, u, v, jac, max_aniso: int = 16, flags=0,
                       out=None, nprobe=False, err_count=None, stream=None):
     """Anisotropic Alg. 3 (the OpenGL anisotropic filter on every fetch);

@@ -75,6 +75,9 @@ SIGNATURES = {
     "htex_unpermute_results": (C.c_int32, [C.c_int64, C.c_int32, _P, _P, _P, _P]),
     "htex_sample_prepared": (C.c_int32, [C.c_int32, _P, _P, _P, C.c_int32, C.c_uint32, _P, _P,
                                          _P]),
+    "htex_sample_reordered_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int64, C.c_int32]),
+    "htex_sample_prepared_reordered": (C.c_int32, [C.c_int32, _P, _P, _P, C.c_int32, _P, _P,
+                                                   C.c_size_t, _P, _P]),
     "htex_sample_aniso": (C.c_int32, [_P, _P, _P, _P, C.c_int32, C.c_uint32, _P, _P, _P, _P]),
     "htex_sample_aniso_prepared": (C.c_int32, [C.c_int32, _P, _P, _P, _P, C.c_int32, C.c_uint32,
                                                _P, _P, _P]),

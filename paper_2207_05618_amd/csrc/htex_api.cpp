@@ -422,8 +422,8 @@ htex_status htex_sort_queries(int32_t H, int64_t Q, const int32_t *h, int32_t *p
     if (overlap(perm, 4 * (size_t)Q, ws, ws_bytes))
         return fail(HTEX_E_ARG, "perm must not overlap the workspace");
     return from_hip(htex::launch_sort(H, nullptr, 0, Q, h, nullptr, nullptr, nullptr, perm, nullptr,
-                                      nullptr,
-                                      nullptr, nullptr, ws, static_cast<hipStream_t>(stream)),
+                                      nullptr, nullptr, nullptr, nullptr, ws,
+                                      static_cast<hipStream_t>(stream)),
                     "sort launch");
 }
 
@@ -437,7 +437,7 @@ htex_status htex_sort_batch(int32_t H, const htex_queries *in, int32_t *perm, in
         return st;
     if (in->Q == 0) return ok();
     return from_hip(htex::launch_sort(H, nullptr, 0, in->Q, in->h, in->u, in->v, in->footprint, perm, h_out,
-                                      u_out, v_out, in->footprint ? f_out : nullptr, ws,
+                                      u_out, v_out, in->footprint ? f_out : nullptr, nullptr, ws,
                                       static_cast<hipStream_t>(stream)),
                     "sort launch");
 }
@@ -465,7 +465,7 @@ htex_status htex_sort_batch_by_key(int32_t H, int32_t nkeys, const int32_t *key_
     }
     return from_hip(htex::launch_sort(H, key_of_h, nkeys, in->Q, in->h, in->u, in->v,
                                       in->footprint, perm, h_out, u_out, v_out,
-                                      in->footprint ? f_out : nullptr, ws,
+                                      in->footprint ? f_out : nullptr, nullptr, ws,
                                       static_cast<hipStream_t>(stream)),
                     "sort launch");
 }
@@ -492,7 +492,7 @@ htex_status htex_sort_batch_noalloc(int32_t H, const htex_queries *in, int32_t *
     if (htex_status st = check_sort_batch(in, perm, h_out, u_out, v_out, f_out, ws, need))
         return st;
     return from_hip(htex::launch_sort(H, nullptr, 0, in->Q, in->h, in->u, in->v, in->footprint, perm, h_out,
-                                      u_out, v_out, in->footprint ? f_out : nullptr, ws,
+                                      u_out, v_out, in->footprint ? f_out : nullptr, nullptr, ws,
                                       static_cast<hipStream_t>(stream)),
                     "sort launch");
 }
@@ -603,6 +603,75 @@ htex_status htex_sample_prepared(int32_t H, const void *prep, const htex_pool *p
     if (htex_status st = prepared_args(H, prep, pool, queries, filter, flags, out, err_count, &a))
         return st;
     return launch_prepared(a, pool, filter, flags, stream);
+}
+
+namespace {
+
+size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Workspace of htex_sample_prepared_reordered: the permutation, the query
+// records in input order, the results in sorted order, then the sort's own.
+size_t reordered_ws_bytes(int32_t H, int64_t Q, int32_t channels)
+{
+    const size_t q = (size_t)(Q > 0 ? Q : 1);
+    return round256(4 * q) + round256(16 * q) + round256(4 * (size_t)channels * q) +
+           htex::sort_workspace_bytes(H, Q);
+}
+
+}  // namespace
+
+size_t htex_sample_reordered_workspace_bytes(int32_t H, int64_t Q, int32_t channels)
+{
+    if (H < 0 || Q < 0 || (channels != 1 && channels != 4)) return 0;
+    return reordered_ws_bytes(H, Q, channels);
+}
+
+htex_status htex_sample_prepared_reordered(int32_t H, const void *prep, const htex_pool *pool,
+                                           const htex_queries *queries, int32_t filter,
+                                           float *out, void *ws, size_t ws_bytes,
+                                           int32_t *err_count, void *stream)
+{
+    htex::SampleArgs a;
+    if (htex_status st = prepared_args(H, prep, pool, queries, filter, 0, out, err_count, &a))
+        return st;
+    const int64_t Q = queries->Q;
+    if (Q == 0) return ok();
+    if (Q >= (int64_t(1) << 31)) return fail(HTEX_E_RANGE, "reordering needs Q < 2^31");
+    const size_t need = reordered_ws_bytes(H, Q, pool->channels);
+    if (!ws || !aligned(ws, 256)) return fail(HTEX_E_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(HTEX_E_ARG, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
+                    need);
+    const size_t n = 4 * (size_t)Q, rows = 4 * (size_t)pool->channels * (size_t)Q;
+    if (overlap(out, rows, ws, ws_bytes)) return fail(HTEX_E_ARG, "out must not overlap the workspace");
+    const void *ins[4] = {queries->h, queries->u, queries->v, queries->footprint};
+    for (const void *in : ins)
+        if (overlap(in, n, ws, ws_bytes))
+            return fail(HTEX_E_ARG, "the queries must not overlap the workspace");
+    char *p = static_cast<char *>(ws);
+    int32_t *perm = reinterpret_cast<int32_t *>(p);
+    p += round256(n);
+    void *records = p;
+    p += round256(16 * (size_t)Q);
+    float *sorted_out = reinterpret_cast<float *>(p);
+    p += round256(rows);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    // 1. the permutation to halfedge order, and the queries as records
+    if (const htex_status st = from_hip(
+            htex::launch_sort(H, nullptr, 0, Q, queries->h, queries->u, queries->v,
+                              queries->footprint, perm, nullptr, nullptr, nullptr, nullptr,
+                              records, p, s),
+            "sort launch"))
+        return st;
+    // 2. the batch sampled in halfedge order, each lane reading its query's
+    // record through the permutation
+    a.order = perm;
+    a.qrec = records;
+    a.out = sorted_out;
+    if (const htex_status st = launch_prepared(a, pool, filter, 0, stream)) return st;
+    // 3. the results back in input order
+    return from_hip(htex::launch_unpermute(perm, Q, pool->channels, sorted_out, out, s),
+                    "unpermute launch");
 }
 
 namespace {

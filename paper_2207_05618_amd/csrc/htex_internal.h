@@ -33,6 +33,8 @@ struct SampleArgs {
     int32_t channels;           // values per texel and per output row: 4 or 1
     int32_t has_mips;           // prepared path: the pool's layout has mip levels
     int64_t total_texels;       // prepared path: size of the pool in texels
+    const int32_t *order;       // prepared forward, nullable: query q is record order[q] ...
+    const void *qrec;           // ... of these 16-byte records (h bits, u, v, footprint)
 };
 
 // Offset of mip level l inside an edge of log2 resolution k, in texels:
@@ -104,10 +106,13 @@ hipError_t static_sort_scratch(void **ptr);
 // is non-NULL): perm, and (when u_out is non-NULL) the sorted h, u, v and
 // (when f_out is non-NULL) footprint.  The workspace is sized for the key
 // range: sort_workspace_bytes(key_of_h ? nkeys : H, Q).
+// With `records` (16 bytes per query), the queries are also copied there
+// in input order as (h bits, u, v, footprint), and no sorted arrays are
+// written (u_out must then be NULL).
 hipError_t launch_sort(int32_t H, const int32_t *key_of_h, int32_t nkeys, int64_t Q,
                        const int32_t *h, const float *u, const float *v, const float *f,
                        int32_t *perm, int32_t *h_out, float *u_out, float *v_out, float *f_out,
-                       void *ws, hipStream_t s);
+                       void *records, void *ws, hipStream_t s);
 hipError_t launch_gather_queries(const int32_t *perm, int64_t Q, const int32_t *h, const float *u,
                                  const float *v, const float *f, int32_t *ho, float *uo, float *vo,
                                  float *fo, hipStream_t s);

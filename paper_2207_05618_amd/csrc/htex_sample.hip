@@ -82,12 +82,23 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a)
 // SCATTERED selects the per-tap predicated fetch for batches in random
 // order (same results).  A record that does not fit the pool (prepared for
 // another layout) makes its query invalid.
-template <int DT, int CH, bool TRI, bool SCATTERED>
+template <int DT, int CH, bool TRI, bool SCATTERED, bool GATHER = false>
 __device__ __forceinline__ void sample_one_prepared(const SampleArgs &a, int64_t q)
 {
-    const int32_t h = __builtin_nontemporal_load(a.qh + q);
-    const float u = __builtin_nontemporal_load(a.qu + q);
-    const float v = __builtin_nontemporal_load(a.qv + q);
+    int32_t h;
+    float u, v, fq = 0.0f;
+    if constexpr (GATHER) {
+        // query q of a batch sampled in another order: record order[q]
+        const float4 r = static_cast<const float4 *>(a.qrec)[__builtin_nontemporal_load(a.order + q)];
+        h = __float_as_int(r.x);
+        u = r.y;
+        v = r.z;
+        fq = r.w;
+    } else {
+        h = __builtin_nontemporal_load(a.qh + q);
+        u = __builtin_nontemporal_load(a.qu + q);
+        v = __builtin_nontemporal_load(a.qv + q);
+    }
     PrepRec rec;
     bool valid = ((uint32_t)h < (uint32_t)a.H) && isfinite(u) && isfinite(v);
     if (valid) {
@@ -101,7 +112,7 @@ __device__ __forceinline__ void sample_one_prepared(const SampleArgs &a, int64_t
         return;
     }
     Lod L{0, 0, 0.0f, 1.0f};
-    if constexpr (TRI) L = lod_of(__builtin_nontemporal_load(a.qf + q));
+    if constexpr (TRI) L = lod_of(GATHER ? fq : __builtin_nontemporal_load(a.qf + q));
     FetchSpec fs[3];
     fetch_specs(h, rec.next, rec.prev, u, v, fs);
     float4 C = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -168,7 +179,7 @@ constexpr int kTasks = 128;   // per wavefront: at most one Next and one Prev fe
 // caches; the compaction saves 6-10% there.  A large float32 pool is bound
 // by the memory pipeline, and there the compaction costs 2-3%.  All 64
 // lanes of the wave must call it; `live` marks lanes that hold a query.
-template <int DT, int CH, bool TRI>
+template <int DT, int CH, bool TRI, bool GATHER = false>
 __device__ __forceinline__ void sample_wave_prepared(const SampleArgs &a, int64_t q, bool live,
                                                      Task *tasks)
 {
@@ -176,10 +187,19 @@ __device__ __forceinline__ void sample_wave_prepared(const SampleArgs &a, int64_
     int32_t h = 0;
     float u = 0.0f, v = 0.0f, f = 0.0f;
     if (live) {
-        h = __builtin_nontemporal_load(a.qh + q);
-        u = __builtin_nontemporal_load(a.qu + q);
-        v = __builtin_nontemporal_load(a.qv + q);
-        if constexpr (TRI) f = __builtin_nontemporal_load(a.qf + q);
+        if constexpr (GATHER) {
+            const float4 r =
+                static_cast<const float4 *>(a.qrec)[__builtin_nontemporal_load(a.order + q)];
+            h = __float_as_int(r.x);
+            u = r.y;
+            v = r.z;
+            if constexpr (TRI) f = r.w;
+        } else {
+            h = __builtin_nontemporal_load(a.qh + q);
+            u = __builtin_nontemporal_load(a.qu + q);
+            v = __builtin_nontemporal_load(a.qv + q);
+            if constexpr (TRI) f = __builtin_nontemporal_load(a.qf + q);
+        }
     }
     bool valid = live && ((uint32_t)h < (uint32_t)a.H) && isfinite(u) && isfinite(v);
     PrepRec rec = PrepRec{};
@@ -282,19 +302,23 @@ __device__ __forceinline__ void sample_wave_prepared(const SampleArgs &a, int64_
 // sampled level read (coherent batches); 1 one lane per query, in-bounds
 // taps only (scattered batches); 2 the wavefront-compacted path
 // (VALU-bound launches).  All three give the same bits.
-enum { kPrepLane = 0, kPrepScattered = 1, kPrepWave = 2 };
+// MODE: the kernel (kPrepLane, kPrepScattered, kPrepWave), plus kPrepGather
+// for a batch read through an order array (SampleArgs::order, ::qrec).
+enum { kPrepLane = 0, kPrepScattered = 1, kPrepWave = 2, kPrepGather = 4 };
 
 template <int DT, int CH, bool TRI, int MODE>
 __global__ void __launch_bounds__(kBlock) k_sample_prep(SampleArgs a)
 {
+    constexpr int KIND = MODE & 3;
+    constexpr bool GATHER = (MODE & kPrepGather) != 0;
     const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if constexpr (MODE == kPrepWave) {
+    if constexpr (KIND == kPrepWave) {
         __shared__ Task tasks[kBlock / 64][kTasks];
         if (q - (int64_t)__lane_id() >= a.Q) return;   // the whole wavefront is past the end
-        sample_wave_prepared<DT, CH, TRI>(a, q, q < a.Q, tasks[threadIdx.x >> 6]);
+        sample_wave_prepared<DT, CH, TRI, GATHER>(a, q, q < a.Q, tasks[threadIdx.x >> 6]);
     } else {
         if (q >= a.Q) return;
-        sample_one_prepared<DT, CH, TRI, MODE == kPrepScattered>(a, q);
+        sample_one_prepared<DT, CH, TRI, KIND == kPrepScattered, GATHER>(a, q);
     }
 }
 
@@ -408,6 +432,18 @@ template <int DT, int CH, bool TRI> struct FwdPrepWave {
         return launch_fwd_prep<DT, CH, TRI, kPrepWave>(a, s);
     }
 };
+template <int DT, int CH, bool TRI> struct FwdPrepGather {
+    static hipError_t run(const SampleArgs &a, hipStream_t s)
+    {
+        return launch_fwd_prep<DT, CH, TRI, kPrepLane | kPrepGather>(a, s);
+    }
+};
+template <int DT, int CH, bool TRI> struct FwdPrepWaveGather {
+    static hipError_t run(const SampleArgs &a, hipStream_t s)
+    {
+        return launch_fwd_prep<DT, CH, TRI, kPrepWave | kPrepGather>(a, s);
+    }
+};
 
 }  // namespace
 
@@ -449,9 +485,13 @@ hipError_t launch_sample_prepared(const SampleArgs &a, int dtype, int filter, bo
                                   bool cache_resident, hipStream_t s)
 {
     if (a.Q == 0) return hipSuccess;
-    if (scattered) return dispatch<FwdPrepScattered>(a, dtype, filter, s);
     // VALU-bound: quantized texels, or a pool that stays in the caches
-    if (dtype != HTEX_F32 || cache_resident) return dispatch<FwdPrepWave>(a, dtype, filter, s);
+    const bool valu = dtype != HTEX_F32 || cache_resident;
+    if (a.order)   // a batch read through an order: its sorted-batch kernels
+        return valu ? dispatch<FwdPrepWaveGather>(a, dtype, filter, s)
+                    : dispatch<FwdPrepGather>(a, dtype, filter, s);
+    if (scattered) return dispatch<FwdPrepScattered>(a, dtype, filter, s);
+    if (valu) return dispatch<FwdPrepWave>(a, dtype, filter, s);
     return dispatch<FwdPrep>(a, dtype, filter, s);
 }
 

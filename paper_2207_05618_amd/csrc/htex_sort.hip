@@ -112,12 +112,14 @@ __global__ void __launch_bounds__(kThreads) k_count(KeySrc ks, int64_t Q, int pa
                     rec[i] = make_float4(__int_as_float(hv[r]), u[i], v[i], f ? f[i] : 0.0f);
             }
         }
+        uint32_t key[kPerThread];   // every key of this thread (and its map lookup) in flight at once
+#pragma unroll
+        for (int r = 0; r < kPerThread; ++r) key[r] = ks.first(hv[r]);
 #pragma unroll
         for (int r = 0; r < kPerThread; ++r) {
             if (t0 + (int64_t)r * kThreads >= Q) break;
-            const uint32_t key = ks.first(hv[r]);
-            if (keys) keys[t0 + (int64_t)r * kThreads] = key;
-            for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][(key >> (p * bits)) & mask], 1u);
+            if (keys) keys[t0 + (int64_t)r * kThreads] = key[r];
+            for (int p = 0; p < passes; ++p) atomicAdd(&cnt[p][(key[r] >> (p * bits)) & mask], 1u);
         }
     }
     __syncthreads();
@@ -463,15 +465,16 @@ hipError_t static_sort_scratch(void **ptr)
 hipError_t launch_sort(int32_t H, const int32_t *key_of_h, int32_t nkeys, int64_t Q,
                        const int32_t *h, const float *u, const float *v, const float *f,
                        int32_t *perm, int32_t *h_out, float *u_out, float *v_out, float *f_out,
-                       void *ws, hipStream_t s)
+                       void *records, void *ws, hipStream_t s)
 {
     if (Q == 0) return hipSuccess;
     const int32_t K = key_of_h ? nkeys : H;
     const SortPlan plan = sort_plan(K);
-    const bool batch = u_out != nullptr;
+    const bool batch = u_out != nullptr;            // the sorted arrays, gathered by the last pass
+    const bool copy = batch || records != nullptr;  // the queries as records
     const int64_t ntiles = cdiv(Q, kTile);
     char *p = static_cast<char *>(ws);
-    float4 *rec = reinterpret_cast<float4 *>(p);
+    float4 *rec = records ? static_cast<float4 *>(records) : reinterpret_cast<float4 *>(p);
     p += align256(16 * (size_t)Q);
     const size_t arr = align256(sizeof(int32_t) * (size_t)Q);
     uint32_t *mapped = key_of_h ? reinterpret_cast<uint32_t *>(p) : nullptr;
@@ -495,8 +498,8 @@ hipError_t launch_sort(int32_t H, const int32_t *key_of_h, int32_t nkeys, int64_
     if (!e) {
         hipLaunchKernelGGL(k_count, dim3((uint32_t)(ntiles < kCountBlocks ? ntiles : kCountBlocks)),
                            block, 0, s, KeySrc{h, nullptr, key_of_h, H, K}, Q, plan.passes,
-                           plan.bits, count, batch ? u : nullptr, batch ? v : nullptr,
-                           batch ? f : nullptr, batch ? rec : nullptr, mapped);
+                           plan.bits, count, copy ? u : nullptr, copy ? v : nullptr,
+                           copy ? f : nullptr, copy ? rec : nullptr, mapped);
         e = hipGetLastError();
     }
     // the first pass reads the keys the counting read wrote, or h itself

@@ -245,6 +245,32 @@ def test_sort_by_key_argument_checks():
     assert f(H, K, key, C.byref(q0), *outs, None, None, 0, None) == 0
 
 
+def test_sample_reordered_argument_checks():
+    """The reordered sampler refuses a short or misaligned workspace, one
+    that overlaps the output or the query arrays, and oversized batches,
+    before launching; its workspace grows with the batch."""
+    L = _lib.load()
+    H, Q = 392, 1000
+    assert L.htex_sample_reordered_workspace_bytes(H, Q, 3) == 0
+    need = L.htex_sample_reordered_workspace_bytes(H, Q, 4)
+    assert need >= L.htex_sample_reordered_workspace_bytes(H, Q, 1) > 0
+    assert L.htex_sample_reordered_workspace_bytes(H, 10 * Q, 4) > need
+    lr = np.full(196, 4, np.uint8)
+    base, total = gpool.layout(lr, True)
+    pool = _lib.htex_pool(196, 0, 1, 4, 4, 0, total, 1 << 30, 2 << 30, 3 << 30, None)
+    q = _lib.htex_queries(Q, 1 << 24, 2 << 24, 3 << 24, 4 << 24)
+    f = L.htex_sample_prepared_reordered
+    prep, out, ws = 5 << 24, 6 << 24, 8 << 24
+    assert f(H, prep, C.byref(pool), C.byref(q), 1, out, ws, need - 1, None, None) == -1
+    assert f(H, prep, C.byref(pool), C.byref(q), 1, out, ws + 16, need, None, None) == -1
+    assert f(H, prep, C.byref(pool), C.byref(q), 1, out, None, need, None, None) == -1
+    assert f(H, prep, C.byref(pool), C.byref(q), 1, ws + 256, ws, need, None, None) == -1
+    assert f(H, prep, C.byref(pool), C.byref(q), 1, out, 2 << 24, need, None, None) == -1
+    big = _lib.htex_queries(1 << 31, 1 << 24, 2 << 24, 3 << 24, 4 << 24)
+    assert f(H, prep, C.byref(pool), C.byref(big), 1, out, ws, 1 << 45, None, None) == -3
+    assert L.htex_last_error().decode() != ""
+
+
 def test_unpermute_checks():
     L = _lib.load()
     # channels must be 1 or 4; rows aligned to their width; no overlap

@@ -130,6 +130,13 @@ def test_frame_prepared_equals_plain(frame):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(p4.cpu().numpy(), np.argsort(qu.h, kind="stable"))
     np.testing.assert_array_equal(o4.cpu().numpy(), out[perm])
+    del p4, h4, u4, v4, f4, o4s, o4
+    # the same in one call: sorted, sampled through the permutation, and
+    # written back in the shuffled order
+    o5 = htex.htex_sample_prepared_reordered(prep, pool, hu, uu, vu, fu,
+                                             filter=htex.HTEX_TRILINEAR)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(o5.cpu().numpy(), out[perm])
 
 
 def test_frame_quantized_error_bounds(frame):

@@ -111,6 +111,46 @@ def test_sample_in_edge_order_matches_direct():
     np.testing.assert_array_equal(back.cpu().numpy(), direct)
 
 
+@pytest.mark.parametrize("Q", [0, 1, 4097, 100003])
+@pytest.mark.parametrize("dtype,channels,tri", [(htex.HTEX_F32, 4, True),
+                                                (htex.HTEX_F32, 1, False),
+                                                (htex.HTEX_BF16, 4, True),
+                                                (htex.HTEX_FP8_E4M3, 1, True)])
+def test_sample_reordered_matches_direct(Q, dtype, channels, tri):
+    """One call that sorts a shuffled batch, samples it in halfedge order
+    through the permutation and writes the rows in the batch's own order
+    gives htex_sample_prepared's bits, invalid queries (NaN rows, counted)
+    included, for the lane and the wavefront kernels."""
+    m = cube_mesh()
+    s = Setup(m, np.full(m.E, 4), has_mips=tri, kind=1, channels=channels)
+    pool = s.pool if dtype == htex.HTEX_F32 else htex.htex_quantize(s.pool, dtype)
+    q = uniform_queries(m.H, Q, 41 + Q, log2f=(-6, 0), shuffle_seed=6) if Q else None
+    h = q.h.copy() if Q else np.zeros(0, np.int32)
+    if Q > 10:
+        h[::997] = -1
+        h[5::1009] = m.H + 2
+    u = q.u if Q else np.zeros(0, np.float32)
+    v = q.v if Q else np.zeros(0, np.float32)
+    f = q.f if Q else np.zeros(0, np.float32)
+    filt = htex.HTEX_TRILINEAR if tri else htex.HTEX_BILINEAR
+    prep = htex.Prepared(s.dmesh, pool)
+    e0 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    e1 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    print(f"reordered Q={Q} dtype={dtype} C={channels} tri={tri}", flush=True)
+    ft = t(f) if tri else None
+    direct = htex.htex_sample_prepared(prep, pool, t(h), t(u), t(v), ft, filter=filt,
+                                       err_count=e0)
+    got = htex.htex_sample_prepared_reordered(prep, pool, t(h), t(u), t(v), ft, filter=filt,
+                                              err_count=e1)
+    torch.cuda.synchronize()
+    d, g = direct.cpu().numpy(), got.cpu().numpy()
+    assert g.shape == d.shape
+    np.testing.assert_array_equal(g.view(np.uint32), d.view(np.uint32))
+    assert int(e1.item()) == int(e0.item())
+    if Q > 10:
+        assert int(e0.item()) > 0
+
+
 def test_sorted_input_is_identity_and_sampling_order_free():
     m = cube_mesh()
     s = Setup(m, np.full(m.E, 5), has_mips=True, kind=1)
