@@ -4,23 +4,23 @@
 // Stable LSD radix sort of (key, input index) pairs; the key of a query is h
 // (or a caller's key of h, such as its edge), and queries with an invalid h
 // sort last.  Digits are as wide as needed to cover the keys in the fewest
-// passes of at most 8 bits
-// (three passes for a million halfedges).  The passes follow the one-sweep
-// scheme of Adinets and Merrill (2022): one read of the keys counts every
-// pass's digits up front, so each pass knows where each digit's run begins,
-// and each pass is then a single launch over tiles of kTile keys in which
-// tile t learns, for each digit, how many keys of the tiles before it share
-// that digit from the tiles before it (decoupled look-back over published
-// per-tile counts) instead of from a separate histogram and scan.
+// passes of at most 8 bits (three passes for a million halfedges).  The
+// passes follow the one-sweep scheme of Adinets and Merrill (2022): one read
+// of the keys counts every pass's digits up front, so a pass knows where
+// each digit's run begins in the output, and each pass is then a single
+// launch over tiles of kTile keys.  Tile t finds how many keys of each digit
+// the tiles before it hold by decoupled look-back over the counts those
+// tiles publish, instead of from a separate histogram and scan.
 //
 // Inside a tile the keys are ranked stably: each wavefront ranks its quarter
 // on its own (ballots within a round of 64 keys and the wavefront's running
 // digit counts in LDS), one scan per digit across the four wavefronts places
 // the quarters, and the tile is written from LDS in sorted order, so
-// consecutive lanes store consecutive addresses of a digit's run.  A sorted
-// batch: the counting read also copies the queries into 16-byte records
-// (h, u, v, footprint), and the last pass gathers each output row's record
-// -- one 16-byte read per query instead of one per array.
+// consecutive lanes store consecutive addresses of a digit's run.  The
+// counting read can also copy the queries into 16-byte records (h, u, v,
+// footprint): for a sorted batch the last pass then gathers each output
+// row's record -- one 16-byte read per query instead of one per array --
+// and for sampling through the permutation the records stay in input order.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -350,11 +350,11 @@ __global__ void __launch_bounds__(kThreads) k_pass(PassArgs a)
         const uint32_t k = lkey[o];
         const uint32_t dg = (k >> a.shift) & mask;
         const int32_t to = delta[dg] + o;
-        const int32_t src = lidx[o];
+        const int32_t from = lidx[o];
         if (a.kout) a.kout[to] = k;
-        a.iout[to] = src;
+        a.iout[to] = from;
         if (a.rec) {
-            const float4 r = a.rec[src];
+            const float4 r = a.rec[from];
             a.ho[to] = __float_as_int(r.x);
             a.uo[to] = r.y;
             a.vo[to] = r.z;
