@@ -108,17 +108,14 @@ __global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
 // binned queries: consecutive queries of one cell share their four target
 // texels, so their contributions are summed in registers and added to the
 // tile once per run (the coarser level of a trilinear fetch keeps a run of
-// its own, and so does the Next and Prev fetches' coarser level; trilinear
-// runs read each query's inputs one query ahead).  Queries on other
-// halfedges, or whose taps fall outside the cell range, take the per-query
-// path.
+// its own; trilinear runs read each query's inputs one query ahead).  Next
+// and Prev textures of the own size ride on these runs and collect their
+// taps in two small strips, one line of texels along the shared edge per
+// level, so such a block's arena holds only its own texture.  Queries on
+// other halfedges, or whose taps fall outside the cell range, take the
+// per-query path.
 constexpr int kTiles = 32;
 constexpr int kArenaFloats = 16384;   // 64 KB
-// Bilinear batches whose textures have at most 32 x 32 texels need one
-// level per fetch, 16 KB a tile in RGBA: a 32 KB arena holds the own tile
-// and a neighbour's, and leaves room for three blocks per compute unit
-// (measured 6% faster than two blocks with 64 KB on config 4).
-constexpr int kArenaSmall = 8192;
 constexpr int kBwdPerThread = 16;
 constexpr int kBwdChunk = kBlock * kBwdPerThread;
 constexpr int kDenseMaxLog2 = 5;
@@ -131,6 +128,22 @@ __host__ __device__ constexpr int dense_cells_before(int k, int l)
     return c;
 }
 constexpr int kDenseCells = dense_cells_before(kDenseMaxLog2, kDenseMaxLog2 + 1);
+// a neighbour strip: one line of texels per level, n = 2^(k - l) on level l
+constexpr int kStripTexels = (2 << kDenseMaxLog2) - 1;
+// Bilinear batches whose textures have at most 32 x 32 texels need one
+// level per fetch, 16 KB a tile in RGBA: this arena holds a dense block's
+// strips and two tiles (the second halfedge's in a block that straddles
+// two, whose queries would otherwise fall back to global atomics), and
+// leaves room for three blocks per compute unit.  Trilinear batches keep
+// the 64 KB arena: with this one a straddling block's second texture and
+// mips overflow to global atomics, which cost more than the third block
+// gains (847 against 713 us on config 4).
+constexpr int kArenaSmall = 8192 + 2 * 4 * kStripTexels;
+// texels of levels 0 .. l - 1 (l <= k + 1): 2^(k+1) - 2^(k+1-l)
+__host__ __device__ constexpr int strip_before(int k, int l) { return (2 << k) - ((2 << k) >> l); }
+static_assert(strip_before(0, 1) == 1 && strip_before(5, 6) == kStripTexels &&
+                  strip_before(5, 1) == 32 && strip_before(3, 2) == 12,
+              "strip offsets");
 constexpr int kCellsPerThread = (kDenseCells + kBlock - 1) / kBlock;
 
 // Cell key of a level plan on level l of a texture of log2 size k, or -1
@@ -205,18 +218,6 @@ __device__ __forceinline__ void add_tap(float *arena, int32_t base_f, uint32_t r
     }
 }
 
-// The transpose of Alg. 3 for query q: every in-bounds tap of every fetch
-// and level receives (om w / W) dL/dout.  With `runs`, no tap is added:
-// the plans of all fetches and levels, 1 / W and dL/dout are handed back
-// for the caller to accumulate.  Returns false for an invalid query.
-struct QueryPlans {
-    int nlev[3];
-    int lv[3][2];
-    LevelPlan p[3][2];
-    float rw;      // 1 / W
-    float4 g;      // dL/dout
-};
-
 // A query's inputs, read ahead of its scatter.
 struct QIn {
     float u, v, f;
@@ -259,20 +260,19 @@ __device__ __forceinline__ Topo topo_of(const SampleArgs &a, int32_t h)
     return t;
 }
 
-// `known` (nullable): the navigation of the query's halfedge, when the
-// caller already has it (every binned query of a dense block shares it).
+// The transpose of Alg. 3 for query q: every in-bounds tap of every fetch
+// and level receives (om w / W) dL/dout.  Returns false for an invalid
+// query.
 template <int CH, bool TRI>
 __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, const TileTable &T,
-                                              int32_t (&memo_key)[3][2], int32_t (&memo_base)[3][2],
-                                              bool runs, QueryPlans &qp, int32_t hk,
-                                              const Topo *known, const QIn *pre = nullptr)
+                                              int32_t (&memo_key)[3][2], int32_t (&memo_base)[3][2])
 {
-    const int32_t h = known ? hk : a.qh[q];
-    const float u = pre ? pre->u : a.qu[q], v = pre ? pre->v : a.qv[q];
+    const int32_t h = a.qh[q];
+    const float u = a.qu[q], v = a.qv[q];
     if (!((uint32_t)h < (uint32_t)a.H) || !isfinite(u) || !isfinite(v)) return false;
-    const Topo tp = known ? *known : topo_of(a, h);
+    const Topo tp = topo_of(a, h);
     Lod L{0, 0, 0.0f, 1.0f};
-    if constexpr (TRI) L = lod_of(pre ? pre->f : a.qf[q]);
+    if constexpr (TRI) L = lod_of(a.qf[q]);
     FetchSpec fs[3];
     fetch_specs(h, tp.n1, tp.p1, u, v, fs);
     const int32_t *es = tp.es, *ks = tp.ks;
@@ -293,7 +293,7 @@ __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, co
             if (sl < nl[s]) W += (pl[s][sl].wx0 + pl[s][sl].wx1) * (pl[s][sl].wy0 + pl[s][sl].wy1);
         }
     }
-    const float4 g4 = pre ? pre->g : load_row<CH>(a.dout, q);
+    const float4 g4 = load_row<CH>(a.dout, q);
     const float rW = 1.0f / W;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
@@ -304,12 +304,6 @@ __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, co
         for (int sl = 0; sl < (TRI ? 2 : 1); ++sl) {
             if (sl >= nlev) break;
             const LevelPlan &p = pl[s][sl];
-            if (runs) {
-                qp.nlev[s] = nlev;
-                qp.lv[s][sl] = lv[sl];
-                qp.p[s][sl] = p;
-                continue;
-            }
             if (!p.act) continue;
             const int m = ks[s] - lv[sl];
             const uint32_t lo = level_offset32(ks[s], lv[sl]);
@@ -334,9 +328,27 @@ __device__ __forceinline__ bool scatter_query(const SampleArgs &a, int64_t q, co
             }
         }
     }
-    qp.rw = rW;
-    qp.g = g4;
     return true;
+}
+
+// One axis of a neighbour fetch as a map of texel indices: x' = sg x + an n
+// + ac on a level of n texels a side, from the own fetch's index x on the
+// axis that reads the same query coordinate.  The neighbour axis reads
+// (neg ? -c : c) under its reflection `flip`, the own axis c under `flip0`
+// (Alg. 2: x -> 1 - x per axis); the map sends texel centres to texel
+// centres and keeps distances.
+struct AxisMap {
+    int32_t sg, an, ac;
+};
+
+__device__ __forceinline__ AxisMap mirror_axis(bool neg, bool flip, bool flip0)
+{
+    const int32_t rho0 = flip0 ? 1 : 0, rs = flip ? 1 : 0;
+    AxisMap m;
+    m.sg = ((neg != flip) != flip0) ? -1 : 1;
+    m.an = m.sg == 1 ? rs - rho0 : rho0 + rs;
+    m.ac = m.sg == 1 ? 0 : -1;
+    return m;
 }
 
 template <int CH, bool TRI, int CAP>
@@ -356,7 +368,6 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
     if (threadIdx.x < kTiles) entry[threadIdx.x] = kFree;
     const int64_t q0 = (int64_t)blockIdx.x * kBwdChunk;
     if (threadIdx.x == 0) {
-        used = 0;
         // bin by tap cell when the block's middle query shares its
         // halfedge with the first or the last (in a sorted batch that
         // halfedge then holds at least half of the block) and its texture
@@ -365,6 +376,8 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
         const int32_t hf = a.qh[q0], hm = a.qh[q0 + (ql - q0) / 2], hl = a.qh[ql];
         dense_h = ((hm == hf || hm == hl) && (uint32_t)hm < (uint32_t)a.H &&
                    a.log2res[a.edge[hm]] <= kDenseMaxLog2) ? hm : -1;
+        // a dense block's Next and Prev strips (below) open the arena
+        used = dense_h >= 0 ? 2 * CH * kStripTexels : 0;
     }
     __syncthreads();
     const TileTable T{arena, entry, &used, CAP};
@@ -374,13 +387,13 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
 #pragma unroll
     for (int s = 0; s < 3; ++s)
         for (int sl = 0; sl < 2; ++sl) memo_key[s][sl] = -1;
-    QueryPlans qp;
-    const int32_t hb = dense_h;
+    // block-uniform: its navigation is read with scalar loads
+    const int32_t hb = __builtin_amdgcn_readfirstlane(dense_h);
     if (hb < 0) {
         for (int r = 0; r < kBwdPerThread; ++r) {
             const int64_t q = q0 + (int64_t)r * kBlock + threadIdx.x;
             if (q >= a.Q) break;
-            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, false, qp, 0, nullptr);
+            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base);
         }
     } else {
         // 1. the tap cell of each query's own fetch on its finer level
@@ -459,121 +472,197 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
                                   (uint16_t)(r * kBlock + threadIdx.x);
         __syncthreads();
         // 4. runs of binned queries, kBwdPerThread consecutive entries per
-        // thread.  Queries of one cell share the four texels of their own
-        // fetch's finer level, so those contributions are summed over the
-        // run; the coarser level's cell changes less often than the query
-        // does and gets a run of its own.  Every binned query has the
-        // block's halfedge, so its Next and Prev fetches go to the same two
-        // textures; their coarser level, where their taps crowd onto few
-        // texels, keeps runs too.  (Runs on every level of every fetch need
-        // more registers than two wavefronts per SIMD leave.)  A run is
-        // added to its tile when its tap cell changes.
+        // thread.  Queries of one cell share the four taps of their own
+        // fetch's finer level, so their contributions are summed in
+        // registers over the run and added to the tiles when the cell
+        // changes; the coarser level's cell changes less often than the
+        // query does and gets a run of its own.
+        //
+        // The Next and Prev fetches ride on these runs where their texture
+        // has the own texture's size.  Alg. 3 reads them at (v, -u) and
+        // (-v, u), each under its own Alg. 2 reflection: per axis an index
+        // map (AxisMap) that sends texel centres to texel centres and keeps
+        // distances, on the same level (same size, same footprint).  Each
+        // tap of such a fetch is then the image of a tap of the own fetch,
+        // with the same bilinear weight (axis_taps forms the weights of both
+        // from the same exact fraction of the coordinate), so a run's four
+        // sums go to every fetch whose texture holds their images, and W
+        // counts each own tap once per fetch that holds it.  A neighbour
+        // texture of another size is planned and added per query.
         constexpr int NL = TRI ? 2 : 1;
-        auto run_slot = [](int s, int sl) { return s == 0 || sl == 1; };
         const int i0 = threadIdx.x * kBwdPerThread;
         const int i1 = i0 + kBwdPerThread < nbinned ? i0 + kBwdPerThread : nbinned;
         const Topo tb = topo_of(a, hb);
-        int32_t rkey[3][NL], rbase[3][NL];
-        float4 acc[3][NL][4];
-#pragma unroll
-        for (int s = 0; s < 3; ++s)
-#pragma unroll
-            for (int sl = 0; sl < NL; ++sl) rkey[s][sl] = -1;
-        // the tile of fetch s's level l (the own fetch's were claimed above)
-        auto tile = [&](int s, int sl, int l) -> int32_t {
-            if (s == 0) return own_base[l];
-            const int32_t key = tb.es[s] * 16 + l;
-            if (memo_key[s][sl] == key) return memo_base[s][sl];
-            const int32_t bf = find_tile(T, key, (int64_t)CH << (2 * (tb.ks[s] - l)));
-            if (bf >= 0) {
-                memo_key[s][sl] = key;
-                memo_base[s][sl] = bf;
-            }
-            return bf;
+        const int rho0 = flip0 ? 1 : 0;
+        const bool eq1 = tb.ks[1] == k0, eq2 = tb.ks[2] == k0;
+        // Own taps (i, j) on a level of n texels a side lie in 0 .. n - 1 on
+        // both axes.  Those of Next are (edge, 0 .. n - 1) and those of Prev
+        // (0 .. n - 1, edge), with edge = -1, or n under the own fetch's
+        // reflection: one line along each shared edge, the index along it
+        // a strip index.  `image` maps a strip texel into its texture.
+        auto holder = [&](int32_t i, int32_t j, int32_t n, int32_t edge) -> int {
+            const bool in_i = (uint32_t)i < (uint32_t)n, in_j = (uint32_t)j < (uint32_t)n;
+            return (in_i && in_j) ? 0 : (eq1 && i == edge && in_j) ? 1
+                                      : (eq2 && j == edge && in_i) ? 2 : -1;
         };
-        auto flush = [&](int s, int sl) {
-            const int32_t key = rkey[s][sl];
-            if (key < 0) return;
-            const int l = key >> 20, k = tb.ks[s], m = k - l, n = 1 << m;
-            const int32_t ti = (key & 1023) - 1, tj = ((key >> 10) & 1023) - 1;
-            const uint32_t lo = level_offset32(k, l);
+        const AxisMap nx = mirror_axis(false, tb.flips[1], flip0);   // Next: x' = v
+        const AxisMap ny = mirror_axis(true, tb.flips[1], flip0);    //       y' = -u
+        const AxisMap px = mirror_axis(true, tb.flips[2], flip0);    // Prev: x' = -v
+        const AxisMap py = mirror_axis(false, tb.flips[2], flip0);   //       y' = u
+        auto image = [&](int s, int32_t i, int32_t j, int32_t n, int32_t &x, int32_t &y) -> bool {
+            const AxisMap mx = s == 1 ? nx : px, my = s == 1 ? ny : py;
+            x = mx.sg * j + mx.an * n + mx.ac;
+            y = my.sg * i + my.an * n + my.ac;
+            return (uint32_t)x < (uint32_t)n && (uint32_t)y < (uint32_t)n;
+        };
+        // adds x[t] to the holders of the taps of cell (ti, tj) on level l:
+        // the own tile, or the Next or Prev strip at the arena's start
+        auto spread = [&](int l, int32_t ti, int32_t tj, const float4 (&x)[4]) {
+            const int m = k0 - l;
+            const int32_t n = 1 << m, edge = flip0 ? n : -1;
+            float *lev = a.dtex + CH * (tb.ebs[0] + level_offset32(k0, l));
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const int32_t x = ti + (t & 1), y = tj + (t >> 1);
-                if ((uint32_t)x >= (uint32_t)n || (uint32_t)y >= (uint32_t)n) continue;
-                const uint32_t rel = ((uint32_t)y << m) + (uint32_t)x;
-                add_tap<CH>(arena, rbase[s][sl], rel, a.dtex + CH * (tb.ebs[s] + lo + rel),
-                            acc[s][sl][t]);
-            }
-        };
-        // each query's inputs are read one query ahead
-        int64_t qn = 0;
-        QIn nxt{};
-        if (TRI && i0 < i1) {
-            qn = q0 + order[i0];
-            nxt = load_qin<CH, TRI>(a, qn);
-        }
-        for (int i = i0; i < i1; ++i) {
-            const int64_t q = TRI ? qn : q0 + order[i];
-            const QIn cur = nxt;
-            if (TRI && i + 1 < i1) {
-                qn = q0 + order[i + 1];
-                nxt = load_qin<CH, TRI>(a, qn);
-            }
-            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base, true, qp, hb, &tb,
-                                   TRI ? &cur : nullptr);
-#pragma unroll
-            for (int s = 0; s < 3; ++s) {
-#pragma unroll
-                for (int sl = 0; sl < NL; ++sl) {
-                    if (sl >= qp.nlev[s] || !qp.p[s][sl].act) continue;
-                    const LevelPlan &p = qp.p[s][sl];
-                    const int l = qp.lv[s][sl], k = tb.ks[s];
-                    const int32_t n = 1 << (k - l);
-                    const float w[4] = {p.wx0 * p.wy0, p.wx1 * p.wy0, p.wx0 * p.wy1,
-                                        p.wx1 * p.wy1};
-                    // the run key: level and tap bases, while the bases lie
-                    // in -1 .. n - 1 of a texture of at most 2^9 texels a side
-                    const bool keyed = run_slot(s, sl) && k <= 9 && p.i0 >= -1 && p.i0 <= n - 1 &&
-                                       p.j0 >= -1 && p.j0 <= n - 1;
-                    if (!keyed) {
-                        const uint32_t off[4] = {p.o00, p.o01, p.o10, p.o11};
-                        const uint32_t lo = level_offset32(k, l);
-                        const int32_t bf = tile(s, sl, l);
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) {
-                            if (!((p.mask >> t) & 1)) continue;
-                            const float wt = w[t] * qp.rw;
-                            add_tap<CH>(arena, bf, off[t] - lo, a.dtex + CH * (tb.ebs[s] + off[t]),
-                                        make_float4(wt * qp.g.x, wt * qp.g.y, wt * qp.g.z,
-                                                    wt * qp.g.w));
-                        }
-                        continue;
-                    }
-                    const int32_t key = l << 20 | (p.j0 + 1) << 10 | (p.i0 + 1);
-                    if (key != rkey[s][sl]) {
-                        flush(s, sl);
-                        rkey[s][sl] = key;
-                        rbase[s][sl] = tile(s, sl, l);
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) acc[s][sl][t] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    }
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const float wt = w[t] * qp.rw;
-                        acc[s][sl][t].x += wt * qp.g.x;
-                        acc[s][sl][t].y += wt * qp.g.y;
-                        acc[s][sl][t].z += wt * qp.g.z;
-                        acc[s][sl][t].w += wt * qp.g.w;
+                const int32_t i = ti + (t & 1), j = tj + (t >> 1);
+                const int s = holder(i, j, n, edge);
+                if (s < 0) continue;
+                if (s == 0) {
+                    const uint32_t rel = ((uint32_t)j << m) + (uint32_t)i;
+                    add_tap<CH>(arena, own_base[l], rel, lev + CH * rel, x[t]);
+                } else {
+                    float *c = &arena[CH * ((s - 1) * kStripTexels + strip_before(k0, l) +
+                                            (s == 1 ? j : i))];
+                    atomicAdd(c + 0, x[t].x);
+                    if constexpr (CH == 4) {
+                        atomicAdd(c + 1, x[t].y);
+                        atomicAdd(c + 2, x[t].z);
+                        atomicAdd(c + 3, x[t].w);
                     }
                 }
             }
+        };
+        // a neighbour fetch of another size, planned per query: its part of
+        // W, or (add) its taps.  (Its fields are selected, not indexed, so
+        // that a call site in a rolled loop keeps them in registers.)
+        auto other = [&](int s, const QIn &x, const Lod &L, bool add, float rW) -> float {
+            FetchSpec fs[3];
+            fetch_specs(hb, tb.n1, tb.p1, x.u, x.v, fs);
+            const FetchSpec f = s == 1 ? fs[1] : fs[2];
+            const int k = s == 1 ? tb.ks[1] : tb.ks[2];
+            const bool flip = s == 1 ? tb.flips[1] : tb.flips[2];
+            const int32_t es = s == 1 ? tb.es[1] : tb.es[2];
+            const int64_t eb = s == 1 ? tb.ebs[1] : tb.ebs[2];
+            int lv[2];
+            float om[2];
+            const int nl = fetch_levels(L, k, lv, om);
+            float Wn = 0.0f;
+#pragma unroll
+            for (int sl = 0; sl < NL; ++sl) {
+                if (sl >= nl) break;
+                const LevelPlan p = plan_level(k, lv[sl], om[sl], f, flip);
+                if (!add) {
+                    Wn += (p.wx0 + p.wx1) * (p.wy0 + p.wy1);
+                    continue;
+                }
+                if (!p.act) continue;
+                const float w[4] = {p.wx0 * p.wy0, p.wx1 * p.wy0, p.wx0 * p.wy1, p.wx1 * p.wy1};
+                const uint32_t off[4] = {p.o00, p.o01, p.o10, p.o11};
+                const uint32_t lo = level_offset32(k, lv[sl]);
+                const int32_t bf =
+                    find_tile(T, es * 16 + lv[sl], (int64_t)CH << (2 * (k - lv[sl])));
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (!((p.mask >> t) & 1)) continue;
+                    const float wt = w[t] * rW;
+                    add_tap<CH>(arena, bf, off[t] - lo, a.dtex + CH * (eb + off[t]),
+                                make_float4(wt * x.g.x, wt * x.g.y, wt * x.g.z, wt * x.g.w));
+                }
+            }
+            return Wn;
+        };
+        int32_t rkey[NL];
+        float cov[NL][4];
+        float4 acc[NL][4];
+#pragma unroll
+        for (int sl = 0; sl < NL; ++sl) rkey[sl] = -1;
+        // trilinear runs read each query's inputs one query ahead
+        QIn nxt{};
+        if (TRI && i0 < i1) nxt = load_qin<CH, TRI>(a, q0 + order[i0]);
+        // one pass past the last query flushes the open runs
+#pragma nounroll
+        for (int i = i0; i <= i1; ++i) {
+            const bool last = i == i1;
+            QIn cur{};
+            if (!last) {
+                if constexpr (TRI) {
+                    cur = nxt;
+                    if (i + 1 < i1) nxt = load_qin<CH, TRI>(a, q0 + order[i + 1]);
+                } else {
+                    cur = load_qin<CH, TRI>(a, q0 + order[i]);
+                }
+            }
+            Lod L{0, 0, 0.0f, 1.0f};
+            if constexpr (TRI) L = lod_of(cur.f);
+            int lv[2] = {0, 0};
+            float om[2] = {0.0f, 0.0f};
+            const int nl = last ? 0 : fetch_levels(L, k0, lv, om);
+            float w[NL][4];
+            float W = 0.0f;
+#pragma unroll
+            for (int sl = 0; sl < NL; ++sl) {
+                // the own fetch's taps on this level, weights not masked:
+                // their bases lie in -1 .. n - 1 (binned on the finer level;
+                // the coarser level's follow from it)
+                const bool on = sl < nl;
+                const int m = k0 - (on ? lv[sl] : 0);
+                const AxisTaps X = axis_taps(cur.u, flip0, rho0, m);
+                const AxisTaps Y = axis_taps(cur.v, flip0, rho0, m);
+                const float wy0 = om[sl] * Y.w0, wy1 = om[sl] * Y.w1;
+                w[sl][0] = X.w0 * wy0;
+                w[sl][1] = X.w1 * wy0;
+                w[sl][2] = X.w0 * wy1;
+                w[sl][3] = X.w1 * wy1;
+                const int32_t key = on ? (lv[sl] << 20 | (Y.i0 + 1) << 10 | (X.i0 + 1)) : -1;
+                if (key != rkey[sl] && (on || last)) {
+                    if (rkey[sl] >= 0)
+                        spread(rkey[sl] >> 20, (rkey[sl] & 1023) - 1, ((rkey[sl] >> 10) & 1023) - 1,
+                               acc[sl]);
+                    rkey[sl] = key;
+                    const int32_t n = 1 << m, edge = flip0 ? n : -1;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        acc[sl][t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        cov[sl][t] = holder(X.i0 + (t & 1), Y.i0 + (t >> 1), n, edge) >= 0 ? 1.0f
+                                                                                          : 0.0f;
+                    }
+                }
+                if (on)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) W = fmaf(w[sl][t], cov[sl][t], W);
+            }
+            if (last) break;
+            // (one call site per pass: inlined twice more, the rarely taken
+            // plans would hold registers that cost occupancy)
+#pragma nounroll
+            for (int s = 1; s < 3; ++s)
+                if (!(s == 1 ? eq1 : eq2)) W += other(s, cur, L, false, 0.0f);
+            const float rW = 1.0f / W;
+#pragma unroll
+            for (int sl = 0; sl < NL; ++sl) {
+                if (sl >= nl) break;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float wt = w[sl][t] * rW;
+                    acc[sl][t].x += wt * cur.g.x;
+                    acc[sl][t].y += wt * cur.g.y;
+                    acc[sl][t].z += wt * cur.g.z;
+                    acc[sl][t].w += wt * cur.g.w;
+                }
+            }
+#pragma nounroll
+            for (int s = 1; s < 3; ++s)
+                if (!(s == 1 ? eq1 : eq2)) other(s, cur, L, true, rW);
         }
-#pragma unroll
-        for (int s = 0; s < 3; ++s)
-#pragma unroll
-            for (int sl = 0; sl < NL; ++sl)
-                if (run_slot(s, sl)) flush(s, sl);
         // the queries left to the per-query path
         uint32_t rest = 0;
 #pragma unroll
@@ -581,7 +670,29 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
             if (cell[r] == -1) rest |= 1u << r;
         for (; rest; rest &= rest - 1)
             scatter_query<CH, TRI>(a, q0 + (int64_t)__builtin_ctz(rest) * kBlock + threadIdx.x, T,
-                                   memo_key, memo_base, false, qp, 0, nullptr);
+                                   memo_key, memo_base);
+        // the strips to the pool: strip texel idx of level l is own tap
+        // (edge, idx) (Next) or (idx, edge) (Prev), edge = -1, or n under the
+        // own fetch's reflection
+        __syncthreads();
+        const int nstrip = strip_before(k0, TRI ? k0 + 1 : 1);
+        for (int e = threadIdx.x; e < 2 * nstrip; e += kBlock) {
+            const int s = e < nstrip ? 1 : 2;
+            if (!(s == 1 ? eq1 : eq2)) continue;
+            const int r = e - (s - 1) * nstrip;
+            int l = 0;
+            while (strip_before(k0, l + 1) <= r) ++l;
+            const int m = k0 - l;
+            const int32_t n = 1 << m, idx = r - strip_before(k0, l), edge = flip0 ? n : -1;
+            int32_t xs, ys;
+            if (!image(s, s == 1 ? edge : idx, s == 1 ? idx : edge, n, xs, ys)) continue;
+            float *dst = a.dtex + CH * (tb.ebs[s] + level_offset32(k0, l) +
+                                        (((uint32_t)ys << m) + (uint32_t)xs));
+            const float *src = &arena[CH * ((s - 1) * kStripTexels + r)];
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                if (src[c] != 0.0f) unsafeAtomicAdd(dst + c, src[c]);
+        }
     }
     __syncthreads();
     // flush the tiles
@@ -607,10 +718,13 @@ hipError_t launch_bwd(const SampleArgs &a, uint32_t flags, int max_log2res, hipS
     if (flags & HTEX_QUERIES_SORTED) {
         // sorted batches meet few textures per block: cache their gradients in LDS
         const uint32_t G = (uint32_t)ceil_div(a.Q, kBwdChunk);
-        if (!TRI && max_log2res <= kDenseMaxLog2)
-            hipLaunchKernelGGL((k_backward_lds<CH, TRI, kArenaSmall>), dim3(G), dim3(kBlock), 0, s,
-                               a);
-        else
+        bool small = false;
+        if constexpr (!TRI) small = max_log2res <= kDenseMaxLog2;
+        if constexpr (!TRI)
+            if (small)
+                hipLaunchKernelGGL((k_backward_lds<CH, TRI, kArenaSmall>), dim3(G), dim3(kBlock), 0,
+                                   s, a);
+        if (!small)
             hipLaunchKernelGGL((k_backward_lds<CH, TRI, kArenaFloats>), dim3(G), dim3(kBlock), 0,
                                s, a);
     } else {

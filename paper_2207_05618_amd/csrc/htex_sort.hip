@@ -377,13 +377,20 @@ __global__ void __launch_bounds__(kThreads) k_gather(const int32_t *perm, int64_
     if (f) fo[i] = f[p];
 }
 
+// Row is float or a 4-float vector type (the nontemporal builtins take
+// native vectors, not HIP's float4 struct).  The sorted rows and the
+// permutation stream through once, so they are loaded nontemporally; the
+// scattered stores stay ordinary: nontemporal ones miss the L2's combining
+// of the 16-byte pieces of a line and took three times as long.
+typedef float row4 __attribute__((ext_vector_type(4)));
+
 template <typename Row>
 __global__ void __launch_bounds__(kThreads) k_unpermute(const int32_t *perm, int64_t Q,
                                                         const Row *in, Row *out)
 {
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= Q) return;
-    out[perm[i]] = in[i];
+    out[__builtin_nontemporal_load(perm + i)] = __builtin_nontemporal_load(in + i);
 }
 
 constexpr int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -546,8 +553,8 @@ hipError_t launch_unpermute(const int32_t *perm, int64_t Q, int channels, const 
     if (Q == 0) return hipSuccess;
     const dim3 grid((uint32_t)cdiv(Q, kThreads));
     if (channels == 4)
-        hipLaunchKernelGGL((k_unpermute<float4>), grid, dim3(kThreads), 0, s, perm, Q,
-                           reinterpret_cast<const float4 *>(in), reinterpret_cast<float4 *>(out));
+        hipLaunchKernelGGL((k_unpermute<row4>), grid, dim3(kThreads), 0, s, perm, Q,
+                           reinterpret_cast<const row4 *>(in), reinterpret_cast<row4 *>(out));
     else
         hipLaunchKernelGGL((k_unpermute<float>), grid, dim3(kThreads), 0, s, perm, Q, in, out);
     return hipGetLastError();

@@ -555,10 +555,11 @@ def test_backward_sorted_flag_is_only_a_hint():
 @pytest.mark.parametrize("tri", [False, True])
 def test_backward_dense_blocks(channels, k, tri):
     """Blocks of 4096 queries on one halfedge take the binned scatter (runs of
-    queries with one tap cell summed before they are added; trilinear
-    fetches keep runs for their coarser level and for the neighbour
-    fetches' coarser level) when the texture has at most 32 x 32 texels
-    (k <= 5), the per-query scatter otherwise.  The batch mixes in what
+    queries with one tap cell summed before they are added, a trilinear
+    fetch's coarser level in runs of its own; the Next and Prev textures,
+    of the same size here, take their taps from the own fetch's runs) when
+    the texture has at most 32 x 32 texels (k <= 5), the per-query scatter
+    otherwise.  The batch mixes in what
     must leave the binned path: queries
     on other halfedges, invalid h, NaN u, coordinates outside the quad
     (tap cells outside the binned range), and one block whose first half
@@ -676,18 +677,20 @@ def test_largest_resolution_k15():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("sizes", [(7, 10), (5, 10), (7, 5)])
 @pytest.mark.parametrize("tri", [False, True])
-def test_backward_dense_blocks_mixed_neighbours(tri):
-    """Dense blocks (own textures of 32 x 32 texels) whose Next textures have
-    128 x 128 texels and whose Prev textures have 1024 x 1024: the
-    neighbour fetches' coarser level is summed in runs on the former and
-    added tap by tap on the latter (too large for the run key).  Queries are
-    drawn close to the spokes, so the neighbour fetches are active.  Against
-    the oracle within 1e-4 of sum |contributions|."""
+def test_backward_dense_blocks_mixed_neighbours(tri, sizes):
+    """Dense blocks (own textures of 32 x 32 texels) whose Next and Prev
+    textures have 2^a and 2^b texels a side, (a, b) = `sizes`: a neighbour
+    of the own size takes its taps from the own fetch's runs, one of another
+    size is planned and added query by query.  Queries are drawn close to
+    the spokes, so the neighbour fetches are active.  Against the oracle
+    within 1e-4 of sum |contributions|."""
     m = cube_mesh()
     hs = np.array([3, 17, 40], np.int32)
     lr = np.full(m.E, 7)
-    lr[m.edge[m.prev[hs]]] = 10
+    lr[m.edge[m.next[hs]]] = sizes[0]
+    lr[m.edge[m.prev[hs]]] = sizes[1]
     lr[m.edge[hs]] = 5
     s = Setup(m, lr, has_mips=tri, kind=1, seed=94, channels=4)
     rng = np.random.default_rng(95)
