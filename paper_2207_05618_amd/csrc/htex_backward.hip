@@ -99,21 +99,22 @@ __global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
 // non-zero texel channel.  Trilinear batches touch about 3 edges x 6
 // levels per block, which is why tiles are sized per level.
 //
-// Dense blocks.  LDS float atomics cost about as much as the rest of the
-// kernel, while LDS integer atomics are cheap.  When most of a block's
-// queries lie on one halfedge whose texture has at most 32 x 32 texels
-// (many samples per texel, as when fitting a texture), the block first bins
-// its queries by the level and tap cell (i0, j0) of their own fetch's finer
-// level, counting with integer atomics, and each thread then walks a run of
-// binned queries: consecutive queries of one cell share their four target
-// texels, so their contributions are summed in registers and added to the
-// tile once per run (the coarser level of a trilinear fetch keeps a run of
-// its own; trilinear runs read each query's inputs one query ahead).  Next
-// and Prev textures of the own size ride on these runs and collect their
-// taps in two small strips, one line of texels along the shared edge per
-// level, so such a block's arena holds only its own texture.  Queries on
-// other halfedges, or whose taps fall outside the cell range, take the
-// per-query path.
+// Dense segments.  LDS float atomics cost about as much as the rest of the
+// kernel, while LDS integer atomics are cheap.  The halfedges of a block's
+// first and last queries are its segments when their textures have at most
+// 32 x 32 texels and each holds an eighth of the block (many samples per
+// texel, as when fitting a texture; in a sorted batch a block straddles at
+// most two such halfedges).  A segment bins its queries by the level and
+// tap cell (i0, j0) of their own fetch's finer level, counting with integer
+// atomics, and each thread then walks a run of binned queries: consecutive
+// queries of one cell share their four target texels, so their
+// contributions are summed in registers and added to the tile once per run
+// (the coarser level of a trilinear fetch keeps a run of its own; trilinear
+// runs read each query's inputs one query ahead).  Next and Prev textures of
+// the own size ride on these runs and collect their taps in two small
+// strips, one line of texels along the shared edge per level, so a segment
+// needs only its own texture in the arena.  Queries on other halfedges, or
+// whose taps fall outside the cell range, take the per-query path.
 constexpr int kTiles = 32;
 constexpr int kArenaFloats = 16384;   // 64 KB
 constexpr int kBwdPerThread = 16;
@@ -130,14 +131,13 @@ __host__ __device__ constexpr int dense_cells_before(int k, int l)
 constexpr int kDenseCells = dense_cells_before(kDenseMaxLog2, kDenseMaxLog2 + 1);
 // a neighbour strip: one line of texels per level, n = 2^(k - l) on level l
 constexpr int kStripTexels = (2 << kDenseMaxLog2) - 1;
-// Bilinear batches whose textures have at most 32 x 32 texels need one
-// level per fetch, 16 KB a tile in RGBA: this arena holds a dense block's
-// strips and two tiles (the second halfedge's in a block that straddles
-// two, whose queries would otherwise fall back to global atomics), and
-// leaves room for three blocks per compute unit.  Trilinear batches keep
-// the 64 KB arena: with this one a straddling block's second texture and
-// mips overflow to global atomics, which cost more than the third block
-// gains (847 against 713 us on config 4).
+// Batches whose textures have at most 32 x 32 texels: this arena holds the
+// strips and two RGBA level-0 tiles of 16 KB (bilinear: both segments of a
+// block that straddles two halfedges), or one RGBA texture with its mips
+// (21.8 KB; trilinear: such a block adds its first segment's tiles to the
+// pool before the second segment), and leaves room for three blocks per
+// compute unit (trilinear on config 4: 616 against 706 us with two blocks
+// and the 64 KB arena).
 constexpr int kArenaSmall = 8192 + 2 * 4 * kStripTexels;
 // texels of levels 0 .. l - 1 (l <= k + 1): 2^(k+1) - 2^(k+1-l)
 __host__ __device__ constexpr int strip_before(int k, int l) { return (2 << k) - ((2 << k) >> l); }
@@ -363,21 +363,24 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
     __shared__ int32_t part[kBlock];
     __shared__ uint16_t order[kBwdChunk];
     __shared__ int32_t own_base[kDenseMaxLog2 + 1];
-    __shared__ int32_t dense_h, nbinned;
+    __shared__ int32_t seg_h[2], nbinned;
     for (int i = threadIdx.x; i < CAP; i += kBlock) arena[i] = 0.0f;
     if (threadIdx.x < kTiles) entry[threadIdx.x] = kFree;
     const int64_t q0 = (int64_t)blockIdx.x * kBwdChunk;
     if (threadIdx.x == 0) {
-        // bin by tap cell when the block's middle query shares its
-        // halfedge with the first or the last (in a sorted batch that
-        // halfedge then holds at least half of the block) and its texture
-        // is small
-        const int64_t ql = (q0 + kBwdChunk < a.Q ? q0 + kBwdChunk : a.Q) - 1;
-        const int32_t hf = a.qh[q0], hm = a.qh[q0 + (ql - q0) / 2], hl = a.qh[ql];
-        dense_h = ((hm == hf || hm == hl) && (uint32_t)hm < (uint32_t)a.H &&
-                   a.log2res[a.edge[hm]] <= kDenseMaxLog2) ? hm : -1;
-        // a dense block's Next and Prev strips (below) open the arena
-        used = dense_h >= 0 ? 2 * CH * kStripTexels : 0;
+        // dense segments: the halfedges of the block's first and last
+        // queries, each binned by tap cell when its texture is small and
+        // it holds an eighth of the block at least (in a sorted batch: the
+        // query an eighth in from that end has it too)
+        const int64_t n = (q0 + kBwdChunk < a.Q ? q0 + kBwdChunk : a.Q) - q0, ql = q0 + n - 1;
+        const int32_t hf = a.qh[q0], hl = a.qh[ql];
+        auto small = [&](int32_t h) {
+            return (uint32_t)h < (uint32_t)a.H && a.log2res[a.edge[h]] <= kDenseMaxLog2;
+        };
+        seg_h[0] = (small(hf) && a.qh[q0 + n / 8] == hf) ? hf : -1;
+        seg_h[1] = (hl != hf && small(hl) && a.qh[ql - n / 8] == hl) ? hl : -1;
+        // a dense segment's Next and Prev strips (below) open the arena
+        used = (seg_h[0] >= 0 || seg_h[1] >= 0) ? 2 * CH * kStripTexels : 0;
     }
     __syncthreads();
     const TileTable T{arena, entry, &used, CAP};
@@ -387,44 +390,105 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
 #pragma unroll
     for (int s = 0; s < 3; ++s)
         for (int sl = 0; sl < 2; ++sl) memo_key[s][sl] = -1;
-    // block-uniform: its navigation is read with scalar loads
-    const int32_t hb = __builtin_amdgcn_readfirstlane(dense_h);
-    if (hb < 0) {
-        for (int r = 0; r < kBwdPerThread; ++r) {
-            const int64_t q = q0 + (int64_t)r * kBlock + threadIdx.x;
-            if (q >= a.Q) break;
-            scatter_query<CH, TRI>(a, q, T, memo_key, memo_base);
+    // every tile to the pool, one float atomic per non-zero texel channel
+    auto flush_tiles = [&]() {
+        for (int t = 0; t < kTiles; ++t) {
+            const uint64_t en = entry[t];
+            if (en == kFree || (uint32_t)(en & 0xffffffffu) >= (uint32_t)CAP) continue;
+            const int32_t key = (int32_t)(en >> 32);
+            const int32_t e = key >> 4, l = key & 15;
+            const int k = a.log2res[e];
+            const int cnt = CH << (2 * (k - l));
+            float *dst = a.dtex + CH * (a.base[e] + level_offset32(k, l));
+            const float *src = &arena[(int32_t)(en & 0xffffffffu)];
+            for (int i = threadIdx.x; i < cnt; i += kBlock) {
+                const float val = src[i];
+                if (val != 0.0f) unsafeAtomicAdd(dst + i, val);
+            }
         }
-    } else {
-        // 1. the tap cell of each query's own fetch on its finer level
-        const int32_t e0 = a.edge[hb];
-        const int k0 = a.log2res[e0];
-        const bool flip0 = !(hb > a.twin[hb]);
+    };
+    // a second segment's texture fits beside the first's in this arena
+    constexpr bool kTwoChains = CAP >= 2 * CH * kStripTexels + 2 * CH * (TRI ? 1365 : 1024);
+    // the segments' halfedges, edges, log2 sizes and reflections
+    // (block-uniform: read with scalar loads)
+    int32_t sh[2], se[2], sk[2];
+    bool sflip[2];
+#pragma unroll
+    for (int sg = 0; sg < 2; ++sg) {
+        sh[sg] = __builtin_amdgcn_readfirstlane(seg_h[sg]);
+        se[sg] = sh[sg] >= 0 ? a.edge[sh[sg]] : 0;
+        sk[sg] = sh[sg] >= 0 ? a.log2res[se[sg]] : 0;
+        sflip[sg] = sh[sg] >= 0 && !(sh[sg] > a.twin[sh[sg]]);
+    }
+    // 1. the tap cell of each query's own fetch on its finer level, for
+    // the segment that holds the query: 16 bits per query, cell | segment
+    // << 15, or 0xffff (computed once: recomputed per segment, the query
+    // loads would be hoisted and held through both walks)
+    uint32_t cells[kBwdPerThread / 2];
+    uint32_t binned = 0;   // bit r: query r of this thread is in a segment
+#pragma unroll
+    for (int r = 0; r < kBwdPerThread; ++r) {
+        const int64_t q = q0 + (int64_t)r * kBlock + threadIdx.x;
+        uint32_t c16 = 0xffffu;
+        if (q < a.Q && (sh[0] >= 0 || sh[1] >= 0)) {
+            const int32_t h = a.qh[q];
+            const float u = a.qu[q], v = a.qv[q];
+            const int sg = (sh[0] >= 0 && h == sh[0]) ? 0 : (sh[1] >= 0 && h == sh[1]) ? 1 : -1;
+            if (sg >= 0 && isfinite(u) && isfinite(v)) {
+                const int k = sg ? sk[1] : sk[0];
+                Lod L{0, 0, 0.0f, 1.0f};
+                if constexpr (TRI) L = lod_of(a.qf[q]);
+                int lv[2];
+                float om[2];
+                fetch_levels(L, k, lv, om);
+                const FetchSpec f0 = {h, u, v, false, false};
+                const int32_t c =
+                    dense_cell(k, lv[0], plan_level(k, lv[0], om[0], f0, sg ? sflip[1] : sflip[0]));
+                if (c >= 0) {
+                    c16 = (uint32_t)c | (uint32_t)sg << 15;
+                    binned |= 1u << r;
+                }
+            }
+        }
+        if (r & 1)
+            cells[r >> 1] |= c16 << 16;
+        else
+            cells[r >> 1] = c16;
+    }
+    // the cell of query r in segment sg, or -1
+    auto cell_of = [&](int r, int sg) -> int32_t {
+        const uint32_t c16 = (cells[r >> 1] >> (16 * (r & 1))) & 0xffffu;
+        return (c16 != 0xffffu && (int)(c16 >> 15) == sg) ? (int32_t)(c16 & 0x7fffu) : -1;
+    };
+    // one dense segment (called for each: a loop over the two would keep
+    // values live across its iterations)
+    auto segment = [&](const int sg) {
+        const int32_t hb = sg ? sh[1] : sh[0];
+        if (!kTwoChains && sg == 1 && sh[0] >= 0) {
+            // the first segment's tiles to the pool, the arena cleared
+            flush_tiles();
+            __syncthreads();
+            if (threadIdx.x < kTiles) entry[threadIdx.x] = kFree;
+            if (threadIdx.x == 0) used = 2 * CH * kStripTexels;
+            for (int i = threadIdx.x; i < CAP; i += kBlock) arena[i] = 0.0f;
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+                for (int sl = 0; sl < 2; ++sl) memo_key[f][sl] = -1;
+            __syncthreads();
+        }
+        const int32_t e0 = sg ? se[1] : se[0];
+        const int k0 = sg ? sk[1] : sk[0];
+        const bool flip0 = sg ? sflip[1] : sflip[0];
         for (int i = threadIdx.x; i < kDenseCells; i += kBlock) cell_ofs[i] = 0;
+        for (int i = threadIdx.x; i < 2 * CH * kStripTexels; i += kBlock) arena[i] = 0.0f;
         if (threadIdx.x <= (TRI ? k0 : 0))
             own_base[threadIdx.x] = find_tile(T, e0 * 16 + (int)threadIdx.x,
                                               (int64_t)CH << (2 * (k0 - (int)threadIdx.x)));
         __syncthreads();
-        int32_t cell[kBwdPerThread];
 #pragma unroll
         for (int r = 0; r < kBwdPerThread; ++r) {
-            const int64_t q = q0 + (int64_t)r * kBlock + threadIdx.x;
-            cell[r] = -2;   // no query
-            if (q >= a.Q) continue;
-            cell[r] = -1;   // per-query path
-            const int32_t h = a.qh[q];
-            const float u = a.qu[q], v = a.qv[q];
-            if (h != hb || !isfinite(u) || !isfinite(v)) continue;
-            Lod L{0, 0, 0.0f, 1.0f};
-            if constexpr (TRI) L = lod_of(a.qf[q]);
-            int lv[2];
-            float om[2];
-            fetch_levels(L, k0, lv, om);
-            const FetchSpec f0 = {h, u, v, false, false};
-            const int32_t c = dense_cell(k0, lv[0], plan_level(k0, lv[0], om[0], f0, flip0));
-            if (c < 0) continue;
-            cell[r] = c;
-            atomicAdd(&cell_ofs[c], 1);
+            const int32_t c = cell_of(r, sg);
+            if (c >= 0) atomicAdd(&cell_ofs[c], 1);
         }
         __syncthreads();
         // 2. exclusive offsets: per-thread sums, one wavefront scans them
@@ -467,9 +531,10 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
         __syncthreads();
         // 3. the binned order
 #pragma unroll
-        for (int r = 0; r < kBwdPerThread; ++r)
-            if (cell[r] >= 0) order[atomicAdd(&cell_ofs[cell[r]], 1)] =
-                                  (uint16_t)(r * kBlock + threadIdx.x);
+        for (int r = 0; r < kBwdPerThread; ++r) {
+            const int32_t c = cell_of(r, sg);
+            if (c >= 0) order[atomicAdd(&cell_ofs[c], 1)] = (uint16_t)(r * kBlock + threadIdx.x);
+        }
         __syncthreads();
         // 4. runs of binned queries, kBwdPerThread consecutive entries per
         // thread.  Queries of one cell share the four taps of their own
@@ -663,14 +728,6 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
             for (int s = 1; s < 3; ++s)
                 if (!(s == 1 ? eq1 : eq2)) other(s, cur, L, true, rW);
         }
-        // the queries left to the per-query path
-        uint32_t rest = 0;
-#pragma unroll
-        for (int r = 0; r < kBwdPerThread; ++r)
-            if (cell[r] == -1) rest |= 1u << r;
-        for (; rest; rest &= rest - 1)
-            scatter_query<CH, TRI>(a, q0 + (int64_t)__builtin_ctz(rest) * kBlock + threadIdx.x, T,
-                                   memo_key, memo_base);
         // the strips to the pool: strip texel idx of level l is own tap
         // (edge, idx) (Next) or (idx, edge) (Prev), edge = -1, or n under the
         // own fetch's reflection
@@ -693,23 +750,19 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
             for (int c = 0; c < CH; ++c)
                 if (src[c] != 0.0f) unsafeAtomicAdd(dst + c, src[c]);
         }
+        // strips and cell counts free for the next segment
+        __syncthreads();
+    };
+    if (sh[0] >= 0) segment(0);
+    if (sh[1] >= 0) segment(1);
+    // the queries left to the per-query path
+    for (int r = 0; r < kBwdPerThread; ++r) {
+        const int64_t q = q0 + (int64_t)r * kBlock + threadIdx.x;
+        if (q >= a.Q) break;
+        if (!((binned >> r) & 1)) scatter_query<CH, TRI>(a, q, T, memo_key, memo_base);
     }
     __syncthreads();
-    // flush the tiles
-    for (int t = 0; t < kTiles; ++t) {
-        const uint64_t en = entry[t];
-        if (en == kFree || (uint32_t)(en & 0xffffffffu) >= (uint32_t)CAP) continue;
-        const int32_t key = (int32_t)(en >> 32);
-        const int32_t e = key >> 4, l = key & 15;
-        const int k = a.log2res[e];
-        const int cnt = CH << (2 * (k - l));
-        float *dst = a.dtex + CH * (a.base[e] + level_offset32(k, l));
-        const float *src = &arena[(int32_t)(en & 0xffffffffu)];
-        for (int i = threadIdx.x; i < cnt; i += kBlock) {
-            const float val = src[i];
-            if (val != 0.0f) unsafeAtomicAdd(dst + i, val);
-        }
-    }
+    flush_tiles();
 }
 
 template <int CH, bool TRI>
@@ -718,13 +771,10 @@ hipError_t launch_bwd(const SampleArgs &a, uint32_t flags, int max_log2res, hipS
     if (flags & HTEX_QUERIES_SORTED) {
         // sorted batches meet few textures per block: cache their gradients in LDS
         const uint32_t G = (uint32_t)ceil_div(a.Q, kBwdChunk);
-        bool small = false;
-        if constexpr (!TRI) small = max_log2res <= kDenseMaxLog2;
-        if constexpr (!TRI)
-            if (small)
-                hipLaunchKernelGGL((k_backward_lds<CH, TRI, kArenaSmall>), dim3(G), dim3(kBlock), 0,
-                                   s, a);
-        if (!small)
+        if (max_log2res <= kDenseMaxLog2)
+            hipLaunchKernelGGL((k_backward_lds<CH, TRI, kArenaSmall>), dim3(G), dim3(kBlock), 0, s,
+                               a);
+        else
             hipLaunchKernelGGL((k_backward_lds<CH, TRI, kArenaFloats>), dim3(G), dim3(kBlock), 0,
                                s, a);
     } else {

@@ -554,8 +554,9 @@ def test_backward_sorted_flag_is_only_a_hint():
 @pytest.mark.parametrize("k", [0, 3, 5, 6])
 @pytest.mark.parametrize("tri", [False, True])
 def test_backward_dense_blocks(channels, k, tri):
-    """Blocks of 4096 queries on one halfedge take the binned scatter (runs of
-    queries with one tap cell summed before they are added, a trilinear
+    """The halfedges at both ends of a block of 4096 queries (runs of about
+    3,500 here, so most blocks straddle two) take the binned scatter (runs
+    of queries with one tap cell summed before they are added, a trilinear
     fetch's coarser level in runs of its own; the Next and Prev textures,
     of the same size here, take their taps from the own fetch's runs) when
     the texture has at most 32 x 32 texels (k <= 5), the per-query scatter
