@@ -109,8 +109,8 @@ __global__ void __launch_bounds__(kBlock) k_backward(SampleArgs a)
 // atomics, and each thread then walks a run of binned queries: consecutive
 // queries of one cell share their four target texels, so their
 // contributions are summed in registers and added to the tile once per run
-// (the coarser level of a trilinear fetch keeps a run of its own; trilinear
-// runs read each query's inputs one query ahead).  Next and Prev textures of
+// (the coarser level of a trilinear fetch keeps a run of its own; the walk
+// reads each query's inputs two queries ahead).  Next and Prev textures of
 // the own size ride on these runs and collect their taps in two small
 // strips, one line of texels along the shared edge per level, so a segment
 // needs only its own texture in the arena.  Queries on other halfedges, or
@@ -650,21 +650,19 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
         float4 acc[NL][4];
 #pragma unroll
         for (int sl = 0; sl < NL; ++sl) rkey[sl] = -1;
-        // trilinear runs read each query's inputs one query ahead
-        QIn nxt{};
-        if (TRI && i0 < i1) nxt = load_qin<CH, TRI>(a, q0 + order[i0]);
+        // each query's inputs are read two queries ahead
+        QIn nxt{}, nxt2{};
+        if (i0 < i1) nxt = load_qin<CH, TRI>(a, q0 + order[i0]);
+        if (i0 + 1 < i1) nxt2 = load_qin<CH, TRI>(a, q0 + order[i0 + 1]);
         // one pass past the last query flushes the open runs
 #pragma nounroll
         for (int i = i0; i <= i1; ++i) {
             const bool last = i == i1;
             QIn cur{};
             if (!last) {
-                if constexpr (TRI) {
-                    cur = nxt;
-                    if (i + 1 < i1) nxt = load_qin<CH, TRI>(a, q0 + order[i + 1]);
-                } else {
-                    cur = load_qin<CH, TRI>(a, q0 + order[i]);
-                }
+                cur = nxt;
+                nxt = nxt2;
+                if (i + 2 < i1) nxt2 = load_qin<CH, TRI>(a, q0 + order[i + 2]);
             }
             Lod L{0, 0, 0.0f, 1.0f};
             if constexpr (TRI) L = lod_of(cur.f);
