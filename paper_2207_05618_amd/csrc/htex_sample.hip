@@ -75,14 +75,47 @@ __global__ void __launch_bounds__(kBlock) k_sample(SampleArgs a)
     }
 }
 
+// The prepared record of halfedge h, read once per run of lanes with the
+// same halfedge: in a sorted batch about ten neighbouring lanes share one,
+// and a 48-byte load on every lane costs the texture data unit, which
+// bounds the sampler, time in proportion to its active lanes.  The first
+// lane of each run loads it (an invalid h loads nothing and reads zeros),
+// the others take its words through ds_bpermute.  Every lane of the
+// wavefront that is still active must call this; a lane's run starts at or
+// below it, so lanes past the end of a batch (the high lanes) are never read.
+__device__ __forceinline__ PrepRec run_shared_record(const SampleArgs &a, int32_t h)
+{
+    const int lane = __lane_id();
+    // every lane shuffles (a lane left out of a ds_bpermute gives it no data)
+    const int32_t hp = __shfl_up(h, 1);
+    const bool first = (lane == 0) | (hp != h);
+    const uint64_t firsts = __ballot(first);
+    const int src = 63 - __builtin_clzll(firsts & ((2ull << lane) - 1ull));
+    constexpr int NW = 11;   // the record's words before its padding
+    static_assert(sizeof(PrepRec) == 4 * (NW + 1), "record words");
+    uint32_t w[NW + 1] = {};
+    if (first && (uint32_t)h < (uint32_t)a.H) {
+        const PrepRec r = static_cast<const PrepRec *>(a.prep)[h];
+        __builtin_memcpy(w, &r, sizeof(PrepRec));
+    }
+#pragma unroll
+    for (int i = 0; i < NW; ++i) w[i] = (uint32_t)__shfl((int)w[i], src);
+    w[NW] = 0u;
+    PrepRec rec;
+    __builtin_memcpy(&rec, w, sizeof(PrepRec));
+    return rec;
+}
+
 // Fast path: the same arithmetic as k_sample with the navigation read from
 // one prepared record per query (bit-identical results).  Shared by the
 // batch kernel and the serving kernel, so a query's result does not depend
 // on which launch, batch or tile computes it.
 // SCATTERED selects the per-tap predicated fetch for batches in random
-// order (same results).  A record that does not fit the pool (prepared for
-// another layout) makes its query invalid.
-template <int DT, int CH, bool TRI, bool SCATTERED, bool GATHER = false>
+// order (same results); SHARE reads the record once per run of lanes on one
+// halfedge (the batch kernel for sorted batches; same results).  A record
+// that does not fit the pool (prepared for another layout) makes its query
+// invalid.
+template <int DT, int CH, bool TRI, bool SCATTERED, bool GATHER = false, bool SHARE = false>
 __device__ __forceinline__ void sample_one_prepared(const SampleArgs &a, int64_t q)
 {
     int32_t h;
@@ -101,7 +134,10 @@ __device__ __forceinline__ void sample_one_prepared(const SampleArgs &a, int64_t
     }
     PrepRec rec;
     bool valid = ((uint32_t)h < (uint32_t)a.H) && isfinite(u) && isfinite(v);
-    if (valid) {
+    if constexpr (SHARE) {
+        rec = run_shared_record(a, h);
+        if (valid) valid = record_in_pool(rec, a.total_texels, a.has_mips != 0);
+    } else if (valid) {
         rec = static_cast<const PrepRec *>(a.prep)[h];
         valid = record_in_pool(rec, a.total_texels, a.has_mips != 0);
     }
@@ -318,7 +354,7 @@ __global__ void __launch_bounds__(kBlock) k_sample_prep(SampleArgs a)
         sample_wave_prepared<DT, CH, TRI, GATHER>(a, q, q < a.Q, tasks[threadIdx.x >> 6]);
     } else {
         if (q >= a.Q) return;
-        sample_one_prepared<DT, CH, TRI, KIND == kPrepScattered, GATHER>(a, q);
+        sample_one_prepared<DT, CH, TRI, KIND == kPrepScattered, GATHER, KIND == kPrepLane>(a, q);
     }
 }
 
