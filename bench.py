@@ -574,14 +574,9 @@ def raster_benchmark(mesh, dmesh, prep, pool, n_iter=10):
     TRI, S = htex.HTEX_TRILINEAR, htex.HTEX_QUERIES_SORTED
 
     def timed(fn):
-        for _ in range(3):
-            fn()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(n_iter):
-            fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t1) / n_iter
+        # HIP events around each launch (a launch takes about 0.1 ms here,
+        # so a host clock would count the launch overhead as well)
+        return kernel_seconds(lambda i: fn(), n=n_iter)[0]
 
     res = {"width": cam.width, "height": cam.height, "queries": int(fr.Q),
            "coverage": fr.Q / (cam.width * cam.height),
