@@ -678,6 +678,41 @@ def test_largest_resolution_k15():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("channels", [4, 1])
+@pytest.mark.parametrize("tri", [False, True])
+def test_backward_dense_twin_segments(tri, channels):
+    """Blocks whose two segments share one texture: the first half of a block
+    on a halfedge, the second half on its twin (the same edge, reflected), so
+    the second segment meets tiles the first one claimed (or, for trilinear
+    RGBA, tiles already added to the pool and cleared).  A third block puts
+    a sixteenth of its queries, under the eighth a segment needs, on another
+    halfedge: they take the per-query path.  Against the oracle within 1e-4
+    of sum |contributions|."""
+    m = cube_mesh()
+    s = Setup(m, np.full(m.E, 5), has_mips=tri, kind=1, seed=97, channels=channels)
+    rng = np.random.default_rng(98)
+    Q = 4096 * 3
+    q = uniform_queries(m.H, Q, 99, log2f=(-9.0, 1.0) if tri else None)
+    h0 = 3
+    q.h[:2048] = h0
+    q.h[2048:4096] = m.twin[h0]
+    q.h[4096:8192] = 17
+    q.h[8192:8192 + 256] = 40
+    q.h[8192 + 256:] = 41
+    g = rng.standard_normal((Q, channels)).astype(np.float32)
+    filt, ofilt = ((htex.HTEX_TRILINEAR, oracle.TRILINEAR) if tri
+                   else (htex.HTEX_BILINEAR, oracle.BILINEAR))
+    ref, dabs = oracle.backward(s.omesh, s.opool, q.h, q.u, q.v, g.astype(np.float64), q.f,
+                                filter=ofilt, with_abs=True)
+    d = htex.htex_sample_backward(s.dmesh, s.pool, t(q.h), t(q.u), t(q.v), t(g),
+                                  t(q.f) if tri else None, filter=filt,
+                                  flags=htex.HTEX_QUERIES_SORTED)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy().astype(np.float64).reshape(ref.shape)
+    err = np.abs(got - ref)
+    assert (err <= 1e-4 * dabs + 1e-12).all(), float((err / np.maximum(dabs, 1e-30)).max())
+
+
 @pytest.mark.parametrize("sizes", [(7, 10), (5, 10), (7, 5)])
 @pytest.mark.parametrize("tri", [False, True])
 def test_backward_dense_blocks_mixed_neighbours(tri, sizes):
