@@ -573,10 +573,21 @@ def raster_benchmark(mesh, dmesh, prep, pool, n_iter=10):
     out = torch.empty((fr.Q, 4), dtype=torch.float32, device="cuda")
     TRI, S = htex.HTEX_TRILINEAR, htex.HTEX_QUERIES_SORTED
 
-    def timed(fn):
-        # HIP events around each launch (a launch takes about 0.1 ms here,
-        # so a host clock would count the launch overhead as well)
-        return kernel_seconds(lambda i: fn(), n=n_iter)[0]
+    def timed(fn, n=20):
+        # two HIP events around n launches queued back to back: a launch
+        # takes about 0.1 ms here, and events around each launch (or a host
+        # clock) also count the time the host spends issuing it
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n / 1e3
 
     res = {"width": cam.width, "height": cam.height, "queries": int(fr.Q),
            "coverage": fr.Q / (cam.width * cam.height),
