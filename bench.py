@@ -513,11 +513,29 @@ def displacement_benchmark(mesh, dmesh, rgb_step, Q_rgb, T=4, n_iter=10, with_by
     e1.record(stream)
     torch.cuda.synchronize()
     k_disp = e0.elapsed_time(e1) / n_iter / 1e3
+    # the same vertices in edge order: both triangles of an intrinsic quad (a
+    # halfedge and its twin read one texture) back to back, each in patch
+    # order (a stable sort, outside the timed region)
+    eo = np.argsort(mesh.edge[q.h], kind="stable")
+    he, ue, ve = dev(q.h[eo]), dev(q.u[eo]), dev(q.v[eo])
+    for _ in range(3):
+        htex.htex_sample_prepared(prep, disp, he, ue, ve, None, filter=htex.HTEX_BILINEAR,
+                                  flags=htex.HTEX_QUERIES_SORTED, out=out)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(n_iter):
+        htex.htex_sample_prepared(prep, disp, he, ue, ve, None, filter=htex.HTEX_BILINEAR,
+                                  flags=htex.HTEX_QUERIES_SORTED, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    k_disp_edge = e0.elapsed_time(e1) / n_iter / 1e3
+    del he, ue, ve
     res = {"tessellation": T, "vertex_queries": int(q.Q), "fragment_queries": int(Q_rgb),
            "displacement_pool_bytes": disp.nbytes(), "corner_preprocess_ms": corner_ms,
            "vertex_stage_ms": t_disp * 1e3, "vertex_stage_kernel_us": k_disp * 1e6,
            "vertex_samples_per_s": q.Q / t_disp, "rgb_only_ms": t_rgb * 1e3,
-           "rgb_plus_disp_ms": t_both * 1e3, "rgb_plus_disp_over_rgb": t_both / t_rgb}
+           "rgb_plus_disp_ms": t_both * 1e3, "rgb_plus_disp_over_rgb": t_both / t_rgb,
+           "vertex_stage_edge_order_kernel_us": k_disp_edge * 1e6}
     if with_bytes:
         _, dbg = htex.htex_sample(dmesh, disp, h, u, v, None, filter=htex.HTEX_BILINEAR,
                                   debug=True)
@@ -531,7 +549,8 @@ def displacement_benchmark(mesh, dmesh, rgb_step, Q_rgb, T=4, n_iter=10, with_by
                            "frac": achieved / HBM_PEAK_GBS,
                            "alg_bytes_per_query": alg["bytes_per_query"],
                            "alg_texel_bytes_per_query": alg["texel_bytes_per_query"],
-                           "line128_bytes_per_query": alg["line128_bytes_per_query"]}
+                           "line128_bytes_per_query": alg["line128_bytes_per_query"],
+                           "edge_order_frac": alg["bytes"] / k_disp_edge / 1e9 / HBM_PEAK_GBS}
     del disp, prep, h, u, v, out
     torch.cuda.empty_cache()
     return res
