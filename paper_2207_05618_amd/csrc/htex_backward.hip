@@ -155,6 +155,7 @@ __device__ __forceinline__ int32_t dense_cell(int k, int l, const LevelPlan &p)
     return dense_cells_before(k, l) + (p.j0 + 1) * (n + 1) + (p.i0 + 1);
 }
 static_assert(kBwdChunk <= 65536, "binned query indices are 16-bit");
+static_assert(kDenseCells < 0x7fff, "a query's cell and segment share 16 bits");
 
 constexpr uint64_t kFree = ~0ull;
 constexpr uint32_t kPending = 0xfffffffeu, kNoRoom = 0xfffffffdu;
@@ -357,8 +358,8 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
     __shared__ float arena[CAP];
     __shared__ uint64_t entry[kTiles];
     __shared__ int32_t used;
-    // dense blocks: per-cell counts, then offsets; the binned query order;
-    // the tile of each level of the block's own texture
+    // dense segments: per-cell counts, then offsets; the binned query order;
+    // the tile of each level of the segment's own texture
     __shared__ int32_t cell_ofs[kDenseCells];
     __shared__ int32_t part[kBlock];
     __shared__ uint16_t order[kBwdChunk];
@@ -408,7 +409,10 @@ __global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
         }
     };
     // a second segment's texture fits beside the first's in this arena
-    constexpr bool kTwoChains = CAP >= 2 * CH * kStripTexels + 2 * CH * (TRI ? 1365 : 1024);
+    // (a texture of 2^kDenseMaxLog2 texels a side: 4^k texels, (4^(k+1) - 1)
+    // / 3 with its mips)
+    constexpr int kChain = TRI ? ((4 << (2 * kDenseMaxLog2)) - 1) / 3 : 1 << (2 * kDenseMaxLog2);
+    constexpr bool kTwoChains = CAP >= 2 * CH * kStripTexels + 2 * CH * kChain;
     // the segments' halfedges, edges, log2 sizes and reflections
     // (block-uniform: read with scalar loads)
     int32_t sh[2], se[2], sk[2];
