@@ -131,14 +131,20 @@ __host__ __device__ constexpr int dense_cells_before(int k, int l)
 constexpr int kDenseCells = dense_cells_before(kDenseMaxLog2, kDenseMaxLog2 + 1);
 // a neighbour strip: one line of texels per level, n = 2^(k - l) on level l
 constexpr int kStripTexels = (2 << kDenseMaxLog2) - 1;
-// Batches whose textures have at most 32 x 32 texels: this arena holds the
-// strips and two RGBA level-0 tiles of 16 KB (bilinear: both segments of a
-// block that straddles two halfedges), or one RGBA texture with its mips
-// (21.8 KB; trilinear: such a block adds its first segment's tiles to the
-// pool before the second segment), and leaves room for three blocks per
-// compute unit (trilinear on config 4: 616 against 706 us with two blocks
-// and the 64 KB arena).
-constexpr int kArenaSmall = 8192 + 2 * 4 * kStripTexels;
+// Batches whose textures have at most 32 x 32 texels: the arena holds one
+// segment's RGBA texture (16 KB, 21.8 KB with mips) and the strips, a block
+// that straddles two halfedges adds its first segment's tiles to the pool
+// before the second, and four blocks fit per compute unit (config 4: 286
+// and 586 us bilinear / trilinear, against 295 and 604 us with room for a
+// second texture and three blocks, and 706 us trilinear with two blocks and
+// the 64 KB arena).  A block with three or more large runs of halfedges
+// then adds its middle ones' taps to the pool directly.
+template <bool TRI>
+constexpr int arena_small()
+{
+    return 4 * (TRI ? ((4 << (2 * kDenseMaxLog2)) - 1) / 3 : 1 << (2 * kDenseMaxLog2)) +
+           2 * 4 * kStripTexels;
+}
 // texels of levels 0 .. l - 1 (l <= k + 1): 2^(k+1) - 2^(k+1-l)
 __host__ __device__ constexpr int strip_before(int k, int l) { return (2 << k) - ((2 << k) >> l); }
 static_assert(strip_before(0, 1) == 1 && strip_before(5, 6) == kStripTexels &&
@@ -352,8 +358,9 @@ __device__ __forceinline__ AxisMap mirror_axis(bool neg, bool flip, bool flip0)
     return m;
 }
 
+// (the small arena's launches hold four blocks per compute unit, 128 VGPRs)
 template <int CH, bool TRI, int CAP>
-__global__ void __launch_bounds__(kBlock) k_backward_lds(SampleArgs a)
+__global__ void __launch_bounds__(kBlock, (CAP < kArenaFloats ? 4 : 1)) k_backward_lds(SampleArgs a)
 {
     __shared__ float arena[CAP];
     __shared__ uint64_t entry[kTiles];
@@ -774,8 +781,8 @@ hipError_t launch_bwd(const SampleArgs &a, uint32_t flags, int max_log2res, hipS
         // sorted batches meet few textures per block: cache their gradients in LDS
         const uint32_t G = (uint32_t)ceil_div(a.Q, kBwdChunk);
         if (max_log2res <= kDenseMaxLog2)
-            hipLaunchKernelGGL((k_backward_lds<CH, TRI, kArenaSmall>), dim3(G), dim3(kBlock), 0, s,
-                               a);
+            hipLaunchKernelGGL((k_backward_lds<CH, TRI, arena_small<TRI>()>), dim3(G),
+                               dim3(kBlock), 0, s, a);
         else
             hipLaunchKernelGGL((k_backward_lds<CH, TRI, kArenaFloats>), dim3(G), dim3(kBlock), 0,
                                s, a);
